@@ -1,0 +1,216 @@
+/*
+ * rlb -- right-looking blocked (RLB) supernodal sparse Cholesky, A = L L^T,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Karsavuran, Ng, Peyton, Peyton, "Some new techniques to use in
+ * serial sparse Cholesky factorization algorithms" -- the RLB factorization of
+ * Section 2.2.2 (Algorithm 5), preceded by the symbolic steps of Section 2.1.2
+ * and Section 3.1 (ordering, supernodes, merging, reordering within
+ * supernodes) and followed by the forward/backward solves of step 4 of the
+ * solution process (Section 1).
+ *
+ * Conventions
+ *  - rlb_status is int32: 0 = success, negative = error (RLB_ERR_*),
+ *    positive k = the matrix is not positive definite: the pivot of column k
+ *    (1-based, factored order) is not positive. Columns 1..k-1 of L are valid.
+ *  - Input matrices are the LOWER triangle (diagonal included) in CSC form
+ *    with 0-based int64 indices, rows strictly ascending in every column, the
+ *    diagonal present in every column, no duplicates. Values are FP64.
+ *  - Host pointers are marked (host); device pointers (device). Device work is
+ *    enqueued on the caller's HIP stream (a hipStream_t passed as void*); no
+ *    call synchronizes except where stated.
+ *  - Handles are not thread-safe; one handle must not be used from two host
+ *    threads at once.
+ *  - Errors leave outputs unspecified; rlb_last_error() returns a message.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rlb_status;
+
+#define RLB_OK 0
+#define RLB_ERR_ARG (-1)            /* bad argument or option value */
+#define RLB_ERR_PATTERN (-2)        /* malformed CSC (unsorted, duplicate, upper, missing diagonal) */
+#define RLB_ERR_ALLOC (-3)          /* host or device allocation failed */
+#define RLB_ERR_WORKSPACE (-4)      /* caller workspace too small */
+#define RLB_ERR_HIP (-5)            /* a HIP runtime call failed */
+#define RLB_ERR_STATE (-6)          /* handle not in a state for this call (e.g. factor failed) */
+#define RLB_ERR_NOT_CONVERGED (-7)  /* refinement did not reach the tolerance */
+#define RLB_ERR_UNSUPPORTED (-8)    /* option combination not implemented */
+
+/* Orderings (step 1 of the solution process, Section 1). */
+#define RLB_ORDER_NATURAL 0
+#define RLB_ORDER_GRID_ND 1 /* geometric nested dissection on grid[] */
+#define RLB_ORDER_USER 2
+
+/* Arithmetic of the bulk SYRK/GEMM updates (POTRF and TRSM are FP64 always). */
+#define RLB_PREC_FP64 0
+#define RLB_PREC_FP32_UPDATES 1
+
+typedef struct rlb_options {
+  int32_t struct_size;      /* sizeof(rlb_options) */
+  int32_t ordering;         /* RLB_ORDER_* */
+  const int64_t* user_perm; /* (host) perm[new] = old, for RLB_ORDER_USER */
+  int64_t grid[4];          /* nx, ny, nz, dofs per node, for RLB_ORDER_GRID_ND;
+                               node (x,y,z) dof d is index d + dofs*(x + nx*(y + ny*z)) */
+  double merge_cap;         /* supernode merging stops before storage grows by more
+                               than this fraction (Section 3.1: 0.125); 0 = no merging */
+  int32_t reorder;          /* 1 = partition-refinement reordering inside supernodes
+                               (Section 1, Fig. 2; Section 3.1), 0 = none */
+  int32_t maximal_blocks;   /* 1 = merge contiguous GEMM blocks (Alg. 5, "maximal") */
+  int32_t precision;        /* RLB_PREC_* used by rlb_numeric_create */
+  int32_t reserved;
+} rlb_options;
+
+typedef struct rlb_info {
+  int64_t n, nnz_a;
+  int64_t n_supernodes, n_fundamental, n_levels;
+  int64_t nnz_exact;     /* entries of L in the exact structure of the final order */
+  int64_t nnz_stored;    /* entries of L in supernodal storage (lower trapezoids) */
+  double flops_exact;    /* sum over columns of (column count)^2, exact structure */
+  double flops_padded;   /* the same over the stored (supernodal) structure */
+  int64_t n_blocks;      /* blocks of all supernodes (Section 2.2.2) */
+  int64_t n_pairs;       /* (J, ancestor P) update pairs */
+  int64_t n_calls;       /* SYRK + GEMM block updates of Alg. 5 */
+  int64_t merge_added, merge_base; /* merging: added stored entries, fundamental entries */
+  int64_t factor_bytes;  /* device workspace needed by rlb_factor (FP64 factor storage) */
+  int64_t n_panel_tiles, n_update_tiles, n_atomic_tiles, n_launches;
+  double flops_tiles;    /* flops carried by the update tiles (incl. padding) */
+} rlb_info;
+
+typedef struct rlb_symbolic_s* rlb_symbolic;
+typedef struct rlb_numeric_s* rlb_numeric;
+
+/* Fill *opt with the defaults of the paper: grid ND ordering (grid must still
+ * be set), merge cap 0.125, reordering on, maximal blocks on, FP64. */
+rlb_status rlb_default_options(rlb_options* opt);
+
+/* Symbolic phase (host only, no device use): ordering, elimination tree,
+ * postorder, fundamental supernodes (Section 2.1.2), merging (Section 3.1),
+ * reordering within supernodes (Section 1, Section 3.1), glbind / relind /
+ * blocks / relindB (Section 2.1.2, Section 2.2.2), and the device work plan.
+ *   n, colptr[n+1], rowidx[colptr[n]] : (host) lower-triangle CSC pattern
+ *   opt   : (host) options, may be NULL for defaults with natural ordering
+ *   out   : receives a new handle owned by the caller (rlb_symbolic_free)
+ * Errors: RLB_ERR_PATTERN, RLB_ERR_ARG, RLB_ERR_ALLOC. */
+rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
+                       const rlb_options* opt, rlb_symbolic* out);
+
+rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* out);
+
+/* Copy one integer array of the analysis into caller memory (host).
+ * which: "perm", "perm_nd", "perm_post", "etree_post", "etree", "fund_ptr",
+ * "sn_ptr", "sn_parent", "gl_ptr", "gl", "rel_ptr", "rel", "blk_ptr", "blk",
+ * "rbp_ptr", "rbp_anc", "rbv_ptr", "rbv", "colcount", "level", "off", "amap".
+ * If out is NULL only *len is set. All arrays are returned as int64. */
+rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out, int64_t* len);
+
+void rlb_symbolic_free(rlb_symbolic sym);
+
+/* Upload the work plan of `sym` to the current HIP device. The numeric handle
+ * borrows `sym`, which must outlive it. precision: RLB_PREC_*.
+ * Errors: RLB_ERR_HIP, RLB_ERR_ALLOC, RLB_ERR_ARG. */
+rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* out);
+
+/* Numeric factorization (Alg. 5): A-load, then per level of the supernodal
+ * elimination tree the cdiv (POTRF + TRSM) of every supernode and its
+ * SYRK/GEMM updates written directly into ancestor storage.
+ *   values    : (device) FP64 values of the analysed CSC, in its entry order
+ *   workspace : (device) caller-owned buffer of >= info.factor_bytes bytes,
+ *               8-byte aligned; receives the factor and must stay alive and
+ *               unmodified while `num` is used for solves
+ *   stream    : hipStream_t (void*), may be NULL for the default stream
+ * Asynchronous; call rlb_factor_status for the outcome.
+ * Errors: RLB_ERR_WORKSPACE, RLB_ERR_ARG, RLB_ERR_HIP. */
+rlb_status rlb_factor(rlb_numeric num, const double* values, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* Synchronize the factor's stream and return 0 or k > 0 (first non-positive
+ * pivot, 1-based column of the factored order); *info receives the same. */
+rlb_status rlb_factor_status(rlb_numeric num, int64_t* info);
+
+/* Solve A X = B in place with the computed factor (forward solve with L,
+ * backward solve with L^T, Section 1 step 4).
+ *   B : (device) n x nrhs column-major FP64 in the ORIGINAL order, ld = ldb
+ * Uses a library scratch buffer of n*nrhs doubles. Errors: RLB_ERR_ARG,
+ * RLB_ERR_STATE (no successful factor), RLB_ERR_HIP. */
+rlb_status rlb_solve(rlb_numeric num, int64_t nrhs, double* B, int64_t ldb, void* stream);
+
+typedef struct rlb_refine_report {
+  int32_t iterations;       /* refinement steps taken after the first solve */
+  int32_t converged;        /* 1 if every column reached tol */
+  double backward_error[16];/* final ||b - A x||_inf / (||A||_inf ||x||_inf) per column */
+  double history[64];       /* max backward error after the first solve and each step */
+} rlb_refine_report;
+
+/* Iterative refinement in FP64 on the device (the mixed forms): X = solve(B),
+ * then repeat r = B - A X (FP64 residual), d = solve(r), X += d until every
+ * column's backward error is <= tol or max_iter steps were taken.
+ *   values : (device) the same FP64 values that were factored (for A X)
+ *   B, X   : (device) n x nrhs column-major, ORIGINAL order, ld = ld; nrhs <= 16
+ * Returns RLB_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not met. */
+rlb_status rlb_refine(rlb_numeric num, const double* values, int64_t nrhs, const double* B,
+                      double* X, int64_t ld, double tol, int32_t max_iter, void* stream,
+                      rlb_refine_report* rep);
+
+/* Backward error ||B - A X||_inf / (||A||_inf ||X||_inf) per column (device
+ * FP64 residual; synchronizes). out: (host) nrhs doubles. */
+rlb_status rlb_backward_error(rlb_numeric num, const double* values, int64_t nrhs,
+                              const double* B, const double* X, int64_t ld, void* stream,
+                              double* out);
+
+/* Copy the factor out of factor storage into a host CSC with the stored
+ * supernodal structure (final order): colptr[n+1], rowidx, vals sized by
+ * info.nnz_stored. Synchronizes. For tests and inspection. */
+rlb_status rlb_factor_export(rlb_numeric num, int64_t* colptr, int64_t* rowidx, double* vals);
+
+void rlb_numeric_free(rlb_numeric num);
+
+/* Batched form: factor many independent matrices with one merged level
+ * schedule (level h of every matrix in the same launches).
+ *   count           : number of matrices
+ *   syms[count]     : (host) analysed patterns
+ *   values[count]   : (host array of device pointers) FP64 values of each
+ *   workspace       : (device) >= rlb_batch_bytes() bytes, caller-owned
+ * rlb_batch_create builds the merged plan once; rlb_batch_factor runs it and
+ * may be called again with new values. Per-matrix status via rlb_batch_status.
+ */
+typedef struct rlb_batch_s* rlb_batch;
+rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t precision,
+                            rlb_batch* out, int64_t* workspace_bytes);
+rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* workspace,
+                            size_t workspace_bytes, void* stream);
+/* info[count] (host): 0 or the failing column of each matrix. Synchronizes. */
+rlb_status rlb_batch_status(rlb_batch b, int64_t* info);
+/* Solve matrix i of the batch in place (B in its original order). */
+rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int64_t ldb,
+                           void* stream);
+void rlb_batch_free(rlb_batch b);
+
+/* Record the factor's launch sequence in a HIP graph on first use and replay
+ * it on later rlb_factor / rlb_batch_factor calls with the same buffers. */
+rlb_status rlb_set_graph_mode(rlb_numeric num, int32_t on);
+rlb_status rlb_batch_set_graph_mode(rlb_batch b, int32_t on);
+
+/* Device time of the dominant kernel family, measured with HIP events on the
+ * factor's stream during the last rlb_factor: total ms of the update launches
+ * and of the panel launches, and the number of each. Enabled by
+ * rlb_set_profiling(num, 1) (adds one event pair per launch). */
+rlb_status rlb_set_profiling(rlb_numeric num, int32_t on);
+rlb_status rlb_last_profile(rlb_numeric num, double* update_ms, double* panel_ms,
+                            int64_t* n_update, int64_t* n_panel);
+
+const char* rlb_status_string(rlb_status s);
+const char* rlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLB_H */

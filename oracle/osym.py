@@ -415,8 +415,8 @@ def analyze(A, ordering="grid", merge_cap=0.125, reorder=True, user_perm=None):
 
     # structures again under the postorder; fundamental supernodes; merging
     cp, ri, _ = permute_lower(n, A.colptr, A.rowidx, None, perm1)
-    structs, parent = column_structures(n, cp, ri)
-    fund_ptr = fundamental_supernodes(structs, parent)
+    structs, parent_post = column_structures(n, cp, ri)
+    fund_ptr = fundamental_supernodes(structs, parent_post)
     if merge_cap > 0:
         sn_ptr, glbm, added, base = merge_supernodes(fund_ptr, structs, merge_cap)
     else:
@@ -445,6 +445,7 @@ def analyze(A, ordering="grid", merge_cap=0.125, reorder=True, user_perm=None):
         "perm": perm,
         "perm_nd": perm0,
         "perm_post": perm1,
+        "parent_post": parent_post,
         "fund_ptr": fund_ptr,
         "sn_ptr": sn_ptr,
         "sn_parent": par,

@@ -1,0 +1,817 @@
+// C-ABI of the rlb library: symbolic handles (host), numeric handles (device
+// plan + factor in caller storage), batched factorization, solves and FP64
+// iterative refinement. Every step of the numeric path runs in the kernels of
+// kernels.hip; this file only plans, uploads and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rlb.h"
+#include "device.h"
+#include "symbolic.h"
+
+using namespace rlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+rlb_status fail(rlb_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_OK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RLB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+template <typename T>
+rlb_status upload(T** dptr, const std::vector<T>& v) {
+  *dptr = nullptr;
+  if (v.empty()) return RLB_OK;
+  HIP_OK(hipMalloc((void**)dptr, v.size() * sizeof(T)));
+  HIP_OK(hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return RLB_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// device copy of everything the factor and the solves need for one matrix
+struct DevPlan {
+  PanelTile* panels = nullptr;
+  UpdTile* updates = nullptr;
+  int64_t* amap = nullptr;
+  SnMeta* meta = nullptr;
+  int32_t* gl = nullptr;
+  int32_t* lvl_sn = nullptr;
+  int64_t* perm = nullptr;
+  int64_t* a_rowptr = nullptr;
+  int32_t* a_col = nullptr;
+  int64_t* a_src = nullptr;
+  void release() {
+    dfree(panels);
+    dfree(updates);
+    dfree(amap);
+    dfree(meta);
+    dfree(gl);
+    dfree(lvl_sn);
+    dfree(perm);
+    dfree(a_rowptr);
+    dfree(a_col);
+    dfree(a_src);
+  }
+};
+
+std::vector<SnMeta> make_meta(const Symbolic& s, int64_t base) {
+  int64_t S = (int64_t)s.sn_ptr.size() - 1;
+  std::vector<SnMeta> meta(S);
+  for (int64_t J = 0; J < S; ++J) {
+    meta[J].off = base + s.plan.off[J];
+    meta[J].f = (int32_t)s.sn_ptr[J];
+    meta[J].w = (int32_t)(s.sn_ptr[J + 1] - s.sn_ptr[J]);
+    meta[J].m = (int32_t)(s.gl_ptr[J + 1] - s.gl_ptr[J]);
+    meta[J].gl = (int32_t)s.gl_ptr[J];
+  }
+  return meta;
+}
+
+// solve/refine data (no factor tiles)
+rlb_status upload_solve(const Symbolic& s, int64_t base, DevPlan& d) {
+  rlb_status st;
+  if ((st = upload(&d.meta, make_meta(s, base)))) return st;
+  if ((st = upload(&d.gl, s.gl))) return st;
+  if ((st = upload(&d.lvl_sn, s.plan.lvl_sn))) return st;
+  if ((st = upload(&d.perm, s.perm))) return st;
+  if ((st = upload(&d.a_rowptr, s.plan.a_rowptr))) return st;
+  if ((st = upload(&d.a_col, s.plan.a_col))) return st;
+  if ((st = upload(&d.a_src, s.plan.a_src))) return st;
+  return RLB_OK;
+}
+
+// scratch for the solves and the refinement of one matrix
+struct SolveScratch {
+  double* y = nullptr;  // n x SOLVE_MAXRHS
+  double* r = nullptr;
+  double* d = nullptr;
+  unsigned long long* norms = nullptr;  // 3*SOLVE_MAXRHS + 1
+  int64_t n = 0;
+  rlb_status ensure(int64_t n_) {
+    if (y && n >= n_) return RLB_OK;  // buffers sized for the largest n seen
+    release();
+    n = n_;
+    size_t bytes = (size_t)std::max<int64_t>(n, 1) * SOLVE_MAXRHS * sizeof(double);
+    HIP_OK(hipMalloc((void**)&y, bytes));
+    HIP_OK(hipMalloc((void**)&r, bytes));
+    HIP_OK(hipMalloc((void**)&d, bytes));
+    HIP_OK(hipMalloc((void**)&norms, (3 * SOLVE_MAXRHS + 1) * sizeof(unsigned long long)));
+    return RLB_OK;
+  }
+  void release() {
+    dfree(y);
+    dfree(r);
+    dfree(d);
+    dfree(norms);
+  }
+};
+
+// forward then backward supernodal solve of nrhs (<= SOLVE_MAXRHS) columns
+// already gathered into y (factored order, ld = n)
+void enqueue_solve_levels(const Symbolic& s, const DevPlan& d, const double* L, double* y,
+                          int nrhs, hipStream_t st) {
+  const Plan& p = s.plan;
+  for (int32_t h = 0; h < p.nlevels; ++h)
+    launch_fwd(d.lvl_sn + p.lvl_ptr[h], p.lvl_ptr[h + 1] - p.lvl_ptr[h], d.meta, d.gl, L, y,
+               nrhs, s.n, st);
+  for (int32_t h = p.nlevels - 1; h >= 0; --h)
+    launch_bwd(d.lvl_sn + p.lvl_ptr[h], p.lvl_ptr[h + 1] - p.lvl_ptr[h], d.meta, d.gl, L, y,
+               nrhs, s.n, st);
+}
+
+rlb_status solve_into(const Symbolic& s, const DevPlan& d, SolveScratch& sc, const double* L,
+                      int64_t nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
+                      hipStream_t st) {
+  rlb_status e = sc.ensure(s.n);
+  if (e) return e;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SOLVE_MAXRHS) {
+    int nr = (int)std::min<int64_t>(SOLVE_MAXRHS, nrhs - c0);
+    launch_perm_in(d.perm, B + c0 * ldb, ldb, sc.y, s.n, s.n, nr, st);
+    enqueue_solve_levels(s, d, L, sc.y, nr, st);
+    launch_perm_out(d.perm, sc.y, s.n, X + c0 * ldx, ldx, s.n, nr, st);
+  }
+  HIP_OK(hipGetLastError());
+  return RLB_OK;
+}
+
+// backward errors of nrhs (<= SOLVE_MAXRHS) columns; synchronizes
+rlb_status backward_errors(const Symbolic& s, const DevPlan& d, SolveScratch& sc,
+                           const double* values, int nrhs, const double* B, const double* X,
+                           int64_t ld, hipStream_t st, double* out, double* anorm_cache) {
+  rlb_status e = sc.ensure(s.n);
+  if (e) return e;
+  launch_zero_u64(sc.norms, 3 * SOLVE_MAXRHS + 1, st);
+  launch_residual(s.n, d.a_rowptr, d.a_col, d.a_src, values, X, ld, B, ld, sc.r, s.n, nrhs, st);
+  launch_absmax(sc.r, s.n, s.n, nrhs, sc.norms, st);
+  launch_absmax(X, s.n, ld, nrhs, sc.norms + SOLVE_MAXRHS, st);
+  bool need_a = !anorm_cache || *anorm_cache < 0;
+  if (need_a) launch_anorm(s.n, d.a_rowptr, d.a_src, values, sc.norms + 3 * SOLVE_MAXRHS, st);
+  unsigned long long h[3 * SOLVE_MAXRHS + 1];
+  HIP_OK(hipMemcpyAsync(h, sc.norms, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  double an;
+  if (need_a) {
+    std::memcpy(&an, &h[3 * SOLVE_MAXRHS], sizeof(double));
+    if (anorm_cache) *anorm_cache = an;
+  } else {
+    an = *anorm_cache;
+  }
+  for (int k = 0; k < nrhs; ++k) {
+    double rn, xn;
+    std::memcpy(&rn, &h[k], sizeof(double));
+    std::memcpy(&xn, &h[SOLVE_MAXRHS + k], sizeof(double));
+    out[k] = (an > 0 && xn > 0) ? rn / (an * xn) : (rn == 0 ? 0.0 : INFINITY);
+  }
+  return RLB_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+struct rlb_symbolic_s {
+  Symbolic s;
+};
+
+struct rlb_numeric_s {
+  rlb_symbolic_s* sym = nullptr;
+  int precision = 0;
+  int device = 0;
+  DevPlan d;
+  int* status = nullptr;
+  double* L = nullptr;
+  bool factored = false;
+  hipStream_t stream = nullptr;
+  SolveScratch sc;
+  double anorm = -1.0;
+  const double* anorm_vals = nullptr;
+  // graph replay
+  bool graph_mode = false;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_vals = nullptr;
+  void* g_L = nullptr;
+  hipStream_t g_stream = nullptr;
+  // per-launch timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  double prof_update_ms = 0, prof_panel_ms = 0;
+  int64_t prof_nupd = 0, prof_npan = 0;
+  ~rlb_numeric_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    d.release();
+    sc.release();
+    dfree(status);
+  }
+};
+
+struct rlb_batch_s {
+  std::vector<rlb_symbolic_s*> syms;
+  int precision = 0;
+  std::vector<int64_t> base;     // factor storage offset of every matrix
+  std::vector<int64_t> nnz_ptr;  // concatenated entry space
+  int64_t l_elems = 0;
+  std::vector<Launch> launches;
+  std::vector<PanelTile> panels;
+  std::vector<UpdTile> updates;
+  PanelTile* d_panels = nullptr;
+  UpdTile* d_updates = nullptr;
+  int64_t* d_amap = nullptr;
+  int64_t* d_nnz_ptr = nullptr;
+  const double** d_vals = nullptr;
+  int* status = nullptr;
+  std::vector<DevPlan> per;  // solve data of every matrix
+  SolveScratch sc;
+  double* L = nullptr;
+  bool factored = false;
+  hipStream_t stream = nullptr;
+  bool graph_mode = false;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const double*> g_vals;
+  void* g_L = nullptr;
+  hipStream_t g_stream = nullptr;
+  ~rlb_batch_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    dfree(d_panels);
+    dfree(d_updates);
+    dfree(d_amap);
+    dfree(d_nnz_ptr);
+    if (d_vals) (void)hipFree((void*)d_vals);
+    dfree(status);
+    for (auto& p : per) p.release();
+    sc.release();
+  }
+};
+
+extern "C" {
+
+const char* rlb_last_error(void) { return g_err.c_str(); }
+
+const char* rlb_status_string(rlb_status s) {
+  switch (s) {
+    case RLB_OK: return "ok";
+    case RLB_ERR_ARG: return "bad argument";
+    case RLB_ERR_PATTERN: return "malformed lower-triangle CSC pattern";
+    case RLB_ERR_ALLOC: return "allocation failed";
+    case RLB_ERR_WORKSPACE: return "workspace too small";
+    case RLB_ERR_HIP: return "HIP runtime error";
+    case RLB_ERR_STATE: return "handle not ready (no successful factorization)";
+    case RLB_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case RLB_ERR_UNSUPPORTED: return "unsupported option";
+    default: return s > 0 ? "matrix not positive definite" : "unknown status";
+  }
+}
+
+rlb_status rlb_default_options(rlb_options* o) {
+  if (!o) return fail(RLB_ERR_ARG, "null options");
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(rlb_options);
+  o->ordering = RLB_ORDER_GRID_ND;
+  o->grid[3] = 1;
+  o->merge_cap = 0.125;
+  o->reorder = 1;
+  o->maximal_blocks = 1;
+  o->precision = RLB_PREC_FP64;
+  return RLB_OK;
+}
+
+rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
+                       const rlb_options* opt, rlb_symbolic* out) {
+  if (!out) return fail(RLB_ERR_ARG, "null output handle");
+  *out = nullptr;
+  AnalyzeOptions ao;
+  if (opt) {
+    if (opt->struct_size != (int32_t)sizeof(rlb_options))
+      return fail(RLB_ERR_ARG, "rlb_options.struct_size mismatch");
+    if (opt->ordering < 0 || opt->ordering > 2) return fail(RLB_ERR_ARG, "bad ordering");
+    if (!(opt->merge_cap >= 0) || opt->merge_cap > 10) return fail(RLB_ERR_ARG, "bad merge_cap");
+    if (opt->precision < 0 || opt->precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+    ao.ordering = opt->ordering;
+    ao.user_perm = opt->user_perm;
+    for (int k = 0; k < 4; ++k) ao.grid[k] = opt->grid[k];
+    ao.merge_cap = opt->merge_cap;
+    ao.reorder = opt->reorder;
+    ao.maximal_blocks = opt->maximal_blocks;
+    ao.precision = opt->precision;
+  } else {
+    ao.ordering = 0;
+  }
+  std::unique_ptr<rlb_symbolic_s> h;
+  try {
+    h.reset(new rlb_symbolic_s());
+    std::string err;
+    int st = analyze(n, colptr, rowidx, ao, h->s, err);
+    if (st) return fail(st, err);
+    st = build_plan(h->s, err);
+    if (st) return fail(RLB_ERR_ARG, err);
+  } catch (const std::bad_alloc&) {
+    return fail(RLB_ERR_ALLOC, "host allocation failed in analyze");
+  }
+  *out = h.release();
+  return RLB_OK;
+}
+
+rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* o) {
+  if (!sym || !o) return fail(RLB_ERR_ARG, "null argument");
+  const Symbolic& s = sym->s;
+  std::memset(o, 0, sizeof(*o));
+  o->n = s.n;
+  o->nnz_a = s.nnz_a;
+  o->n_supernodes = (int64_t)s.sn_ptr.size() - 1;
+  o->n_fundamental = (int64_t)s.fund_ptr.size() - 1;
+  o->n_levels = s.plan.nlevels;
+  o->nnz_exact = s.nnz_exact;
+  o->nnz_stored = s.nnz_stored;
+  o->flops_exact = s.flops_exact;
+  o->flops_padded = s.flops_padded;
+  o->n_blocks = s.n_blocks;
+  o->n_pairs = s.n_pairs;
+  o->n_calls = s.n_calls;
+  o->merge_added = s.merge_added;
+  o->merge_base = s.merge_base;
+  o->factor_bytes = s.plan.l_elems * (int64_t)sizeof(double);
+  o->n_panel_tiles = (int64_t)s.plan.panels.size();
+  o->n_update_tiles = (int64_t)s.plan.updates.size();
+  o->n_atomic_tiles = s.plan.n_atomic_tiles;
+  o->n_launches = (int64_t)s.plan.launches.size();
+  o->flops_tiles = s.plan.flops_tiles;
+  return RLB_OK;
+}
+
+rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out, int64_t* len) {
+  if (!sym || !which || !len) return fail(RLB_ERR_ARG, "null argument");
+  const Symbolic& s = sym->s;
+  std::vector<int64_t> tmp;
+  auto put64 = [&](const std::vector<int64_t>& v) { tmp = v; };
+  auto put32 = [&](const std::vector<int32_t>& v) { tmp.assign(v.begin(), v.end()); };
+  std::string w(which);
+  if (w == "perm") put64(s.perm);
+  else if (w == "perm_nd") put64(s.perm_nd);
+  else if (w == "perm_post") put64(s.perm_post);
+  else if (w == "etree_post") put64(s.etree_post);
+  else if (w == "etree") put64(s.etree);
+  else if (w == "fund_ptr") put64(s.fund_ptr);
+  else if (w == "sn_ptr") put64(s.sn_ptr);
+  else if (w == "sn_parent") put64(s.sn_parent);
+  else if (w == "gl_ptr") put64(s.gl_ptr);
+  else if (w == "gl") put32(s.gl);
+  else if (w == "rel_ptr") put64(s.rel_ptr);
+  else if (w == "rel") put32(s.rel);
+  else if (w == "blk_ptr") put64(s.blk_ptr);
+  else if (w == "blk") put32(s.blk);
+  else if (w == "rbp_ptr") put64(s.rbp_ptr);
+  else if (w == "rbp_anc") put32(s.rbp_anc);
+  else if (w == "rbv_ptr") put64(s.rbv_ptr);
+  else if (w == "rbv") put32(s.rbv);
+  else if (w == "colcount") put64(s.colcount);
+  else if (w == "level") put32(s.plan.level);
+  else if (w == "off") put64(s.plan.off);
+  else if (w == "amap") put64(s.plan.amap);
+  else return fail(RLB_ERR_ARG, "unknown array " + w);
+  *len = (int64_t)tmp.size();
+  if (out && !tmp.empty()) std::memcpy(out, tmp.data(), tmp.size() * sizeof(int64_t));
+  return RLB_OK;
+}
+
+void rlb_symbolic_free(rlb_symbolic sym) { delete sym; }
+
+rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* out) {
+  if (!sym || !out) return fail(RLB_ERR_ARG, "null argument");
+  if (precision < 0 || precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+  *out = nullptr;
+  std::unique_ptr<rlb_numeric_s> h(new rlb_numeric_s());
+  h->sym = sym;
+  h->precision = precision;
+  HIP_OK(hipGetDevice(&h->device));
+  const Symbolic& s = sym->s;
+  rlb_status st;
+  if ((st = upload(&h->d.panels, s.plan.panels))) return st;
+  if ((st = upload(&h->d.updates, s.plan.updates))) return st;
+  if ((st = upload(&h->d.amap, s.plan.amap))) return st;
+  if ((st = upload_solve(s, 0, h->d))) return st;
+  HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
+  *out = h.release();
+  return RLB_OK;
+}
+
+static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hipStream_t st,
+                           bool timed) {
+  const Symbolic& s = h->sym->s;
+  const Plan& p = s.plan;
+  launch_init_status(h->status, 1, st);
+  launch_fill(L, p.l_elems, 0.0, st);
+  launch_scatter_a(values, h->d.amap, s.nnz_a, L, st);
+  size_t ei = 0;
+  for (const Launch& l : p.launches) {
+    if (timed) (void)hipEventRecord(h->ev[ei++], st);
+    if (l.kind == 0)
+      launch_panel(h->d.panels + l.start, l.count, L, h->status, st);
+    else
+      launch_update(h->d.updates + l.start, l.count, L, h->precision, st);
+    if (timed) (void)hipEventRecord(h->ev[ei++], st);
+  }
+}
+
+rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size_t ws_bytes,
+                      void* stream) {
+  if (!h || (!values && h->sym->s.nnz_a) || (!workspace && h->sym->s.plan.l_elems))
+    return fail(RLB_ERR_ARG, "null argument");
+  const Symbolic& s = h->sym->s;
+  if (ws_bytes < (size_t)s.plan.l_elems * sizeof(double))
+    return fail(RLB_ERR_WORKSPACE, "workspace smaller than factor_bytes");
+  if (((uintptr_t)workspace & 7) != 0) return fail(RLB_ERR_ARG, "workspace not 8-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  h->L = (double*)workspace;
+  h->stream = st;
+  h->factored = false;
+  if (h->anorm_vals != values) h->anorm = -1.0;
+  if (h->profiling) {
+    size_t need = 2 * s.plan.launches.size();
+    while (h->ev.size() < need) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+    enqueue_factor(h, values, h->L, st, true);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    h->prof_update_ms = h->prof_panel_ms = 0;
+    h->prof_nupd = h->prof_npan = 0;
+    size_t ei = 0;
+    for (const Launch& l : s.plan.launches) {
+      float ms = 0;
+      HIP_OK(hipEventElapsedTime(&ms, h->ev[ei], h->ev[ei + 1]));
+      ei += 2;
+      if (l.kind == 0) {
+        h->prof_panel_ms += ms;
+        h->prof_npan++;
+      } else {
+        h->prof_update_ms += ms;
+        h->prof_nupd++;
+      }
+    }
+  } else if (h->graph_mode) {
+    if (!h->gexec || h->g_vals != values || h->g_L != workspace || h->g_stream != st) {
+      if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+      }
+      hipStream_t cs;
+      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g;
+      HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      enqueue_factor(h, values, h->L, cs, false);
+      hipError_t ce = hipStreamEndCapture(cs, &g);
+      (void)hipStreamDestroy(cs);
+      if (ce != hipSuccess) return fail(RLB_ERR_HIP, "graph capture failed");
+      hipError_t ie = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(RLB_ERR_HIP, "graph instantiate failed");
+      h->g_vals = values;
+      h->g_L = workspace;
+      h->g_stream = st;
+    }
+    HIP_OK(hipGraphLaunch(h->gexec, st));
+  } else {
+    enqueue_factor(h, values, h->L, st, false);
+  }
+  HIP_OK(hipGetLastError());
+  h->factored = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_factor_status(rlb_numeric h, int64_t* info) {
+  if (!h || !info) return fail(RLB_ERR_ARG, "null argument");
+  if (!h->L) return fail(RLB_ERR_STATE, "no factorization enqueued");
+  int v = 0;
+  HIP_OK(hipMemcpyAsync(&v, h->status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  *info = (v == 0x7fffffff) ? 0 : v;
+  if (*info) h->factored = false;
+  return (rlb_status)*info;
+}
+
+rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* stream) {
+  if (!h || nrhs < 0 || (nrhs > 0 && !B)) return fail(RLB_ERR_ARG, "bad argument");
+  const Symbolic& s = h->sym->s;
+  if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
+  if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
+  if (nrhs == 0 || s.n == 0) return RLB_OK;
+  return solve_into(s, h->d, h->sc, h->L, nrhs, B, ldb, B, ldb, (hipStream_t)stream);
+}
+
+rlb_status rlb_backward_error(rlb_numeric h, const double* values, int64_t nrhs, const double* B,
+                              const double* X, int64_t ld, void* stream, double* out) {
+  if (!h || !values || !B || !X || !out || nrhs < 0) return fail(RLB_ERR_ARG, "bad argument");
+  const Symbolic& s = h->sym->s;
+  if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
+  if (h->anorm_vals != values) {
+    h->anorm = -1.0;
+    h->anorm_vals = values;
+  }
+  for (int64_t c0 = 0; c0 < nrhs; c0 += SOLVE_MAXRHS) {
+    int nr = (int)std::min<int64_t>(SOLVE_MAXRHS, nrhs - c0);
+    rlb_status e = backward_errors(s, h->d, h->sc, values, nr, B + c0 * ld, X + c0 * ld, ld,
+                                   (hipStream_t)stream, out + c0, &h->anorm);
+    if (e) return e;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const double* B,
+                      double* X, int64_t ld, double tol, int32_t max_iter, void* stream,
+                      rlb_refine_report* rep) {
+  if (!h || !values || !B || !X || nrhs < 1 || nrhs > SOLVE_MAXRHS || max_iter < 0)
+    return fail(RLB_ERR_ARG, "bad argument (1 <= nrhs <= 16)");
+  const Symbolic& s = h->sym->s;
+  if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
+  if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
+  hipStream_t st = (hipStream_t)stream;
+  rlb_refine_report r;
+  std::memset(&r, 0, sizeof(r));
+  rlb_status e = solve_into(s, h->d, h->sc, h->L, nrhs, B, ld, X, ld, st);
+  if (e) return e;
+  if (h->anorm_vals != values) {
+    h->anorm = -1.0;
+    h->anorm_vals = values;
+  }
+  double be[SOLVE_MAXRHS];
+  int it = 0;
+  for (;;) {
+    e = backward_errors(s, h->d, h->sc, values, (int)nrhs, B, X, ld, st, be, &h->anorm);
+    if (e) return e;
+    double worst = 0;
+    for (int k = 0; k < nrhs; ++k) worst = std::max(worst, be[k]);
+    if (it < 64) r.history[it] = worst;
+    if (worst <= tol || it >= max_iter) {
+      r.converged = worst <= tol;
+      break;
+    }
+    // d = solve(r), X += d  (r = B - A X was left in the scratch by backward_errors)
+    launch_perm_in(h->d.perm, h->sc.r, s.n, h->sc.y, s.n, s.n, (int)nrhs, st);
+    enqueue_solve_levels(s, h->d, h->L, h->sc.y, (int)nrhs, st);
+    launch_perm_out(h->d.perm, h->sc.y, s.n, h->sc.d, s.n, s.n, (int)nrhs, st);
+    launch_axpy(X, ld, h->sc.d, s.n, s.n, (int)nrhs, st);
+    HIP_OK(hipGetLastError());
+    ++it;
+  }
+  r.iterations = it;
+  for (int k = 0; k < nrhs; ++k) r.backward_error[k] = be[k];
+  if (rep) *rep = r;
+  return r.converged ? RLB_OK : fail(RLB_ERR_NOT_CONVERGED, "refinement did not reach tol");
+}
+
+rlb_status rlb_factor_export(rlb_numeric h, int64_t* colptr, int64_t* rowidx, double* vals) {
+  if (!h || !colptr || !rowidx || !vals) return fail(RLB_ERR_ARG, "null argument");
+  if (!h->L) return fail(RLB_ERR_STATE, "no factorization");
+  const Symbolic& s = h->sym->s;
+  std::vector<double> hl(s.plan.l_elems);
+  HIP_OK(hipStreamSynchronize(h->stream));
+  HIP_OK(hipMemcpy(hl.data(), h->L, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
+  int64_t S = (int64_t)s.sn_ptr.size() - 1, q = 0;
+  colptr[0] = 0;
+  for (int64_t J = 0; J < S; ++J) {
+    int64_t f = s.sn_ptr[J], w = s.sn_ptr[J + 1] - f, m = s.gl_ptr[J + 1] - s.gl_ptr[J];
+    const int32_t* g = s.gl.data() + s.gl_ptr[J];
+    for (int64_t c = 0; c < w; ++c) {
+      for (int64_t r = c; r < m; ++r) {
+        rowidx[q] = g[r];
+        vals[q] = hl[s.plan.off[J] + c * m + r];
+        ++q;
+      }
+      colptr[f + c + 1] = q;
+    }
+  }
+  return RLB_OK;
+}
+
+void rlb_numeric_free(rlb_numeric h) { delete h; }
+
+rlb_status rlb_set_graph_mode(rlb_numeric h, int32_t on) {
+  if (!h) return fail(RLB_ERR_ARG, "null handle");
+  h->graph_mode = on != 0;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_profiling(rlb_numeric h, int32_t on) {
+  if (!h) return fail(RLB_ERR_ARG, "null handle");
+  h->profiling = on != 0;
+  return RLB_OK;
+}
+
+rlb_status rlb_last_profile(rlb_numeric h, double* update_ms, double* panel_ms, int64_t* n_update,
+                            int64_t* n_panel) {
+  if (!h) return fail(RLB_ERR_ARG, "null handle");
+  if (update_ms) *update_ms = h->prof_update_ms;
+  if (panel_ms) *panel_ms = h->prof_panel_ms;
+  if (n_update) *n_update = h->prof_nupd;
+  if (n_panel) *n_panel = h->prof_npan;
+  return RLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+
+rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t precision,
+                            rlb_batch* out, int64_t* ws_bytes) {
+  if (count < 1 || !syms || !out) return fail(RLB_ERR_ARG, "bad argument");
+  if (precision < 0 || precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+  *out = nullptr;
+  std::unique_ptr<rlb_batch_s> b(new rlb_batch_s());
+  b->precision = precision;
+  b->syms.assign(syms, syms + count);
+  b->base.resize(count);
+  b->nnz_ptr.assign(count + 1, 0);
+  int64_t run = 0;
+  int32_t maxlev = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!syms[i]) return fail(RLB_ERR_ARG, "null symbolic handle");
+    b->base[i] = run;
+    run += syms[i]->s.plan.l_elems;
+    b->nnz_ptr[i + 1] = b->nnz_ptr[i] + syms[i]->s.nnz_a;
+    maxlev = std::max(maxlev, syms[i]->s.plan.nlevels);
+  }
+  b->l_elems = run;
+  // merge: for each (level, step, kind) the tiles of every matrix, in matrix order
+  std::vector<size_t> cur(count, 0);
+  for (;;) {
+    // the smallest (level, step, kind) among the matrices' next launches
+    bool any = false;
+    int32_t bl = 0, bs = 0, bk = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      const auto& L = syms[i]->s.plan.launches;
+      if (cur[i] >= L.size()) continue;
+      const Launch& l = L[cur[i]];
+      if (!any || std::make_tuple(l.level, l.step, l.kind) < std::make_tuple(bl, bs, bk)) {
+        bl = l.level;
+        bs = l.step;
+        bk = l.kind;
+        any = true;
+      }
+    }
+    if (!any) break;
+    Launch m{bk, bl, bs, 0, 0, 0};
+    m.start = bk == 0 ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
+    for (int32_t i = 0; i < count; ++i) {
+      const Plan& p = syms[i]->s.plan;
+      if (cur[i] >= p.launches.size()) continue;
+      const Launch& l = p.launches[cur[i]];
+      if (l.level != bl || l.step != bs || l.kind != bk) continue;
+      if (bk == 0) {
+        for (int64_t t = 0; t < l.count; ++t) {
+          PanelTile pt = p.panels[l.start + t];
+          pt.diag += b->base[i];
+          pt.slot = i;
+          b->panels.push_back(pt);
+        }
+      } else {
+        for (int64_t t = 0; t < l.count; ++t) {
+          UpdTile ut = p.updates[l.start + t];
+          ut.c += b->base[i];
+          ut.x += b->base[i];
+          ut.y += b->base[i];
+          b->updates.push_back(ut);
+        }
+      }
+      cur[i]++;
+    }
+    m.count = (bk == 0 ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) - m.start;
+    b->launches.push_back(m);
+  }
+  (void)maxlev;
+  std::vector<int64_t> amap;
+  amap.reserve(b->nnz_ptr[count]);
+  for (int32_t i = 0; i < count; ++i)
+    for (int64_t a : syms[i]->s.plan.amap) amap.push_back(a + b->base[i]);
+  rlb_status st;
+  if ((st = upload(&b->d_panels, b->panels))) return st;
+  if ((st = upload(&b->d_updates, b->updates))) return st;
+  if ((st = upload(&b->d_amap, amap))) return st;
+  if ((st = upload(&b->d_nnz_ptr, b->nnz_ptr))) return st;
+  HIP_OK(hipMalloc((void**)&b->d_vals, sizeof(double*) * count));
+  HIP_OK(hipMalloc((void**)&b->status, sizeof(int) * count));
+  b->per.resize(count);
+  for (int32_t i = 0; i < count; ++i)
+    if ((st = upload_solve(syms[i]->s, b->base[i], b->per[i]))) return st;
+  if (ws_bytes) *ws_bytes = b->l_elems * (int64_t)sizeof(double);
+  *out = b.release();
+  return RLB_OK;
+}
+
+static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
+  int32_t count = (int32_t)b->syms.size();
+  launch_init_status(b->status, count, st);
+  launch_fill(L, b->l_elems, 0.0, st);
+  launch_scatter_batch(b->d_vals, b->d_nnz_ptr, count, b->nnz_ptr[count], b->d_amap, L, st);
+  for (const Launch& l : b->launches) {
+    if (l.kind == 0)
+      launch_panel(b->d_panels + l.start, l.count, L, b->status, st);
+    else
+      launch_update(b->d_updates + l.start, l.count, L, b->precision, st);
+  }
+}
+
+rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  if (!b || !values || !workspace) return fail(RLB_ERR_ARG, "null argument");
+  if (ws_bytes < (size_t)b->l_elems * sizeof(double))
+    return fail(RLB_ERR_WORKSPACE, "workspace smaller than the batch needs");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t count = (int32_t)b->syms.size();
+  std::vector<const double*> vals(values, values + count);
+  b->L = (double*)workspace;
+  b->stream = st;
+  bool same = b->gexec && b->g_vals == vals && b->g_L == workspace && b->g_stream == st;
+  if (!same) {
+    // pointer table: a pageable copy enqueued on the stream before the factor
+    HIP_OK(hipMemcpyAsync((void*)b->d_vals, vals.data(), sizeof(double*) * count,
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  if (b->graph_mode) {
+    if (!same) {
+      if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+      }
+      hipStream_t cs;
+      HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g;
+      HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      enqueue_batch(b, b->L, cs);
+      hipError_t ce = hipStreamEndCapture(cs, &g);
+      (void)hipStreamDestroy(cs);
+      if (ce != hipSuccess) return fail(RLB_ERR_HIP, "graph capture failed");
+      hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(RLB_ERR_HIP, "graph instantiate failed");
+      b->g_vals = vals;
+      b->g_L = workspace;
+      b->g_stream = st;
+    }
+    HIP_OK(hipGraphLaunch(b->gexec, st));
+  } else {
+    enqueue_batch(b, b->L, st);
+    b->g_vals = vals;  // pointer table on the device matches these values
+    b->g_L = nullptr;
+  }
+  HIP_OK(hipGetLastError());
+  b->factored = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_batch_status(rlb_batch b, int64_t* info) {
+  if (!b || !info) return fail(RLB_ERR_ARG, "null argument");
+  if (!b->L) return fail(RLB_ERR_STATE, "no factorization enqueued");
+  int32_t count = (int32_t)b->syms.size();
+  std::vector<int> v(count);
+  HIP_OK(hipMemcpyAsync(v.data(), b->status, sizeof(int) * count, hipMemcpyDeviceToHost,
+                        b->stream));
+  HIP_OK(hipStreamSynchronize(b->stream));
+  rlb_status worst = RLB_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    info[i] = v[i] == 0x7fffffff ? 0 : v[i];
+    if (info[i] && !worst) worst = (rlb_status)info[i];
+  }
+  return worst;
+}
+
+rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int64_t ldb,
+                           void* stream) {
+  if (!b || i < 0 || i >= (int32_t)b->syms.size() || nrhs < 0 || (nrhs && !B))
+    return fail(RLB_ERR_ARG, "bad argument");
+  if (!b->factored) return fail(RLB_ERR_STATE, "no factorization");
+  const Symbolic& s = b->syms[i]->s;
+  if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
+  if (nrhs == 0 || s.n == 0) return RLB_OK;
+  return solve_into(s, b->per[i], b->sc, b->L, nrhs, B, ldb, B, ldb, (hipStream_t)stream);
+}
+
+rlb_status rlb_batch_set_graph_mode(rlb_batch b, int32_t on) {
+  if (!b) return fail(RLB_ERR_ARG, "null handle");
+  b->graph_mode = on != 0;
+  return RLB_OK;
+}
+
+void rlb_batch_free(rlb_batch b) { delete b; }
+
+}  // extern "C"

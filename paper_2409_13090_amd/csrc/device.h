@@ -1,0 +1,48 @@
+// Host-side launch wrappers of the device kernels (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "symbolic.h"
+
+namespace rlb {
+
+struct SnMeta {
+  int64_t off;  // Lnz(J) offset in factor storage
+  int32_t f;    // first column
+  int32_t w;    // width
+  int32_t m;    // rows
+  int32_t gl;   // offset of glbind(J) in the index array
+};
+
+constexpr int SOLVE_MAXRHS = 16;
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_init_status(int* status, int count, hipStream_t st);
+void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, double* L,
+                      hipStream_t st);
+void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
+                          int64_t total, const int64_t* amap, double* L, hipStream_t st);
+void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st);
+void launch_update(const UpdTile* tiles, int64_t count, double* L, int precision,
+                   hipStream_t st);
+void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
+                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st);
+void launch_bwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
+                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st);
+void launch_perm_in(const int64_t* perm, const double* b, int64_t ldb, double* y, int64_t ldy,
+                    int64_t n, int nrhs, hipStream_t st);
+void launch_perm_out(const int64_t* perm, const double* y, int64_t ldy, double* x, int64_t ldx,
+                     int64_t n, int nrhs, hipStream_t st);
+void launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* src,
+                     const double* vals, const double* x, int64_t ldx, const double* b,
+                     int64_t ldb, double* r, int64_t ldr, int nrhs, hipStream_t st);
+void launch_absmax(const double* v, int64_t n, int64_t ld, int nrhs, unsigned long long* out,
+                   hipStream_t st);
+void launch_anorm(int64_t n, const int64_t* rp, const int64_t* src, const double* vals,
+                  unsigned long long* out, hipStream_t st);
+void launch_axpy(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
+                 hipStream_t st);
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
+
+}  // namespace rlb

@@ -1,0 +1,115 @@
+// Host symbolic analysis and numeric plan for right-looking blocked (RLB)
+// supernodal Cholesky. Internal header of the rlb library (not installed).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rlb {
+
+struct AnalyzeOptions {
+  int ordering = 1;  // 0 natural, 1 grid nested dissection, 2 user permutation
+  const int64_t* user_perm = nullptr;
+  int64_t grid[4] = {0, 0, 0, 1};
+  double merge_cap = 0.125;
+  int reorder = 1;
+  int maximal_blocks = 1;
+  int precision = 0;
+  int tile_policy = 0;
+};
+
+// One dense update C -= X * Y^T into factor storage, cut to at most a 64x64
+// output tile. Offsets are element offsets into the factor buffer.
+struct UpdTile {
+  int64_t c;        // target tile origin
+  int64_t x;        // first source row of X at its first column
+  int64_t y;        // first source row of Y at its first column
+  int32_t ldc;      // leading dimension of the target panel
+  int32_t lds;      // leading dimension of the source panel
+  int32_t m, n, k;  // tile rows, tile columns, inner dimension
+  int32_t flags;    // bit0: diagonal tile (write only row >= col); bit1: atomic
+  int32_t src;      // source supernode (for per-panel scales)
+};
+static_assert(sizeof(UpdTile) == 56, "UpdTile layout");
+
+// One row tile of the fused POTRF + TRSM of a <=64-wide column block.
+struct PanelTile {
+  int64_t diag;       // offset of the diagonal tile's top-left element
+  int32_t ld;         // leading dimension of the panel
+  int32_t nb;         // columns in the block (1..64)
+  int32_t nrows;      // rows from the diagonal tile down to the panel bottom
+  int32_t row0;       // first row handled here, relative to the diagonal tile
+  int32_t col;        // factored-order index of the block's first column
+  int32_t slot;       // status slot (matrix index in a batch)
+};
+static_assert(sizeof(PanelTile) == 32, "PanelTile layout");
+
+struct Launch {
+  int32_t kind;   // 0 panel, 1 update
+  int32_t level;
+  int32_t step;   // column block index inside the level
+  int32_t pad;
+  int64_t start;  // first tile
+  int64_t count;  // number of tiles
+};
+
+struct Plan {
+  // factor storage: Lnz(J) is m_J x w_J column-major at off[J], ld = m_J
+  std::vector<int64_t> off;
+  int64_t l_elems = 0;
+  std::vector<int64_t> amap;  // input CSC entry -> position in factor storage
+  std::vector<PanelTile> panels;
+  std::vector<UpdTile> updates;
+  std::vector<Launch> launches;
+  int32_t nlevels = 0;
+  std::vector<int32_t> level;       // height of every supernode
+  std::vector<int64_t> lvl_ptr;     // supernodes grouped by level
+  std::vector<int32_t> lvl_sn;
+  // full symmetric A in the factored order, CSR, values gathered from the input
+  std::vector<int64_t> a_rowptr;
+  std::vector<int32_t> a_col;
+  std::vector<int64_t> a_src;
+  int64_t n_atomic_tiles = 0;
+  double flops_tiles = 0;  // flops the update tiles execute (full 64x64 MFMA work)
+  double flops_upd_alg = 0;  // algorithmic flops of the update tiles (entries written x 2k)
+};
+
+struct Symbolic {
+  int64_t n = 0;
+  int64_t nnz_a = 0;
+  AnalyzeOptions opt;
+  std::vector<int64_t> colptr, rowidx;  // copy of the input pattern
+  std::vector<int64_t> perm;       // final: perm[new] = old
+  std::vector<int64_t> perm_nd;    // after the fill-reducing ordering
+  std::vector<int64_t> perm_post;  // after the postorder
+  std::vector<int64_t> etree_post; // column etree under perm_post
+  std::vector<int64_t> etree;      // column etree under perm
+  std::vector<int64_t> fund_ptr;   // fundamental supernodes (perm_post numbering)
+  std::vector<int64_t> sn_ptr;     // merged supernodes
+  std::vector<int64_t> sn_parent;
+  std::vector<int64_t> gl_ptr;     // glbind(J), final numbering
+  std::vector<int32_t> gl;
+  std::vector<int64_t> rel_ptr;    // relind(J, p(J)) for every row below the diagonal block
+  std::vector<int32_t> rel;
+  std::vector<int64_t> blk_ptr;    // block sizes, top to bottom
+  std::vector<int32_t> blk;
+  std::vector<int64_t> rbp_ptr;    // per J: its (J, P) pairs
+  std::vector<int32_t> rbp_anc;    // ancestor P of each pair
+  std::vector<int64_t> rbv_ptr;    // per pair: relindB(J, P) values
+  std::vector<int32_t> rbv;
+  std::vector<int64_t> colcount;   // exact column counts, final numbering
+  int64_t merge_added = 0, merge_base = 0;
+  int64_t nnz_exact = 0, nnz_stored = 0;
+  double flops_exact = 0, flops_padded = 0;
+  int64_t n_blocks = 0, n_pairs = 0, n_calls = 0;  // blocks, (J,P) pairs, SYRK+GEMM calls
+  Plan plan;
+};
+
+// Returns 0 or a negative rlb status; fills `err` with a message on failure.
+int analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
+            const AnalyzeOptions& opt, Symbolic& out, std::string& err);
+
+int build_plan(Symbolic& s, std::string& err);
+
+}  // namespace rlb

@@ -1,0 +1,207 @@
+"""Device path (HIP kernels through the C-ABI) against the CPU oracle.
+
+Small and medium matrices are compared element by element (structure rule:
+the oracle's exact structure lies inside the stored structure and every
+stored-only entry is exactly 0.0; values within relative Frobenius 1e-10).
+The 48^3 workload is compared on the columns the oracle can afford (a prefix
+of the factored order, which Algorithm 1 computes exactly on its own) and on
+properties of the whole factor."""
+import numpy as np
+import pytest
+
+from parity_util import FP64_TOL, compare_factor, gpu_factor, oracle_factor, probe_residual
+from paper_2409_13090_amd import rlb
+from paper_2409_13090_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return torch
+
+
+def solve_check(num, A, tol=1e-14):
+    torch = _torch()
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).cuda()
+    B = B.T.contiguous().T if B.dim() == 2 else B
+    X = B.clone()
+    X = X.T.contiguous().T
+    num.solve(X)
+    be = num.backward_error(B, X)
+    assert np.all(be <= tol), be
+    return be
+
+
+CASES = [
+    ("c1_lap2d5_30", lambda: W.config1()),
+    ("lap2d9_45x38", lambda: W.small_grid("9pt", (45, 38, 1), seed=21)),
+    ("lap3d7_17", lambda: W.small_grid("7pt", (17, 17, 17), seed=22, shift=1e-4)),
+    ("lap3d7_23x19x15", lambda: W.small_grid("7pt", (23, 19, 15), seed=23)),
+    ("lap3d27_13", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                        shift=1e-4)),
+    ("elast_7x6x6", lambda: W.elasticity_like((7, 6, 6), np.random.default_rng(25), 1e-6)),
+    ("batch_member_7", lambda: W.batch_member(7)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_factor_matches_oracle(name, make):
+    A = make()
+    print(f"[case] {name} n={A.n} nnz={A.nnz}", flush=True)
+    o, f = oracle_factor(A)
+    s, num, vals, info = gpu_factor(A)
+    assert info == 0 and f["info"] == 0
+    assert np.array_equal(s.array("perm"), o["perm"])
+    err = compare_factor(num.export(), f, A.n)
+    print(f"[case] {name} rel_err={err:.3e}", flush=True)
+    if A.rhs is not None:
+        solve_check(num, A)
+
+
+def test_supernode_wider_than_many_panels():
+    """A dense-ish 3D block whose top separator spans several 64-column panels
+    and ragged tails (widths not multiples of 64)."""
+    A = W.small_grid("27pt", (11, 11, 9), seed=26, shift=1e-3)
+    s = rlb.Symbolic.from_matrix(A)
+    sn = s.array("sn_ptr")
+    assert np.max(np.diff(sn)) > 128 and np.max(np.diff(sn)) % 64 != 0
+    o, f = oracle_factor(A)
+    s2, num, vals, info = gpu_factor(A)
+    compare_factor(num.export(), f, A.n)
+
+
+def test_edge_cases_tiny_diagonal_chain():
+    torch = _torch()
+    # n = 1
+    A = W.from_dense_lower(np.array([[4.0]]))
+    s, num, vals, info = gpu_factor(A)
+    cp, ri, vx = num.export()
+    assert info == 0 and vx[0] == 2.0
+    # diagonal: no updates at all
+    d = np.arange(1.0, 40.0)
+    A = W.from_dense_lower(np.diag(d))
+    s, num, vals, info = gpu_factor(A)
+    cp, ri, vx = num.export()
+    assert np.array_equal(vx, np.sqrt(d))
+    # tridiagonal chain (one supernode after merging), closed form
+    n = 200
+    Ad = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    A = W.from_dense_lower(Ad)
+    o, f = oracle_factor(A, ordering="natural")
+    s, num, vals, info = gpu_factor(A, ordering="natural")
+    compare_factor(num.export(), f, n)
+    k = np.arange(1, n + 1, dtype=float)
+    L = np.zeros((n, n))
+    cp, ri, vx = num.export()
+    for j in range(n):
+        L[ri[cp[j]:cp[j + 1]], j] = vx[cp[j]:cp[j + 1]]
+    assert np.allclose(np.diag(L), np.sqrt((k + 1) / k), rtol=1e-13)
+    # no merging, no reordering
+    A = W.small_grid("7pt", (9, 9, 9), seed=27)
+    o, f = oracle_factor(A, merge_cap=0.0, reorder=False)
+    s, num, vals, info = gpu_factor(A, merge_cap=0.0, reorder=False)
+    compare_factor(num.export(), f, A.n)
+
+
+def test_not_positive_definite_reports_oracle_column():
+    A = W.small_grid("7pt", (10, 10, 10), seed=28)
+    # make it indefinite: a large negative shift on a set of late diagonals
+    A.values = A.values.copy()
+    diag_pos = A.colptr[:-1]
+    A.values[diag_pos[700:]] -= 50.0
+    o, f = oracle_factor(A)
+    assert f["info"] > 0
+    s, num, vals, info = gpu_factor(A)
+    assert info == f["info"]
+    with pytest.raises(rlb.RlbError):
+        torch = _torch()
+        num.solve(torch.zeros(A.n, dtype=torch.float64, device="cuda"))
+
+
+def test_repeat_factor_is_stable_and_graph_replay_matches():
+    torch = _torch()
+    A = W.small_grid("7pt", (14, 13, 12), seed=29)
+    o, f = oracle_factor(A)
+    s, num, vals, info = gpu_factor(A)
+    ref = num.export()[2].copy()
+    compare_factor(num.export(), f, A.n)
+    num2 = rlb.Numeric(s)
+    num2.set_graph_mode(True)
+    for rep in range(3):
+        assert num2.factor(vals) == 0
+        got = num2.export()[2]
+        compare_factor(num2.export(), f, A.n)
+        # eager work between replays
+        num.factor(vals)
+        torch.cuda.synchronize()
+        d = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert d < 1e-13, d
+
+
+def test_batched_matches_unbatched_and_oracle():
+    torch = _torch()
+    mats = [W.batch_member(i) for i in range(12)]
+    syms = [rlb.Symbolic.from_matrix(A) for A in mats]
+    b = rlb.Batch(syms)
+    vals = [torch.from_numpy(A.values).cuda() for A in mats]
+    info = b.factor(vals)
+    assert np.all(info == 0)
+    for i, A in enumerate(mats):
+        num = rlb.Numeric(syms[i])
+        num.factor(vals[i])
+        # the batch's factor of matrix i, solved through the batch handle
+        B = torch.from_numpy(A.rhs[:, 0].copy()).cuda()
+        X = B.clone()
+        b.solve(i, X)
+        be = num.backward_error(B, X)
+        assert be[0] <= 1e-14, (i, be)
+        if i < 3:
+            o, f = oracle_factor(A)
+            compare_factor(num.export(), f, A.n)
+
+
+def test_fp32_updates_with_refinement_reach_1e14():
+    torch = _torch()
+    A = W.small_grid("27pt", (14, 14, 14), seed=30, lo=0.1, hi=1.0, shift=1e-4, nrhs=4)
+    s = rlb.Symbolic.from_matrix(A)
+    num = rlb.Numeric(s, rlb.RLB_PREC_FP32_UPDATES)
+    vals = torch.from_numpy(A.values).cuda()
+    assert num.factor(vals) == 0
+    # the FP32-update factor is close to the FP64 oracle, not equal
+    o, f = oracle_factor(A)
+    err = compare_factor(num.export(), f, A.n, tol=1e-3)
+    assert err > 1e-12
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).cuda().T.contiguous().T
+    X = torch.zeros_like(B).T.contiguous().T
+    rep = num.refine(B, X, tol=1e-14, max_iter=30)
+    assert rep["converged"], rep
+    assert max(rep["backward_error"]) <= 1e-14
+
+
+@pytest.mark.timeout(600)
+def test_full_size_lap3d7_48_sampled_and_properties():
+    """The 48^3 workload in the launch configuration the benchmark times."""
+    torch = _torch()
+    A = W.config2()
+    print(f"[case] lap3d7_48 n={A.n}", flush=True)
+    s, num, vals, info = gpu_factor(A)
+    assert info == 0
+    gpu = num.export()
+    # whole-factor properties
+    perm = s.array("perm")
+    pr = probe_residual(A, perm, gpu, nprobe=3)
+    print(f"[case] probe residual {pr:.3e}", flush=True)
+    assert pr < 1e-14
+    assert np.all(gpu[2][gpu[0][:-1]] > 0)  # positive diagonal
+    be = solve_check(num, A, tol=1e-14)
+    print(f"[case] backward errors {be}", flush=True)
+    # exact columns: the oracle's own analysis, Algorithm 1 on a column prefix
+    from oracle import onum, osym
+    o = osym.analyze(A)
+    assert np.array_equal(o["perm"], perm)
+    ncols = int(0.8 * A.n)
+    f = onum.factor(A, o["perm"], o["structs"], ncols=ncols)
+    err = compare_factor(gpu, f, A.n, ncols=ncols)
+    print(f"[case] prefix {ncols} cols rel_err={err:.3e}", flush=True)

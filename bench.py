@@ -1,0 +1,217 @@
+"""Benchmark of the RLB supernodal Cholesky hot path on one MI355X.
+
+Workload: 3D 7-point Laplacian on a 48^3 grid (n = 110592), edge weights
+10^U(-2,2), diagonal shift 1e-6 * max diagonal, nested dissection with
+reordering inside supernodes, 4 right-hand sides (seeded synthetic data).
+
+One step = one pass of the device hot path in FP64: factor (A-load, then per
+level the POTRF+TRSM of every supernode and its SYRK/GEMM updates written
+straight into ancestor storage), solve of the 4 right-hand sides, and the
+FP64 residual / backward error. The analysis (host symbolic phase) and the
+upload of the integer plan happen once, before timing.
+
+value = factorization GFLOP/s = F_exact / t_factor, where F_exact is the sum
+over columns of (column count)^2 on the exact structure and t_factor is the
+mean device time of the factor (HIP events on the factor's stream, timed
+steps only). The same matrix is also factored with FP32-operand updates and
+refined in FP64 to backward error <= 1e-14 (reported under "fp32_ir").
+
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "factor GFLOP/s + % MFMA peak, FP64 vs FP32-update+IR at backward err ≤1e-14"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def cpu_baseline(A, sym, budget_flops=3.0e10):
+    """Time the CPU oracle (Algorithm 1, one thread) on a bounded sample of the
+    same workload: the first k columns of the factored matrix, whose factor
+    columns Algorithm 1 computes exactly on their own."""
+    import numpy as np
+
+    from oracle import onum, osym
+
+    perm = sym.array("perm")
+    cc = sym.array("colcount").astype(np.float64)
+    cum = np.cumsum(cc * cc)
+    k = int(np.searchsorted(cum, budget_flops))
+    k = max(1, min(k, A.n))
+    a_cp, a_ri, a_x = osym.permute_lower(A.n, A.colptr, A.rowidx, A.values, perm)
+    structs, _ = osym.column_structures(A.n, a_cp, a_ri, upto=k)
+    l_cp, l_ri = onum.pattern_csc(structs)
+    t0 = time.perf_counter()
+    _, info = onum.alg1(A.n, a_cp, a_ri, a_x, l_cp, l_ri, ncols=k)
+    dt = time.perf_counter() - t0
+    flops = float(cum[k - 1])
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"Algorithm 1 on the first {k} of {A.n} columns of the 48^3 factor "
+                      f"({flops:.3e} flops, {dt:.1f} s, info={info})",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=7)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--side", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the factor as a HIP graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the distributed path is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_13090_amd import rlb
+    from paper_2409_13090_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    A = W.config2(side=args.side)
+    t0 = time.perf_counter()
+    sym = rlb.Symbolic.from_matrix(A)
+    t_analyze = time.perf_counter() - t0
+    info = sym.info()
+    F = info["flops_exact"]
+
+    vals = torch.from_numpy(A.values).to(dev)
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).to(dev).T.contiguous().T
+    X = torch.empty_like(B).T.contiguous().T
+    num = rlb.Numeric(sym, rlb.RLB_PREC_FP64)
+    if args.graph:
+        num.set_graph_mode(True)
+    ws = torch.empty(info["factor_bytes"] // 8 + 1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(profile):
+        num.set_profiling(profile)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        num.factor(vals, ws, check=False)
+        e1.record(stream)
+        st = num.status()
+        assert st == 0, f"factor reported info={st}"
+        X.copy_(B)
+        num.solve(X)
+        be = num.backward_error(B, X)
+        return e0, e1, be, (num.last_profile() if profile else None)
+
+    for _ in range(args.warmup):
+        step(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    recs = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    fac_ms = [a.elapsed_time(b) for a, b, _, _ in recs]
+    be = np.max([r[2] for r in recs], axis=0)
+    upd_ms = [r[3]["update_ms"] for r in recs]
+    n_upd = recs[0][3]["n_update"]
+    pan_ms = [r[3]["panel_ms"] for r in recs]
+    t_fac = statistics.mean(fac_ms) / 1e3
+    gflops = F / t_fac / 1e9
+
+    # dominant kernel: the SYRK/GEMM update tiles (FP64 MFMA)
+    upd_s = statistics.mean(upd_ms) / 1e3
+    ach = info["flops_upd_alg"] / upd_s / 1e12
+    roof = {"kernel": "k_update<double> (SYRK/GEMM into target, MFMA f64 16x16x4)",
+            "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "launches_per_factor": n_upd,
+            "avg_launch_us": round(statistics.mean(upd_ms) / n_upd * 1e3, 2),
+            "alg_flops_per_launch": info["flops_upd_alg"] / n_upd}
+
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lap3d7_{args.side}: 3D 7-point Laplacian {args.side}^3 "
+                               f"(n={A.n}), weights 10^U(-2,2), shift 1e-6*max diag, "
+                               "nested dissection + reordering within supernodes, 4 RHS",
+                   "n": A.n, "nrhs": int(A.rhs.shape[1]), "graph": bool(args.graph)},
+        "pct_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS * 100, 3),
+        "factor_ms": round(t_fac * 1e3, 3),
+        "factor_ms_min": round(min(fac_ms), 3),
+        "panel_ms": round(statistics.mean(pan_ms), 3),
+        "update_ms": round(statistics.mean(upd_ms), 3),
+        "flops_exact": F,
+        "backward_error": [float(f"{v:.3e}") for v in be],
+        "analyze_s": round(t_analyze, 3),
+        "plan": {k: info[k] for k in ("n_supernodes", "n_levels", "n_launches",
+                                      "n_update_tiles", "n_panel_tiles", "n_atomic_tiles",
+                                      "nnz_stored")},
+        "roofline": roof,
+    }
+
+    if not args.no_mixed:
+        num32 = rlb.Numeric(sym, rlb.RLB_PREC_FP32_UPDATES)
+        ws32 = torch.empty_like(ws)
+        ms32, its, tts, be32 = [], [], [], []
+        for rep in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            num32.factor(vals, ws32, check=False)
+            e1.record(stream)
+            assert num32.status() == 0
+            X32 = torch.zeros_like(B).T.contiguous().T
+            r = num32.refine(B, X32, tol=1e-14, max_iter=30)
+            torch.cuda.synchronize()
+            tts.append(time.perf_counter() - t0)
+            ms32.append(e0.elapsed_time(e1))
+            its.append(r["iterations"])
+            be32.append(max(r["backward_error"]))
+        t32 = statistics.mean(ms32[1:]) / 1e3
+        # FP64 time to solution for comparison: factor + solve + residual check
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        num.set_profiling(False)
+        num.factor(vals, ws)
+        X.copy_(B)
+        num.solve(X)
+        num.backward_error(B, X)
+        torch.cuda.synchronize()
+        tts64 = time.perf_counter() - t0
+        out["fp32_ir"] = {"factor_gflops": round(F / t32 / 1e9, 2),
+                          "pct_fp32_peak": round(F / t32 / 1e12 / PEAK_FP32_TFLOPS * 100, 3),
+                          "factor_ms": round(t32 * 1e3, 3),
+                          "ir_iterations": its[-1],
+                          "backward_error": float(f"{max(be32):.3e}"),
+                          "time_to_solution_ms": round(statistics.mean(tts[1:]) * 1e3, 3),
+                          "fp64_time_to_solution_ms": round(tts64 * 1e3, 3)}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, sym)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -354,6 +354,8 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* o) {
   o->n_atomic_tiles = s.plan.n_atomic_tiles;
   o->n_launches = (int64_t)s.plan.launches.size();
   o->flops_tiles = s.plan.flops_tiles;
+  o->flops_upd_alg = s.plan.flops_upd_alg;
+  o->flops_panel = s.plan.flops_panel;
   return RLB_OK;
 }
 
@@ -386,6 +388,22 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
   else if (w == "level") put32(s.plan.level);
   else if (w == "off") put64(s.plan.off);
   else if (w == "amap") put64(s.plan.amap);
+  else if (w == "update_tiles") {  // c, x, y, ldc, lds, m, n, k, flags, src per tile
+    for (const UpdTile& t : s.plan.updates) {
+      int64_t v[10] = {t.c, t.x, t.y, t.ldc, t.lds, t.m, t.n, t.k, t.flags, t.src};
+      tmp.insert(tmp.end(), v, v + 10);
+    }
+  } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, mode per tile
+    for (const PanelTile& t : s.plan.panels) {
+      int64_t v[8] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.mode};
+      tmp.insert(tmp.end(), v, v + 8);
+    }
+  } else if (w == "launches") {  // kind, level, step, start, count per launch
+    for (const Launch& l : s.plan.launches) {
+      int64_t v[5] = {l.kind, l.level, l.step, l.start, l.count};
+      tmp.insert(tmp.end(), v, v + 5);
+    }
+  }
   else return fail(RLB_ERR_ARG, "unknown array " + w);
   *len = (int64_t)tmp.size();
   if (out && !tmp.empty()) std::memcpy(out, tmp.data(), tmp.size() * sizeof(int64_t));
@@ -423,10 +441,10 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   size_t ei = 0;
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
-    if (l.kind == 0)
-      launch_panel(h->d.panels + l.start, l.count, L, h->status, st);
-    else
+    if (l.kind == LAUNCH_UPDATE)
       launch_update(h->d.updates + l.start, l.count, L, h->precision, st);
+    else
+      launch_panel(h->d.panels + l.start, l.count, L, h->status, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
 }
@@ -461,12 +479,12 @@ rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size
       float ms = 0;
       HIP_OK(hipEventElapsedTime(&ms, h->ev[ei], h->ev[ei + 1]));
       ei += 2;
-      if (l.kind == 0) {
-        h->prof_panel_ms += ms;
-        h->prof_npan++;
-      } else {
+      if (l.kind == LAUNCH_UPDATE) {
         h->prof_update_ms += ms;
         h->prof_nupd++;
+      } else {
+        h->prof_panel_ms += ms;
+        h->prof_npan++;
       }
     }
   } else if (h->graph_mode) {
@@ -670,13 +688,13 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     }
     if (!any) break;
     Launch m{bk, bl, bs, 0, 0, 0};
-    m.start = bk == 0 ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
+    m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
       const Plan& p = syms[i]->s.plan;
       if (cur[i] >= p.launches.size()) continue;
       const Launch& l = p.launches[cur[i]];
       if (l.level != bl || l.step != bs || l.kind != bk) continue;
-      if (bk == 0) {
+      if (bk != LAUNCH_UPDATE) {
         for (int64_t t = 0; t < l.count; ++t) {
           PanelTile pt = p.panels[l.start + t];
           pt.diag += b->base[i];
@@ -694,7 +712,8 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
       }
       cur[i]++;
     }
-    m.count = (bk == 0 ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) - m.start;
+    m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
+              m.start;
     b->launches.push_back(m);
   }
   (void)maxlev;
@@ -723,10 +742,10 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   launch_fill(L, b->l_elems, 0.0, st);
   launch_scatter_batch(b->d_vals, b->d_nnz_ptr, count, b->nnz_ptr[count], b->d_amap, L, st);
   for (const Launch& l : b->launches) {
-    if (l.kind == 0)
-      launch_panel(b->d_panels + l.start, l.count, L, b->status, st);
-    else
+    if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, l.count, L, b->precision, st);
+    else
+      launch_panel(b->d_panels + l.start, l.count, L, b->status, st);
   }
 }
 

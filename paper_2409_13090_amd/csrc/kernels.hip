@@ -80,8 +80,8 @@ __global__ __launch_bounds__(64) void k_panel(const PanelTile* __restrict__ tile
   const int nb = t.nb;
   const int64_t ld = t.ld;
   double* D = L + t.diag;
-  int bad = 0x7fffffff;
-  {
+  if (t.mode != 2) {
+    int bad = 0x7fffffff;
     double row[64];
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
@@ -104,13 +104,23 @@ __global__ __launch_bounds__(64) void k_panel(const PanelTile* __restrict__ tile
       sr[lane][c] = row[c];
       __syncthreads();
     }
-    if (t.row0 == nb && lane < nb) {
+    if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
+    if (lane < nb) {
 #pragma unroll
       for (int j = 0; j < 64; ++j)
         if (j < nb && j <= lane) D[(int64_t)j * ld + lane] = row[j];
     }
+    if (t.mode == 1) return;
+  } else {
+    // the diagonal tile was factored by this block's mode-1 item in an
+    // earlier launch: stage it (identity beyond nb)
+    for (int j = 0; j < 64; ++j) {
+      double v = (j == lane) ? 1.0 : 0.0;
+      if (lane < nb && j < nb && j <= lane) v = D[(int64_t)j * ld + lane];
+      sr[lane][j] = v;
+    }
+    __syncthreads();
   }
-  if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
   // TRSM: x * L^T = a for row r, x_c = (a_c - sum_{k<c} x_k L(c,k)) / L(c,c).
   // Loads are unconditional (clamped indices, 32-bit offsets from a uniform
   // base) and every column ends with an LDS store into the unused pad column:

@@ -199,30 +199,49 @@ int build_plan(Symbolic& s, std::string& err) {
     for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
       steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
     for (int64_t k = 0; k < steps; ++k) {
-      // PANEL
-      Launch lp{0, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
+      // POTRF (and the TRSM of blocks with at most one row tile), then the
+      // TRSM row tiles of the taller blocks against their factored tiles
+      Launch lp{LAUNCH_POTRF, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
+      std::vector<PanelTile> trsm;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         if (k * NB >= w) continue;
         int64_t c0 = k * NB, nb = std::min<int64_t>(NB, w - c0), nrows = m - c0;
         int64_t below = nrows - nb;
-        int64_t nt = std::max<int64_t>(1, (below + 63) / 64);
-        for (int64_t t = 0; t < nt; ++t) {
-          PanelTile pt;
-          pt.diag = p.off[J] + c0 * m + c0;
-          pt.ld = (int32_t)m;
-          pt.nb = (int32_t)nb;
-          pt.nrows = (int32_t)nrows;
-          pt.row0 = (int32_t)(nb + 64 * t);
-          pt.col = (int32_t)(s.sn_ptr[J] + c0);
-          pt.slot = 0;
-          p.panels.push_back(pt);
+        // POTRF of the nb x nb tile (sum over its columns of (count)^2 with
+        // counts nb..1) plus TRSM of the rows below (nb^2 per row)
+        for (int64_t t = 0; t < nb; ++t) p.flops_panel += (double)(nb - t) * (double)(nb - t);
+        p.flops_panel += (double)below * (double)nb * (double)nb;
+        int64_t nt = (below + 63) / 64;
+        PanelTile pt;
+        pt.diag = p.off[J] + c0 * m + c0;
+        pt.ld = (int32_t)m;
+        pt.nb = (int32_t)nb;
+        pt.nrows = (int32_t)nrows;
+        pt.row0 = (int32_t)nb;
+        pt.col = (int32_t)(s.sn_ptr[J] + c0);
+        pt.slot = 0;
+        pt.pad = 0;
+        pt.mode = nt <= 1 ? 0 : 1;
+        p.panels.push_back(pt);
+        if (nt > 1) {
+          for (int64_t t = 0; t < nt; ++t) {
+            PanelTile tt = pt;
+            tt.mode = 2;
+            tt.row0 = (int32_t)(nb + 64 * t);
+            trsm.push_back(tt);
+          }
         }
       }
       lp.count = (int64_t)p.panels.size() - lp.start;
       if (lp.count) p.launches.push_back(lp);
+      if (!trsm.empty()) {
+        Launch lt{LAUNCH_TRSM, h, (int32_t)k, 0, (int64_t)p.panels.size(), (int64_t)trsm.size()};
+        p.panels.insert(p.panels.end(), trsm.begin(), trsm.end());
+        p.launches.push_back(lt);
+      }
       // UPDATE: trailing updates of step k, ancestor updates of finished supernodes
-      Launch lu{1, h, (int32_t)k, 0, (int64_t)p.updates.size(), 0};
+      Launch lu{LAUNCH_UPDATE, h, (int32_t)k, 0, (int64_t)p.updates.size(), 0};
       std::vector<int64_t> finished;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);

@@ -33,7 +33,13 @@ struct UpdTile {
 };
 static_assert(sizeof(UpdTile) == 56, "UpdTile layout");
 
-// One row tile of the fused POTRF + TRSM of a <=64-wide column block.
+// Work item of the cdiv of a <=64-wide column block (POTRF of the diagonal
+// tile, TRSM of the rows below it).
+//   mode 0: POTRF, write the diagonal tile, TRSM of rows [row0, row0+64)
+//           (a column block with at most 64 rows below its diagonal tile)
+//   mode 1: POTRF and write the diagonal tile only
+//   mode 2: TRSM of rows [row0, row0+64) against the factored diagonal tile
+//           (a later launch than the block's mode-1 item)
 struct PanelTile {
   int64_t diag;       // offset of the diagonal tile's top-left element
   int32_t ld;         // leading dimension of the panel
@@ -42,11 +48,18 @@ struct PanelTile {
   int32_t row0;       // first row handled here, relative to the diagonal tile
   int32_t col;        // factored-order index of the block's first column
   int32_t slot;       // status slot (matrix index in a batch)
+  int32_t mode;
+  int32_t pad;
 };
-static_assert(sizeof(PanelTile) == 32, "PanelTile layout");
+static_assert(sizeof(PanelTile) == 40, "PanelTile layout");
+
+// launch kinds, in execution order inside one (level, step)
+constexpr int32_t LAUNCH_POTRF = 0;
+constexpr int32_t LAUNCH_TRSM = 1;
+constexpr int32_t LAUNCH_UPDATE = 2;
 
 struct Launch {
-  int32_t kind;   // 0 panel, 1 update
+  int32_t kind;   // LAUNCH_*
   int32_t level;
   int32_t step;   // column block index inside the level
   int32_t pad;
@@ -73,6 +86,7 @@ struct Plan {
   int64_t n_atomic_tiles = 0;
   double flops_tiles = 0;  // flops the update tiles execute (full 64x64 MFMA work)
   double flops_upd_alg = 0;  // algorithmic flops of the update tiles (entries written x 2k)
+  double flops_panel = 0;    // flops of the POTRF + TRSM column blocks
 };
 
 struct Symbolic {

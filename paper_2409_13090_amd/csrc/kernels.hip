@@ -155,11 +155,12 @@ __global__ __launch_bounds__(64) void k_panel(const PanelTile* __restrict__ tile
 // arrangement, each owning a 32x32 quarter = 2x2 MFMA 16x16 blocks. K is
 // staged through LDS in chunks of 16 (column-major, as in factor storage).
 //
-// MFMA 16x16x4 operand layout (lane l): A[l%16][l/16], B[l/16][l%16], and
-// D[4*(l/16)+v][l%16] in accumulator element v. The kernel computes
-// D = Y * X^T so that a lane's accumulators are 4 consecutive target columns
-// of one target row: for fixed v, 16 lanes cover 16 consecutive rows of one
-// column, which makes the read-modify-write of column-major storage coalesced.
+// MFMA 16x16x4 operand layout (lane l): A[l%16][l/16] and B[l/16][l%16]. The
+// accumulator layout differs by type: for FP64 element v of lane l is
+// D[4*v + l/16][l%16]; for FP32 it is D[4*(l/16) + v][l%16]. The kernel computes
+// D = Y * X^T, so D's column index is the target row: for fixed v, 16 lanes
+// cover 16 consecutive rows of one target column, which keeps the
+// read-modify-write of column-major storage coalesced.
 template <typename T>
 struct Mfma;
 template <>
@@ -168,6 +169,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 template <>
 struct Mfma<float> {
@@ -175,6 +177,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 constexpr int KC = 16;  // K chunk staged per LDS buffer
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
     }
   }
   // epilogue: acc[bj][bi][v] is the update of target row wr+16*bi+(lane&15),
-  // target column wc+16*bj+4*(lane>>4)+v
+  // target column wc+16*bj+drow(lane,v)
   double* __restrict__ C = L + t.c;
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = wr + 16 * bi + (lane & 15);
-        const int col = wc + 16 * bj + 4 * (lane >> 4) + v;
+        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
         if (row < t.m && col < t.n && (!diag || row >= col)) {
           double* p = C + (int64_t)col * ldc + row;
           const double u = (double)acc[bj][bi][v];

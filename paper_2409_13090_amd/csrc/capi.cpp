@@ -443,8 +443,10 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE)
       launch_update(h->d.updates + l.start, l.count, L, h->precision, st);
+    else if (l.kind == LAUNCH_TRSM)
+      launch_trsm(h->d.panels + l.start, l.count, L, st);
     else
-      launch_panel(h->d.panels + l.start, l.count, L, h->status, st);
+      launch_potrf(h->d.panels + l.start, l.count, L, h->status, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
 }
@@ -744,8 +746,10 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, l.count, L, b->precision, st);
+    else if (l.kind == LAUNCH_TRSM)
+      launch_trsm(b->d_panels + l.start, l.count, L, st);
     else
-      launch_panel(b->d_panels + l.start, l.count, L, b->status, st);
+      launch_potrf(b->d_panels + l.start, l.count, L, b->status, st);
   }
 }
 

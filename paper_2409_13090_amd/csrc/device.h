@@ -23,7 +23,8 @@ void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, doub
                       hipStream_t st);
 void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
                           int64_t total, const int64_t* amap, double* L, hipStream_t st);
-void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st);
+void launch_potrf(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st);
+void launch_trsm(const PanelTile* tiles, int64_t count, double* L, hipStream_t st);
 void launch_update(const UpdTile* tiles, int64_t count, double* L, int precision,
                    hipStream_t st);
 void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,

@@ -4,9 +4,9 @@
 // Factor storage: Lnz(J) is m_J x w_J column-major (ld = m_J), one FP64 buffer.
 //  * k_fill / k_scatter_a  -- A-load: zero the factor storage, then place A's
 //    lower-triangle values (Alg. 5 input: Lnz(J) holds A_{*,J} on entry).
-//  * k_panel               -- cdiv of one <=64-wide column block (Alg. 5 line 4):
-//    the 64x64 diagonal tile is factored (POTRF) in registers of one
-//    wavefront, then every lane solves one row below it (TRSM).
+//  * k_potrf / k_trsm      -- cdiv of one <=64-wide column block (Alg. 5 line 4):
+//    POTRF of the 64x64 diagonal tile in the registers of one wavefront, then
+//    TRSM of the rows below it, one row per lane.
 //  * k_update<T>           -- C -= X * Y^T on a 64x64 tile of factor storage:
 //    the in-supernode trailing update and the SYRK/GEMM updates written
 //    directly into ancestors (Alg. 5 lines 11-16), on MFMA 16x16x4 (FP64, or
@@ -61,10 +61,20 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// cdiv of a column block: POTRF of the diagonal tile + TRSM of up to 64 rows.
-// One wavefront per tile. Both steps are left-looking (Crout order): lane i
-// keeps row i in registers and forms column c as a dot product with row c of
-// the factor, which every lane reads from LDS as a broadcast.
+// cdiv of a column block (Alg. 5 line 4) in two launches.
+//
+// k_potrf (one wavefront per block): blocked Cholesky of the <=64x64 diagonal
+// tile T in LDS with 16-column steps. Only the 16x16 base blocks pivot in
+// registers (lane = row, row c reaches every lane through readlane); the
+// block TRSM and the trailing SYRK of each step are 16x16x16 products on FP64
+// MFMA. The kernel also forms inv(L) of the tile -- inverses of the base blocks
+// by substitution, then a block forward substitution on MFMA -- and stores its
+// strict lower part transposed in the tile's unused strict upper triangle
+// (the diagonal of inv(L) is 1/L(i,i)). No floating-point working storage
+// beyond factor storage is used.
+//
+// k_trsm (four wavefronts per 64 rows below the tile): X = A * inv(L)^T as one
+// 64x64x64 MFMA product, written over A.
 
 __device__ __forceinline__ double lane_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -72,82 +82,186 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(64) void k_panel(const PanelTile* __restrict__ tiles,
+constexpr int TP = 65;  // LDS row pitch of a 64x64 tile (doubles)
+
+// D += A * B for 16x16 blocks in LDS. A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc].
+__device__ __forceinline__ v4d mma16(const double* A, int ar, int ac, const double* B, int br,
+                                     int bc, v4d acc, int lane) {
+#pragma unroll
+  for (int kq = 0; kq < 4; ++kq) {
+    const int k = kq * 4 + (lane >> 4);
+    const double a = A[(lane & 15) * ar + k * ac];
+    const double b = B[k * br + (lane & 15) * bc];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// element v of lane l of a 16x16 FP64 MFMA result is D(4v + l/16, l%16)
+__device__ __forceinline__ void st16(double* D, const v4d& acc, int lane, double scale) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) D[(4 * v + (lane >> 4)) * TP + (lane & 15)] = scale * acc[v];
+}
+
+__global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tiles,
                                               double* __restrict__ L, int* __restrict__ status) {
   const PanelTile t = tiles[blockIdx.x];
   const int lane = threadIdx.x;
-  __shared__ double sr[64][65];  // sr[i][k] = L(i, k) of the factored diagonal tile
   const int nb = t.nb;
-  const int64_t ld = t.ld;
+  const int ldi = t.ld;
   double* D = L + t.diag;
-  if (t.mode != 2) {
-    int bad = 0x7fffffff;
-    double row[64];
-#pragma unroll
+  __shared__ double T[64 * TP];   // the tile, row-major: T[i*TP + j]
+  __shared__ double I[64 * TP];   // inv(L), row-major
+  // stage the lower triangle (identity beyond nb); unconditional clamped loads
+  {
+    const int li = min(lane, nb - 1);
+#pragma unroll 8
     for (int j = 0; j < 64; ++j) {
-      double v = (j == lane) ? 1.0 : 0.0;  // identity beyond nb
-      if (lane < nb && j < nb && j <= lane) v = D[(int64_t)j * ld + lane];
-      row[j] = v;
+      const double v = D[min(j, nb - 1) * ldi + li];
+      T[lane * TP + j] = (lane < nb && j < nb && j <= lane) ? v : (j == lane ? 1.0 : 0.0);
+      I[lane * TP + j] = 0.0;
     }
+  }
+  __syncthreads();
+  int bad = 0x7fffffff;
+  for (int b = 0; b < 4; ++b) {
+    const int o = 16 * b;
+    // (1) base POTRF of T[o:o+16, o:o+16]: lanes 0..15 hold its rows
+    const int r = lane & 15;
+    double blk[16];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) {
-      double v = row[c];
+    for (int j = 0; j < 16; ++j) blk[j] = T[(o + r) * TP + o + j];
 #pragma unroll
-      for (int k = 0; k < c; ++k) v -= row[k] * sr[c][k];
+    for (int c = 0; c < 16; ++c) {
+      double v = blk[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) v -= blk[k] * lane_bcast(blk[k], c);
       double piv = lane_bcast(v, c);
       if (!(piv > 0.0)) {
-        if (c < nb) bad = min(bad, t.col + c + 1);
+        if (o + c < nb) bad = min(bad, t.col + o + c + 1);
         piv = 1.0;
       }
       const double d = sqrt(piv);
-      row[c] = (lane == c) ? d : (lane > c ? v / d : 0.0);
-      sr[lane][c] = row[c];
-      __syncthreads();
+      blk[c] = (r == c) ? d : (r > c ? v / d : 0.0);
     }
-    if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
-    if (lane < nb) {
+    // (2) base inverse: lane j < 16 forms column j of inv(L_bb) by substitution
+    double y[16];
 #pragma unroll
-      for (int j = 0; j < 64; ++j)
-        if (j < nb && j <= lane) D[(int64_t)j * ld + lane] = row[j];
+    for (int i = 0; i < 16; ++i) {
+      double v = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= lane_bcast(blk[k], i) * y[k];
+      y[i] = v / lane_bcast(blk[i], i);
     }
-    if (t.mode == 1) return;
-  } else {
-    // the diagonal tile was factored by this block's mode-1 item in an
-    // earlier launch: stage it (identity beyond nb)
-    for (int j = 0; j < 64; ++j) {
-      double v = (j == lane) ? 1.0 : 0.0;
-      if (lane < nb && j < nb && j <= lane) v = D[(int64_t)j * ld + lane];
-      sr[lane][j] = v;
+    if (lane < 16) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) T[(o + r) * TP + o + j] = blk[j];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = y[i];
     }
     __syncthreads();
-  }
-  // TRSM: x * L^T = a for row r, x_c = (a_c - sum_{k<c} x_k L(c,k)) / L(c,c).
-  // Loads are unconditional (clamped indices, 32-bit offsets from a uniform
-  // base) and every column ends with an LDS store into the unused pad column:
-  // both keep the register footprint at one 64-double row.
-  if (t.row0 >= t.nrows) return;
-  const bool live = t.row0 + lane < t.nrows;
-  const int rr = live ? t.row0 + lane : t.row0;
-  const int ldi = (int)ld;
-  double x[64];
+    // (3) panel below the base block: L(q, bb) = T(q, bb) * inv(L_bb)^T
+    for (int qb = b + 1; qb < 4; ++qb) {
+      v4d acc = {0, 0, 0, 0};
+      acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &I[o * TP + o], 1, TP, acc, lane);
+      __syncthreads();
+      st16(&T[(16 * qb) * TP + o], acc, lane, 1.0);
+    }
+    __syncthreads();
+    // (4) trailing SYRK: T(q, p) -= L(q, bb) * L(p, bb)^T for b < p <= q
+    for (int qb = b + 1; qb < 4; ++qb)
+      for (int pb = b + 1; pb <= qb; ++pb) {
+        v4d acc = {0, 0, 0, 0};
+        acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &T[(16 * pb) * TP + o], 1, TP, acc, lane);
 #pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    const double v = D[min(c, nb - 1) * ldi + rr];
-    x[c] = c < nb ? v : 0.0;
+        for (int v = 0; v < 4; ++v)
+          T[(16 * qb + 4 * v + (lane >> 4)) * TP + 16 * pb + (lane & 15)] -= acc[v];
+      }
+    __syncthreads();
   }
-#pragma unroll
-  for (int c = 0; c < 64; ++c) {
-    double v = x[c];
-#pragma unroll
-    for (int k = 0; k < c; ++k) v -= x[k] * sr[c][k];
-    x[c] = v / sr[c][c];
-    sr[lane][64] = x[c];
+  // (5) block forward substitution for the off-diagonal blocks of inv(L):
+  //     inv(L)(i,j) = -inv(L_ii) * sum_{j<=k<i} L(i,k) * inv(L)(k,j)
+  for (int jb = 0; jb < 3; ++jb)
+    for (int ib = jb + 1; ib < 4; ++ib) {
+      v4d s = {0, 0, 0, 0};
+      for (int kb = jb; kb < ib; ++kb)
+        s = mma16(&T[(16 * ib) * TP + 16 * kb], TP, 1, &I[(16 * kb) * TP + 16 * jb], TP, 1, s,
+                  lane);
+      __syncthreads();
+      // stage S into the (ib, jb) block of I, then multiply by -inv(L_ii)
+      st16(&I[(16 * ib) * TP + 16 * jb], s, lane, 1.0);
+      __syncthreads();
+      v4d u = {0, 0, 0, 0};
+      u = mma16(&I[(16 * ib) * TP + 16 * ib], TP, 1, &I[(16 * ib) * TP + 16 * jb], TP, 1, u, lane);
+      __syncthreads();
+      st16(&I[(16 * ib) * TP + 16 * jb], u, lane, -1.0);
+      __syncthreads();
+    }
+  if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
+  // (6) L to the lower triangle, strict lower of inv(L) transposed to the
+  //     strict upper triangle (only inside the nb x nb tile)
+  if (lane < nb) {
+    for (int j = 0; j < nb; ++j) {
+      if (j <= lane) D[j * ldi + lane] = T[lane * TP + j];
+      else D[j * ldi + lane] = I[j * TP + lane];
+    }
   }
-  if (live) {
-#pragma unroll
-    for (int j = 0; j < 64; ++j)
-      if (j < nb) D[j * ldi + rr] = x[j];
+}
+
+// X = A * inv(L)^T for up to 64 rows below the diagonal tile, in place.
+__global__ __launch_bounds__(256) void k_trsm(const PanelTile* __restrict__ tiles,
+                                              double* __restrict__ L) {
+  const PanelTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = t.nb;
+  const int ldi = t.ld;
+  const int nr = min(64, t.nrows - t.row0);
+  if (nr <= 0) return;
+  double* D = L + t.diag;
+  __shared__ double sA[64][64];   // sA[k][r] = A(row0 + r, k)
+  __shared__ double sV[64][64];   // sV[k][j] = inv(L)(j, k)
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int k = e >> 6, r = e & 63;  // consecutive threads: consecutive rows
+    const double a = D[min(k, nb - 1) * ldi + t.row0 + min(r, nr - 1)];
+    sA[k][r] = (k < nb && r < nr) ? a : 0.0;
   }
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int j = e >> 6, k = e & 63;  // inv(L)(j,k) for j > k sits at D[j*ld + k]
+    const int jj = min(j, nb - 1), kk = min(k, nb - 1);
+    const double u = D[jj * ldi + kk];
+    double v = 0.0;
+    if (j < nb && k < nb) v = (j > k) ? u : (j == k ? 1.0 / u : 0.0);
+    sV[k][j] = v;
+  }
+  __syncthreads();
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+#pragma unroll 4
+  for (int kq = 0; kq < 16; ++kq) {
+    const int k = kq * 4 + (lane >> 4);
+    const double a0 = sV[k][wc + (lane & 15)], a1 = sV[k][wc + 16 + (lane & 15)];
+    const double b0 = sA[k][wr + (lane & 15)], b1 = sA[k][wr + 16 + (lane & 15)];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  // D = V * A^T: element v of lane l of block (bj, bi) is X(row wr+16bi+l%16,
+  // column wc+16bj+4v+l/16)
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + 4 * v + (lane >> 4);
+        if (row < nr && col < nb) D[col * ldi + t.row0 + row] = acc[bj][bi][v];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -284,92 +398,132 @@ static_assert(sizeof(SnMeta) == 24, "SnMeta layout");
 constexpr int SB = 64;  // columns per in-LDS triangular chunk of the solves
 constexpr int MAXRHS = SOLVE_MAXRHS;
 
+// Stage the nb x nb diagonal chunk of L at (c0, c0) into Ld (identity beyond nb).
+__device__ __forceinline__ void stage_chunk(double (*Ld)[SB + 1], const double* Lj, int64_t ld,
+                                            int c0, int nb, int tid) {
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int col = e / SB, row = e % SB;
+    double v = (row == col) ? 1.0 : 0.0;
+    if (row < nb && col < nb && row >= col) v = Lj[(int64_t)(c0 + col) * ld + c0 + row];
+    Ld[row][col] = v;
+  }
+}
+
+// Forward solve L y = b for the supernodes of one level, one workgroup each.
+// Per 64-column chunk: triangle in LDS (one wavefront per right-hand side,
+// lane = row, pivots broadcast with readlane), then a coalesced GEMV for every
+// row below the chunk (own rows plainly, ancestor rows with atomics).
 __global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ sns,
                                              const SnMeta* __restrict__ meta,
                                              const int32_t* __restrict__ gl,
                                              const double* __restrict__ L,
                                              double* __restrict__ y, int nrhs, int64_t ldy) {
   const SnMeta s = meta[sns[blockIdx.x]];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* Lj = L + s.off;
   const int64_t ld = s.m;
   const int32_t* g = gl + s.gl;
+  __shared__ double Ld[SB][SB + 1];
   __shared__ double xs[MAXRHS][SB];
   for (int c0 = 0; c0 < s.w; c0 += SB) {
     const int nb = min(SB, s.w - c0);
-    // load the chunk of y into LDS
-    for (int e = tid; e < nb * nrhs; e += 256) {
-      const int c = e % nb, r = e / nb;
-      xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c];
+    stage_chunk(Ld, Lj, ld, c0, nb, tid);
+    for (int e = tid; e < SB * nrhs; e += 256) {
+      const int c = e % SB, r = e / SB;
+      xs[r][c] = c < nb ? y[(int64_t)r * ldy + s.f + c0 + c] : 0.0;
     }
     __syncthreads();
-    // in-chunk lower solve: one thread per right-hand side
-    if (tid < nrhs) {
+    for (int r = wave; r < nrhs; r += 4) {
+      double yj = xs[r][lane];
       for (int c = 0; c < nb; ++c) {
-        const double x = xs[tid][c] / Lj[(int64_t)(c0 + c) * ld + c0 + c];
-        xs[tid][c] = x;
-        for (int q = c + 1; q < nb; ++q) xs[tid][q] -= Lj[(int64_t)(c0 + c) * ld + c0 + q] * x;
+        const double xc = lane_bcast(yj, c) / Ld[c][c];
+        if (lane == c) yj = xc;
+        if (lane > c) yj -= Ld[lane][c] * xc;
       }
+      xs[r][lane] = yj;
     }
     __syncthreads();
     for (int e = tid; e < nb * nrhs; e += 256) {
       const int c = e % nb, r = e / nb;
       y[(int64_t)r * ldy + s.f + c0 + c] = xs[r][c];
     }
-    // rows below the chunk: own rows of the diagonal block, then ancestors
-    const int below = s.m - c0 - nb;
-    for (int e = tid; e < below * nrhs; e += 256) {
-      const int q = c0 + nb + e % below, r = e / below;
-      double acc = 0.0;
-      for (int c = 0; c < nb; ++c) acc += Lj[(int64_t)(c0 + c) * ld + q] * xs[r][c];
-      if (q < s.w)
-        y[(int64_t)r * ldy + s.f + q] -= acc;
-      else
-        atomicAdd(&y[(int64_t)r * ldy + g[q]], -acc);
+    const int q0 = c0 + nb;
+    for (int q = q0 + tid; q < s.m; q += 256) {
+      double acc[MAXRHS];
+#pragma unroll
+      for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double l = Lj[(int64_t)(c0 + c) * ld + q];
+#pragma unroll
+        for (int r = 0; r < MAXRHS; ++r)
+          if (r < nrhs) acc[r] += l * xs[r][c];
+      }
+      const int gq = g[q];
+#pragma unroll
+      for (int r = 0; r < MAXRHS; ++r) {
+        if (r < nrhs) {
+          if (q < s.w)
+            y[(int64_t)r * ldy + gq] -= acc[r];
+          else
+            atomicAdd(&y[(int64_t)r * ldy + gq], -acc[r]);
+        }
+      }
     }
     __syncthreads();
   }
 }
 
+// Backward solve L^T x = y, levels from the root down, one workgroup per
+// supernode. Chunks from the last: every column of the chunk first subtracts
+// its dot product with the already final x of all rows below the chunk (own
+// rows and ancestors alike, both read through glbind), one wavefront per
+// column with a wave reduction; then the chunk's triangle is solved in LDS.
 __global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ sns,
                                              const SnMeta* __restrict__ meta,
                                              const int32_t* __restrict__ gl,
                                              const double* __restrict__ L,
                                              double* __restrict__ y, int nrhs, int64_t ldy) {
   const SnMeta s = meta[sns[blockIdx.x]];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* Lj = L + s.off;
   const int64_t ld = s.m;
   const int32_t* g = gl + s.gl;
+  __shared__ double Ld[SB][SB + 1];
   __shared__ double xs[MAXRHS][SB];
-  // contributions of the rows below the diagonal block (ancestors are final)
-  const int below = s.m - s.w;
-  for (int e = tid; e < s.w * nrhs; e += 256) {
-    const int c = e % s.w, r = e / s.w;
-    double acc = 0.0;
-    for (int q = 0; q < below; ++q)
-      acc += Lj[(int64_t)c * ld + s.w + q] * y[(int64_t)r * ldy + g[s.w + q]];
-    y[(int64_t)r * ldy + s.f + c] -= acc;
-  }
-  __syncthreads();
   const int nchunks = (s.w + SB - 1) / SB;
   for (int ch = nchunks - 1; ch >= 0; --ch) {
-    const int c0 = ch * SB, nb = min(SB, s.w - c0), c1 = c0 + nb;
-    // contributions of the already solved columns [c1, w) of the diagonal block
-    for (int e = tid; e < nb * nrhs; e += 256) {
-      const int c = e % nb, r = e / nb;
-      double acc = 0.0;
-      for (int q = c1; q < s.w; ++q)
-        acc += Lj[(int64_t)(c0 + c) * ld + q] * y[(int64_t)r * ldy + s.f + q];
-      xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c] - acc;
+    const int c0 = ch * SB, nb = min(SB, s.w - c0), q0 = c0 + nb;
+    stage_chunk(Ld, Lj, ld, c0, nb, tid);
+    for (int c = wave; c < nb; c += 4) {
+      double acc[MAXRHS];
+#pragma unroll
+      for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
+      const double* col = Lj + (int64_t)(c0 + c) * ld;
+      for (int q = q0 + lane; q < s.m; q += 64) {
+        const double l = col[q];
+        const int gq = g[q];
+#pragma unroll
+        for (int r = 0; r < MAXRHS; ++r)
+          if (r < nrhs) acc[r] += l * y[(int64_t)r * ldy + gq];
+      }
+#pragma unroll
+      for (int r = 0; r < MAXRHS; ++r) {
+        if (r < nrhs) {
+          double v = acc[r];
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+          if (lane == 0) xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c] - v;
+        }
+      }
     }
     __syncthreads();
-    if (tid < nrhs) {
+    for (int r = wave; r < nrhs; r += 4) {
+      double yj = lane < nb ? xs[r][lane] : 0.0;
       for (int c = nb - 1; c >= 0; --c) {
-        double v = xs[tid][c];
-        for (int q = c + 1; q < nb; ++q) v -= Lj[(int64_t)(c0 + c) * ld + c0 + q] * xs[tid][q];
-        xs[tid][c] = v / Lj[(int64_t)(c0 + c) * ld + c0 + c];
+        const double xc = lane_bcast(yj, c) / Ld[c][c];
+        if (lane == c) yj = xc;
+        if (lane < c) yj -= Ld[c][lane] * xc;
       }
+      if (lane < nb) xs[r][lane] = yj;
     }
     __syncthreads();
     for (int e = tid; e < nb * nrhs; e += 256) {
@@ -478,9 +632,13 @@ void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int
   hipLaunchKernelGGL(k_scatter_batch, dim3(grid_for(total, 256, INT32_MAX)), dim3(256), 0, st,
                      vals, nnz_ptr, count, total, amap, L);
 }
-void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st) {
+void launch_potrf(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_panel, dim3((unsigned)count), dim3(64), 0, st, tiles, L, status);
+  hipLaunchKernelGGL(k_potrf, dim3((unsigned)count), dim3(64), 0, st, tiles, L, status);
+}
+void launch_trsm(const PanelTile* tiles, int64_t count, double* L, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_trsm, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, int64_t count, double* L, int precision,
                    hipStream_t st) {

@@ -212,7 +212,7 @@ int build_plan(Symbolic& s, std::string& err) {
         // counts nb..1) plus TRSM of the rows below (nb^2 per row)
         for (int64_t t = 0; t < nb; ++t) p.flops_panel += (double)(nb - t) * (double)(nb - t);
         p.flops_panel += (double)below * (double)nb * (double)nb;
-        int64_t nt = (below + 63) / 64;
+        int64_t nt = (below + 63) / 64;  // TRSM row tiles of 64 rows
         PanelTile pt;
         pt.diag = p.off[J] + c0 * m + c0;
         pt.ld = (int32_t)m;
@@ -222,9 +222,9 @@ int build_plan(Symbolic& s, std::string& err) {
         pt.col = (int32_t)(s.sn_ptr[J] + c0);
         pt.slot = 0;
         pt.pad = 0;
-        pt.mode = nt <= 1 ? 0 : 1;
+        pt.mode = 1;
         p.panels.push_back(pt);
-        if (nt > 1) {
+        if (nt > 0) {
           for (int64_t t = 0; t < nt; ++t) {
             PanelTile tt = pt;
             tt.mode = 2;

@@ -33,13 +33,10 @@ struct UpdTile {
 };
 static_assert(sizeof(UpdTile) == 56, "UpdTile layout");
 
-// Work item of the cdiv of a <=64-wide column block (POTRF of the diagonal
-// tile, TRSM of the rows below it).
-//   mode 0: POTRF, write the diagonal tile, TRSM of rows [row0, row0+64)
-//           (a column block with at most 64 rows below its diagonal tile)
-//   mode 1: POTRF and write the diagonal tile only
-//   mode 2: TRSM of rows [row0, row0+64) against the factored diagonal tile
-//           (a later launch than the block's mode-1 item)
+// Work item of the cdiv of a <=64-wide column block.
+//   mode 1: POTRF of the diagonal tile, written back in place
+//   mode 2: TRSM of rows [row0, row0+64) below the tile against the factored
+//           tile (a later launch than the block's mode-1 item)
 struct PanelTile {
   int64_t diag;       // offset of the diagonal tile's top-left element
   int32_t ld;         // leading dimension of the panel

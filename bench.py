@@ -67,7 +67,10 @@ def main():
     ap.add_argument("--side", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the factor as a HIP graph")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the factor's kernels one by one instead of replaying a HIP graph")
+    ap.add_argument("--prof-reps", type=int, default=3,
+                    help="factorizations timed launch by launch for the roofline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -94,13 +97,12 @@ def main():
     B = torch.from_numpy(np.asfortranarray(A.rhs)).to(dev).T.contiguous().T
     X = torch.empty_like(B).T.contiguous().T
     num = rlb.Numeric(sym, rlb.RLB_PREC_FP64)
-    if args.graph:
-        num.set_graph_mode(True)
+    graph = not args.no_graph
+    num.set_graph_mode(graph)
     ws = torch.empty(info["factor_bytes"] // 8 + 1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(profile):
-        num.set_profiling(profile)
+    def step():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -111,22 +113,31 @@ def main():
         X.copy_(B)
         num.solve(X)
         be = num.backward_error(B, X)
-        return e0, e1, be, (num.last_profile() if profile else None)
+        return e0, e1, be
 
     for _ in range(args.warmup):
-        step(True)
+        step()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    recs = [step(True) for _ in range(args.steps)]
+    recs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    fac_ms = [a.elapsed_time(b) for a, b, _, _ in recs]
+    fac_ms = [a.elapsed_time(b) for a, b, _ in recs]
     be = np.max([r[2] for r in recs], axis=0)
-    upd_ms = [r[3]["update_ms"] for r in recs]
-    n_upd = recs[0][3]["n_update"]
-    pan_ms = [r[3]["panel_ms"] for r in recs]
     t_fac = statistics.mean(fac_ms) / 1e3
     gflops = F / t_fac / 1e9
+
+    # per-launch HIP events on the factor's stream (eager launches of the same
+    # kernels) for the roofline of the dominant kernel
+    num.set_profiling(True)
+    profs = []
+    for _ in range(args.prof_reps):
+        num.factor(vals, ws, check=True)
+        profs.append(num.last_profile())
+    num.set_profiling(False)
+    upd_ms = [p["update_ms"] for p in profs]
+    pan_ms = [p["panel_ms"] for p in profs]
+    n_upd = profs[0]["n_update"]
 
     # dominant kernel: the SYRK/GEMM update tiles (FP64 MFMA)
     upd_s = statistics.mean(upd_ms) / 1e3
@@ -154,12 +165,13 @@ def main():
         "config": {"workload": f"lap3d7_{args.side}: 3D 7-point Laplacian {args.side}^3 "
                                f"(n={A.n}), weights 10^U(-2,2), shift 1e-6*max diag, "
                                "nested dissection + reordering within supernodes, 4 RHS",
-                   "n": A.n, "nrhs": int(A.rhs.shape[1]), "graph": bool(args.graph)},
+                   "n": A.n, "nrhs": int(A.rhs.shape[1]), "graph": graph},
         "pct_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS * 100, 3),
         "factor_ms": round(t_fac * 1e3, 3),
         "factor_ms_min": round(min(fac_ms), 3),
         "panel_ms": round(statistics.mean(pan_ms), 3),
         "update_ms": round(statistics.mean(upd_ms), 3),
+        "n_panel_launches": profs[0]["n_panel"],
         "flops_exact": F,
         "backward_error": [float(f"{v:.3e}") for v in be],
         "analyze_s": round(t_analyze, 3),
@@ -171,6 +183,7 @@ def main():
 
     if not args.no_mixed:
         num32 = rlb.Numeric(sym, rlb.RLB_PREC_FP32_UPDATES)
+        num32.set_graph_mode(graph)
         ws32 = torch.empty_like(ws)
         ms32, its, tts, be32 = [], [], [], []
         for rep in range(3):
@@ -193,7 +206,6 @@ def main():
         # FP64 time to solution for comparison: factor + solve + residual check
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        num.set_profiling(False)
         num.factor(vals, ws)
         X.copy_(B)
         num.solve(X)

@@ -115,10 +115,12 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
   // stage the lower triangle (identity beyond nb); unconditional clamped loads
   {
     const int li = min(lane, nb - 1);
-#pragma unroll 8
+    double v[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) v[j] = D[min(j, nb - 1) * ldi + li];  // all loads in flight
+#pragma unroll
     for (int j = 0; j < 64; ++j) {
-      const double v = D[min(j, nb - 1) * ldi + li];
-      T[lane * TP + j] = (lane < nb && j < nb && j <= lane) ? v : (j == lane ? 1.0 : 0.0);
+      T[lane * TP + j] = (lane < nb && j < nb && j <= lane) ? v[j] : (j == lane ? 1.0 : 0.0);
       I[lane * TP + j] = 0.0;
     }
   }
@@ -452,11 +454,20 @@ __global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ sns,
       double acc[MAXRHS];
 #pragma unroll
       for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double l = Lj[(int64_t)(c0 + c) * ld + q];
+      const double* lq = Lj + q;
+      for (int cb = 0; cb < nb; cb += 16) {
+        double l[16];
 #pragma unroll
-        for (int r = 0; r < MAXRHS; ++r)
-          if (r < nrhs) acc[r] += l * xs[r][c];
+        for (int u = 0; u < 16; ++u)  // 16 independent loads in flight
+          l[u] = lq[(int64_t)(c0 + min(cb + u, nb - 1)) * ld];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          if (cb + u < nb) {
+#pragma unroll
+            for (int r = 0; r < MAXRHS; ++r)
+              if (r < nrhs) acc[r] += l[u] * xs[r][cb + u];
+          }
+        }
       }
       const int gq = g[q];
 #pragma unroll
@@ -499,12 +510,25 @@ __global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ sns,
 #pragma unroll
       for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
       const double* col = Lj + (int64_t)(c0 + c) * ld;
-      for (int q = q0 + lane; q < s.m; q += 64) {
-        const double l = col[q];
-        const int gq = g[q];
+      for (int q = q0 + lane; q < s.m; q += 256) {  // four rows per lane per pass
+        double l[4];
+        int gq[4];
 #pragma unroll
-        for (int r = 0; r < MAXRHS; ++r)
-          if (r < nrhs) acc[r] += l * y[(int64_t)r * ldy + gq];
+        for (int u = 0; u < 4; ++u) {
+          const int qq = min(q + 64 * u, s.m - 1);
+          l[u] = (q + 64 * u < s.m) ? col[qq] : 0.0;
+          gq[u] = g[qq];
+        }
+#pragma unroll
+        for (int r = 0; r < MAXRHS; ++r) {
+          if (r < nrhs) {
+            double yv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yv[u] = y[(int64_t)r * ldy + gq[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[r] += l[u] * yv[u];
+          }
+        }
       }
 #pragma unroll
       for (int r = 0; r < MAXRHS; ++r) {

@@ -119,47 +119,63 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
 #pragma unroll
     for (int j = 0; j < 64; ++j) v[j] = D[min(j, nb - 1) * ldi + li];  // all loads in flight
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
+    for (int j = 0; j < 64; ++j)
       T[lane * TP + j] = (lane < nb && j < nb && j <= lane) ? v[j] : (j == lane ? 1.0 : 0.0);
-      I[lane * TP + j] = 0.0;
-    }
   }
   __syncthreads();
   int bad = 0x7fffffff;
   for (int b = 0; b < 4; ++b) {
     const int o = 16 * b;
     // (1) base POTRF of T[o:o+16, o:o+16]: lanes 0..15 hold its rows
+    // (lanes 16..63 mirror them). Left-looking, four partial sums per dot
+    // product; the column below each pivot is scaled by 1/L(c,c) from one rsq
+    // with two Newton steps, while L(c,c) itself is the correctly rounded sqrt.
     const int r = lane & 15;
-    double blk[16];
+    double blk[16], rinv[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) blk[j] = T[(o + r) * TP + o + j];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      double v = blk[c];
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-      for (int k = 0; k < c; ++k) v -= blk[k] * lane_bcast(blk[k], c);
+      for (int k = 0; k + 3 < c; k += 4) {
+        p0 += blk[k] * lane_bcast(blk[k], c);
+        p1 += blk[k + 1] * lane_bcast(blk[k + 1], c);
+        p2 += blk[k + 2] * lane_bcast(blk[k + 2], c);
+        p3 += blk[k + 3] * lane_bcast(blk[k + 3], c);
+      }
+#pragma unroll
+      for (int k = c & ~3; k < c; ++k) p0 += blk[k] * lane_bcast(blk[k], c);
+      const double v = blk[c] - ((p0 + p1) + (p2 + p3));
       double piv = lane_bcast(v, c);
       if (!(piv > 0.0)) {
         if (o + c < nb) bad = min(bad, t.col + o + c + 1);
         piv = 1.0;
       }
-      const double d = sqrt(piv);
-      blk[c] = (r == c) ? d : (r > c ? v / d : 0.0);
+      double y = __builtin_amdgcn_rsq(piv);
+      y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+      y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+      rinv[c] = y;
+      blk[c] = (r == c) ? sqrt(piv) : (r > c ? v * y : 0.0);
     }
     // (2) base inverse: lane j < 16 forms column j of inv(L_bb) by substitution
-    double y[16];
+    double yv[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      double v = (i == r) ? 1.0 : 0.0;
+      double q0 = (i == r) ? 1.0 : 0.0, q1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < i; ++k) v -= lane_bcast(blk[k], i) * y[k];
-      y[i] = v / lane_bcast(blk[i], i);
+      for (int k = 0; k + 1 < i; k += 2) {
+        q0 -= lane_bcast(blk[k], i) * yv[k];
+        q1 -= lane_bcast(blk[k + 1], i) * yv[k + 1];
+      }
+      if (i & 1) q0 -= lane_bcast(blk[i - 1], i) * yv[i - 1];
+      yv[i] = (q0 + q1) * rinv[i];
     }
     if (lane < 16) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) T[(o + r) * TP + o + j] = blk[j];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = y[i];
+      for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = yv[i];
     }
     __syncthreads();
     // (3) panel below the base block: L(q, bb) = T(q, bb) * inv(L_bb)^T
@@ -202,10 +218,14 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
   if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
   // (6) L to the lower triangle, strict lower of inv(L) transposed to the
   //     strict upper triangle (only inside the nb x nb tile)
-  if (lane < nb) {
-    for (int j = 0; j < nb; ++j) {
-      if (j <= lane) D[j * ldi + lane] = T[lane * TP + j];
-      else D[j * ldi + lane] = I[j * TP + lane];
+  {
+    double w[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) w[j] = (j <= lane) ? T[lane * TP + j] : I[j * TP + lane];
+    if (lane < nb) {
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        if (j < nb) D[j * ldi + lane] = w[j];
     }
   }
 }

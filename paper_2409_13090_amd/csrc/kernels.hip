@@ -124,7 +124,8 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
   }
   __syncthreads();
   int bad = 0x7fffffff;
-  for (int b = 0; b < 4; ++b) {
+  const int nbb = (nb + 15) >> 4;  // base blocks that hold columns of the tile
+  for (int b = 0; b < nbb; ++b) {
     const int o = 16 * b;
     // (1) base POTRF of T[o:o+16, o:o+16]: lanes 0..15 hold its rows
     // (lanes 16..63 mirror them). Left-looking, four partial sums per dot
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
     }
     __syncthreads();
     // (3) panel below the base block: L(q, bb) = T(q, bb) * inv(L_bb)^T
-    for (int qb = b + 1; qb < 4; ++qb) {
+    for (int qb = b + 1; qb < nbb; ++qb) {
       v4d acc = {0, 0, 0, 0};
       acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &I[o * TP + o], 1, TP, acc, lane);
       __syncthreads();
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
     }
     __syncthreads();
     // (4) trailing SYRK: T(q, p) -= L(q, bb) * L(p, bb)^T for b < p <= q
-    for (int qb = b + 1; qb < 4; ++qb)
+    for (int qb = b + 1; qb < nbb; ++qb)
       for (int pb = b + 1; pb <= qb; ++pb) {
         v4d acc = {0, 0, 0, 0};
         acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &T[(16 * pb) * TP + o], 1, TP, acc, lane);
@@ -199,8 +200,8 @@ __global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tile
   }
   // (5) block forward substitution for the off-diagonal blocks of inv(L):
   //     inv(L)(i,j) = -inv(L_ii) * sum_{j<=k<i} L(i,k) * inv(L)(k,j)
-  for (int jb = 0; jb < 3; ++jb)
-    for (int ib = jb + 1; ib < 4; ++ib) {
+  for (int jb = 0; jb + 1 < nbb; ++jb)
+    for (int ib = jb + 1; ib < nbb; ++ib) {
       v4d s = {0, 0, 0, 0};
       for (int kb = jb; kb < ib; ++kb)
         s = mma16(&T[(16 * ib) * TP + 16 * kb], TP, 1, &I[(16 * kb) * TP + 16 * jb], TP, 1, s,
@@ -470,33 +471,28 @@ __global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ sns,
       y[(int64_t)r * ldy + s.f + c0 + c] = xs[r][c];
     }
     const int q0 = c0 + nb;
-    for (int q = q0 + tid; q < s.m; q += 256) {
-      double acc[MAXRHS];
+    for (int q = q0 + tid; q < s.m + 255; q += 256) {
+      // one row per thread; all 64 column loads in flight (coalesced across
+      // threads), clamped to valid slots
+      const int qq = min(q, s.m - 1);
+      const double* lq = Lj + qq;
+      double l[SB];
 #pragma unroll
-      for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
-      const double* lq = Lj + q;
-      for (int cb = 0; cb < nb; cb += 16) {
-        double l[16];
+      for (int c = 0; c < SB; ++c) l[c] = lq[(int64_t)(c0 + min(c, nb - 1)) * ld];
+      if (q < s.m) {
+        const int gq = g[q];
+        for (int r = 0; r < nrhs; ++r) {
+          double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u)  // 16 independent loads in flight
-          l[u] = lq[(int64_t)(c0 + min(cb + u, nb - 1)) * ld];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          if (cb + u < nb) {
-#pragma unroll
-            for (int r = 0; r < MAXRHS; ++r)
-              if (r < nrhs) acc[r] += l[u] * xs[r][cb + u];
+          for (int c = 0; c < SB; c += 2) {
+            a0 += l[c] * xs[r][c];         // xs is 0 beyond nb
+            a1 += l[c + 1] * xs[r][c + 1];
           }
-        }
-      }
-      const int gq = g[q];
-#pragma unroll
-      for (int r = 0; r < MAXRHS; ++r) {
-        if (r < nrhs) {
+          const double acc = a0 + a1;
           if (q < s.w)
-            y[(int64_t)r * ldy + gq] -= acc[r];
+            y[(int64_t)r * ldy + gq] -= acc;
           else
-            atomicAdd(&y[(int64_t)r * ldy + gq], -acc[r]);
+            atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
         }
       }
     }
@@ -521,43 +517,50 @@ __global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ sns,
   const int32_t* g = gl + s.gl;
   __shared__ double Ld[SB][SB + 1];
   __shared__ double xs[MAXRHS][SB];
+  __shared__ double part[4][MAXRHS][SB];
   const int nchunks = (s.w + SB - 1) / SB;
   for (int ch = nchunks - 1; ch >= 0; --ch) {
     const int c0 = ch * SB, nb = min(SB, s.w - c0), q0 = c0 + nb;
     stage_chunk(Ld, Lj, ld, c0, nb, tid);
-    for (int c = wave; c < nb; c += 4) {
+    // column dot products over the rows below the chunk: lane = column, each
+    // wave walks a quarter of the rows (8 rows in flight per iteration); the
+    // four partial sums meet in LDS
+    {
+      const int c = min(lane, nb - 1);
+      const double* col = Lj + (int64_t)(c0 + c) * ld;
+      const int rows = s.m - q0;
+      const int per = (rows + 3) / 4;
+      const int qa = q0 + wave * per, qe = min(s.m, qa + per);
       double acc[MAXRHS];
 #pragma unroll
       for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
-      const double* col = Lj + (int64_t)(c0 + c) * ld;
-      for (int q = q0 + lane; q < s.m; q += 256) {  // four rows per lane per pass
-        double l[4];
-        int gq[4];
+      for (int q = qa; q < qe; q += 8) {
+        double l[8];
+        int gq[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int qq = min(q + 64 * u, s.m - 1);
-          l[u] = (q + 64 * u < s.m) ? col[qq] : 0.0;
+        for (int u = 0; u < 8; ++u) {
+          const int qq = min(q + u, qe - 1);
+          l[u] = (q + u < qe) ? col[qq] : 0.0;
           gq[u] = g[qq];
         }
 #pragma unroll
         for (int r = 0; r < MAXRHS; ++r) {
           if (r < nrhs) {
-            double yv[4];
+            double yv[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) yv[u] = y[(int64_t)r * ldy + gq[u]];
+            for (int u = 0; u < 8; ++u) yv[u] = y[(int64_t)r * ldy + gq[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[r] += l[u] * yv[u];
+            for (int u = 0; u < 8; ++u) acc[r] += l[u] * yv[u];
           }
         }
       }
-#pragma unroll
-      for (int r = 0; r < MAXRHS; ++r) {
-        if (r < nrhs) {
-          double v = acc[r];
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-          if (lane == 0) xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c] - v;
-        }
-      }
+      for (int r = 0; r < nrhs; ++r) part[wave][r][lane] = acc[r];
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nrhs; e += 256) {
+      const int c = e % nb, r = e / nb;
+      const double d = (part[0][r][c] + part[1][r][c]) + (part[2][r][c] + part[3][r][c]);
+      xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c] - d;
     }
     __syncthreads();
     for (int r = wave; r < nrhs; r += 4) {

@@ -231,7 +231,7 @@ def main():
         "backward_error": [float(f"{v:.3e}") for v in be],
         "analyze_s": round(t_analyze, 3),
         "plan": {k: info[k] for k in ("n_supernodes", "n_levels", "n_launches",
-                                      "n_update_tiles", "n_panel_tiles", "n_atomic_tiles",
+                                      "n_update_tiles", "n_panel_tiles", "n_merged_tiles", "n_split_tiles",
                                       "nnz_stored")},
         "roofline": roof,
     }

@@ -81,10 +81,14 @@ typedef struct rlb_info {
   int64_t n_calls;       /* SYRK + GEMM block updates of Alg. 5 */
   int64_t merge_added, merge_base; /* merging: added stored entries, fundamental entries */
   int64_t factor_bytes;  /* device workspace needed by rlb_factor (FP64 factor storage) */
-  int64_t n_panel_tiles, n_update_tiles, n_atomic_tiles, n_launches;
-  double flops_tiles;    /* flops the update tiles execute (full MFMA tiles) */
-  double flops_upd_alg;  /* algorithmic flops of the update tiles: 2 * inner dimension *
-                            entries written, summed over tiles */
+  int64_t n_panel_tiles;  /* workgroups of all panel launches */
+  int64_t n_update_tiles; /* target tiles of all update launches */
+  int64_t n_merged_tiles; /* target tiles that sum contributions of several supernodes */
+  int64_t n_split_tiles;  /* update workgroups of tiles cut for load balance (atomic adds) */
+  int64_t n_launches;
+  double flops_tiles;    /* flops the update kernels execute (16x16 MFMA blocks touched) */
+  double flops_upd_alg;  /* algorithmic flops of the updates: 2 * inner dimension *
+                            entries written, summed over contributions */
   double flops_panel;    /* flops of the panel (POTRF + TRSM) steps */
 } rlb_info;
 
@@ -112,12 +116,14 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* out);
  * which: "perm", "perm_nd", "perm_post", "etree_post", "etree", "fund_ptr",
  * "sn_ptr", "sn_parent", "gl_ptr", "gl", "rel_ptr", "rel", "blk_ptr", "blk",
  * "rbp_ptr", "rbp_anc", "rbv_ptr", "rbv", "colcount", "level", "off", "amap",
- * and the device work lists "update_tiles" (10 values per tile: target,
- * X, Y offsets, ldc, lds, m, n, k, flags, source supernode), "panel_tiles"
- * (8 per tile: diagonal offset, ld, nb, nrows, row0, column, status slot,
- * mode 0 POTRF+TRSM / 1 POTRF / 2 TRSM) and "launches" (5 per launch: kind
- * 0 POTRF / 1 TRSM / 2 update, level, step, first tile, tile count). If out is NULL only *len is set. All arrays are returned as
- * int64. */
+ * and the device work lists "update_tiles" (7 values per target tile:
+ * target offset, ldc, m, n, flags, first contribution, contribution count),
+ * "update_segs" (9 per contribution: X and Y source offsets, source ld, k,
+ * tile rows [ra, rb), tile columns [ca, cb), source supernode),
+ * "panel_tiles" (9 per tile: diagonal offset, ld, nb, nrows, row0, column,
+ * status slot, group counter, group size) and "launches" (5 per launch:
+ * kind 0 panel (POTRF+TRSM) / 1 update, level, step, first tile, tile
+ * count). If out is NULL only *len is set. All arrays are returned as int64. */
 rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out, int64_t* len);
 
 void rlb_symbolic_free(rlb_symbolic sym);

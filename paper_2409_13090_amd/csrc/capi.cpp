@@ -52,6 +52,7 @@ void dfree(T*& p) {
 struct DevPlan {
   PanelTile* panels = nullptr;
   UpdTile* updates = nullptr;
+  UpdSeg* segs = nullptr;
   int64_t* amap = nullptr;
   SnMeta* meta = nullptr;
   int32_t* gl = nullptr;
@@ -63,6 +64,7 @@ struct DevPlan {
   void release() {
     dfree(panels);
     dfree(updates);
+    dfree(segs);
     dfree(amap);
     dfree(meta);
     dfree(gl);
@@ -198,6 +200,8 @@ struct rlb_numeric_s {
   int device = 0;
   DevPlan d;
   int* status = nullptr;
+  int* counters = nullptr;  // panel group counters (zero between launches)
+  int ncounters = 0;
   double* L = nullptr;
   bool factored = false;
   hipStream_t stream = nullptr;
@@ -221,6 +225,7 @@ struct rlb_numeric_s {
     d.release();
     sc.release();
     dfree(status);
+    dfree(counters);
   }
 };
 
@@ -233,12 +238,16 @@ struct rlb_batch_s {
   std::vector<Launch> launches;
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
+  std::vector<UpdSeg> segs;
   PanelTile* d_panels = nullptr;
   UpdTile* d_updates = nullptr;
+  UpdSeg* d_segs = nullptr;
   int64_t* d_amap = nullptr;
   int64_t* d_nnz_ptr = nullptr;
   const double** d_vals = nullptr;
   int* status = nullptr;
+  int* counters = nullptr;
+  int ncounters = 0;
   std::vector<DevPlan> per;  // solve data of every matrix
   SolveScratch sc;
   double* L = nullptr;
@@ -253,10 +262,12 @@ struct rlb_batch_s {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     dfree(d_panels);
     dfree(d_updates);
+    dfree(d_segs);
     dfree(d_amap);
     dfree(d_nnz_ptr);
     if (d_vals) (void)hipFree((void*)d_vals);
     dfree(status);
+    dfree(counters);
     for (auto& p : per) p.release();
     sc.release();
   }
@@ -351,7 +362,8 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* o) {
   o->factor_bytes = s.plan.l_elems * (int64_t)sizeof(double);
   o->n_panel_tiles = (int64_t)s.plan.panels.size();
   o->n_update_tiles = (int64_t)s.plan.updates.size();
-  o->n_atomic_tiles = s.plan.n_atomic_tiles;
+  o->n_merged_tiles = s.plan.n_merged_tiles;
+  o->n_split_tiles = s.plan.n_split_tiles;
   o->n_launches = (int64_t)s.plan.launches.size();
   o->flops_tiles = s.plan.flops_tiles;
   o->flops_upd_alg = s.plan.flops_upd_alg;
@@ -388,15 +400,20 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
   else if (w == "level") put32(s.plan.level);
   else if (w == "off") put64(s.plan.off);
   else if (w == "amap") put64(s.plan.amap);
-  else if (w == "update_tiles") {  // c, x, y, ldc, lds, m, n, k, flags, src per tile
+  else if (w == "update_tiles") {  // c, ldc, m, n, flags, seg0, nseg per tile
     for (const UpdTile& t : s.plan.updates) {
-      int64_t v[10] = {t.c, t.x, t.y, t.ldc, t.lds, t.m, t.n, t.k, t.flags, t.src};
-      tmp.insert(tmp.end(), v, v + 10);
+      int64_t v[7] = {t.c, t.ldc, t.m, t.n, t.flags, t.seg0, t.nseg};
+      tmp.insert(tmp.end(), v, v + 7);
     }
-  } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, mode per tile
+  } else if (w == "update_segs") {  // x, y, lds, k, ra, rb, ca, cb, src per contribution
+    for (const UpdSeg& g : s.plan.segs) {
+      int64_t v[9] = {g.x, g.y, g.lds, g.k, g.ra, g.rb, g.ca, g.cb, g.src};
+      tmp.insert(tmp.end(), v, v + 9);
+    }
+  } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, grp, gcnt
     for (const PanelTile& t : s.plan.panels) {
-      int64_t v[8] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.mode};
-      tmp.insert(tmp.end(), v, v + 8);
+      int64_t v[9] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.grp, t.gcnt};
+      tmp.insert(tmp.end(), v, v + 9);
     }
   } else if (w == "launches") {  // kind, level, step, start, count per launch
     for (const Launch& l : s.plan.launches) {
@@ -424,9 +441,13 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   rlb_status st;
   if ((st = upload(&h->d.panels, s.plan.panels))) return st;
   if ((st = upload(&h->d.updates, s.plan.updates))) return st;
+  if ((st = upload(&h->d.segs, s.plan.segs))) return st;
   if ((st = upload(&h->d.amap, s.plan.amap))) return st;
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
+  h->ncounters = std::max<int32_t>(1, s.plan.max_groups);
+  HIP_OK(hipMalloc((void**)&h->counters, sizeof(int) * h->ncounters));
+  HIP_OK(hipMemset(h->counters, 0, sizeof(int) * h->ncounters));
   *out = h.release();
   return RLB_OK;
 }
@@ -435,18 +456,16 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
                            bool timed) {
   const Symbolic& s = h->sym->s;
   const Plan& p = s.plan;
-  launch_init_status(h->status, 1, st);
+  launch_init_status(h->status, 1, h->counters, h->ncounters, st);
   launch_fill(L, p.l_elems, 0.0, st);
   launch_scatter_a(values, h->d.amap, s.nnz_a, L, st);
   size_t ei = 0;
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(h->d.updates + l.start, l.count, L, h->precision, st);
-    else if (l.kind == LAUNCH_TRSM)
-      launch_trsm(h->d.panels + l.start, l.count, L, st);
+      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, st);
     else
-      launch_potrf(h->d.panels + l.start, l.count, L, h->status, st);
+      launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
 }
@@ -671,6 +690,17 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     maxlev = std::max(maxlev, syms[i]->s.plan.nlevels);
   }
   b->l_elems = run;
+  // contributions of every matrix, concatenated
+  std::vector<int64_t> segbase(count, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    segbase[i] = (int64_t)b->segs.size();
+    for (UpdSeg g : syms[i]->s.plan.segs) {
+      g.x += b->base[i];
+      g.y += b->base[i];
+      b->segs.push_back(g);
+    }
+  }
+  if (b->segs.size() > (size_t)INT32_MAX) return fail(RLB_ERR_ARG, "batch too large");
   // merge: for each (level, step, kind) the tiles of every matrix, in matrix order
   std::vector<size_t> cur(count, 0);
   for (;;) {
@@ -690,6 +720,7 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     }
     if (!any) break;
     Launch m{bk, bl, bs, 0, 0, 0};
+    int32_t gbase = 0;  // group counters are numbered across the merged matrices
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
       const Plan& p = syms[i]->s.plan;
@@ -697,18 +728,21 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
       const Launch& l = p.launches[cur[i]];
       if (l.level != bl || l.step != bs || l.kind != bk) continue;
       if (bk != LAUNCH_UPDATE) {
+        int32_t g_hi = 0;
         for (int64_t t = 0; t < l.count; ++t) {
           PanelTile pt = p.panels[l.start + t];
           pt.diag += b->base[i];
           pt.slot = i;
+          g_hi = std::max(g_hi, pt.grp + 1);
+          pt.grp += gbase;
           b->panels.push_back(pt);
         }
+        gbase += g_hi;
       } else {
         for (int64_t t = 0; t < l.count; ++t) {
           UpdTile ut = p.updates[l.start + t];
           ut.c += b->base[i];
-          ut.x += b->base[i];
-          ut.y += b->base[i];
+          ut.seg0 += (int32_t)segbase[i];
           b->updates.push_back(ut);
         }
       }
@@ -717,6 +751,7 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
               m.start;
     b->launches.push_back(m);
+    b->ncounters = std::max(b->ncounters, (int)gbase);
   }
   (void)maxlev;
   std::vector<int64_t> amap;
@@ -726,10 +761,14 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
   rlb_status st;
   if ((st = upload(&b->d_panels, b->panels))) return st;
   if ((st = upload(&b->d_updates, b->updates))) return st;
+  if ((st = upload(&b->d_segs, b->segs))) return st;
   if ((st = upload(&b->d_amap, amap))) return st;
   if ((st = upload(&b->d_nnz_ptr, b->nnz_ptr))) return st;
   HIP_OK(hipMalloc((void**)&b->d_vals, sizeof(double*) * count));
   HIP_OK(hipMalloc((void**)&b->status, sizeof(int) * count));
+  b->ncounters = std::max(1, b->ncounters);
+  HIP_OK(hipMalloc((void**)&b->counters, sizeof(int) * b->ncounters));
+  HIP_OK(hipMemset(b->counters, 0, sizeof(int) * b->ncounters));
   b->per.resize(count);
   for (int32_t i = 0; i < count; ++i)
     if ((st = upload_solve(syms[i]->s, b->base[i], b->per[i]))) return st;
@@ -740,16 +779,14 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
 
 static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   int32_t count = (int32_t)b->syms.size();
-  launch_init_status(b->status, count, st);
+  launch_init_status(b->status, count, b->counters, b->ncounters, st);
   launch_fill(L, b->l_elems, 0.0, st);
   launch_scatter_batch(b->d_vals, b->d_nnz_ptr, count, b->nnz_ptr[count], b->d_amap, L, st);
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(b->d_updates + l.start, l.count, L, b->precision, st);
-    else if (l.kind == LAUNCH_TRSM)
-      launch_trsm(b->d_panels + l.start, l.count, L, st);
+      launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, st);
     else
-      launch_potrf(b->d_panels + l.start, l.count, L, b->status, st);
+      launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, st);
   }
 }
 

@@ -18,15 +18,15 @@ struct SnMeta {
 constexpr int SOLVE_MAXRHS = 16;
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
-void launch_init_status(int* status, int count, hipStream_t st);
+void launch_init_status(int* status, int count, int* counters, int ncounters, hipStream_t st);
 void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, double* L,
                       hipStream_t st);
 void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
                           int64_t total, const int64_t* amap, double* L, hipStream_t st);
-void launch_potrf(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st);
-void launch_trsm(const PanelTile* tiles, int64_t count, double* L, hipStream_t st);
-void launch_update(const UpdTile* tiles, int64_t count, double* L, int precision,
-                   hipStream_t st);
+void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
+                  hipStream_t st);
+void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
+                   int precision, hipStream_t st);
 void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
                 const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st);
 void launch_bwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,

@@ -4,16 +4,17 @@
 // Factor storage: Lnz(J) is m_J x w_J column-major (ld = m_J), one FP64 buffer.
 //  * k_fill / k_scatter_a  -- A-load: zero the factor storage, then place A's
 //    lower-triangle values (Alg. 5 input: Lnz(J) holds A_{*,J} on entry).
-//  * k_potrf / k_trsm      -- cdiv of one <=64-wide column block (Alg. 5 line 4):
-//    POTRF of the 64x64 diagonal tile in the registers of one wavefront, then
-//    TRSM of the rows below it, one row per lane.
-//  * k_update<T>           -- C -= X * Y^T on a 64x64 tile of factor storage:
-//    the in-supernode trailing update and the SYRK/GEMM updates written
-//    directly into ancestors (Alg. 5 lines 11-16), on MFMA 16x16x4 (FP64, or
-//    FP32 operands with FP32 accumulation in the mixed form).
+//  * k_panel               -- cdiv of one <=64-wide column block (Alg. 5 line 4):
+//    POTRF of the diagonal tile in LDS fused with the TRSM of the rows below.
+//  * k_update<T>           -- C -= sum of X * Y^T on a 64x64 tile of factor
+//    storage: the in-supernode trailing update and the SYRK/GEMM updates
+//    written directly into ancestors (Alg. 5 lines 11-16), on MFMA 16x16x4
+//    (FP64, or FP32 operands with FP32 accumulation in the mixed form).
 //  * solves, SpMV residual, norms.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "device.h"
 
@@ -28,9 +29,10 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_init_status(int* status, int count) {
+__global__ void k_init_status(int* status, int count, int* counters, int ncounters) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) status[i] = 0x7fffffff;
+  if (i < ncounters) counters[i] = 0;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int count) {
@@ -61,20 +63,31 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// cdiv of a column block (Alg. 5 line 4) in two launches.
+// cdiv of one <=64-column block (Alg. 5 line 4): POTRF of the diagonal tile
+// fused with the TRSM of every row below it, in one launch.
 //
-// k_potrf (one wavefront per block): blocked Cholesky of the <=64x64 diagonal
-// tile T in LDS with 16-column steps. Only the 16x16 base blocks pivot in
-// registers (lane = row, row c reaches every lane through readlane); the
-// block TRSM and the trailing SYRK of each step are 16x16x16 products on FP64
-// MFMA. The kernel also forms inv(L) of the tile -- inverses of the base blocks
-// by substitution, then a block forward substitution on MFMA -- and stores its
-// strict lower part transposed in the tile's unused strict upper triangle
-// (the diagonal of inv(L) is 1/L(i,i)). No floating-point working storage
-// beyond factor storage is used.
+// A group is the set of workgroups that share one diagonal tile: one per 64
+// rows below it (or a single one when there are none). Every member stages
+// the unfactored tile into LDS, factors it there redundantly, forms inv(L) of
+// the tile and overwrites its own 64-row tile A with X = A * inv(L)^T. After
+// staging, each member increments the group's counter; the member that brings
+// it to the group size is the last reader of the unfactored tile, and only it
+// writes the factored tile back (L in the lower triangle, the strict lower
+// part of inv(L) transposed into the unused strict upper triangle, where the
+// solves read it). It also resets the counter for the next launch.
 //
-// k_trsm (four wavefronts per 64 rows below the tile): X = A * inv(L)^T as one
-// 64x64x64 MFMA product, written over A.
+// Factorization of the tile T (identity beyond nb) in 16-column rounds. In
+// round r, wavefront 0 factors the 64 x 16 column block r in registers
+// (lane = row, right-looking: the pivot and the next column's multiplier
+// reach every lane through readlane, the other multipliers through
+// same-address LDS reads of the finished column) while wavefronts 1-2 apply
+// block r-1's updates to the column blocks right of r+1 and wavefront 3
+// inverts the 16 x 16 diagonal block r-1; then all wavefronts update column
+// block r+1 with block r on MFMA. The pivot reciprocal is an rsq with two
+// Newton steps; the stored diagonal is the correctly rounded square root.
+// inv(L) follows from the 16 x 16 inverses by two levels of the 2 x 2 block
+// formula [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1]. X = A * inv(L)^T is a
+// 64x64 MFMA product that skips inv(L)^T's zero lower part.
 
 __device__ __forceinline__ double lane_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -83,18 +96,38 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 }
 
 constexpr int TP = 65;  // LDS row pitch of a 64x64 tile (doubles)
+constexpr int AP = 65;  // LDS pitch of the staged row tile: sA[k * AP + r] = A(r, k)
 
-// D += A * B for 16x16 blocks in LDS. A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc].
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// A * B for 16x16 blocks in LDS, A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc];
+// two accumulation chains over the halves of k
 __device__ __forceinline__ v4d mma16(const double* A, int ar, int ac, const double* B, int br,
-                                     int bc, v4d acc, int lane) {
+                                     int bc, int lane) {
+  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
 #pragma unroll
-  for (int kq = 0; kq < 4; ++kq) {
-    const int k = kq * 4 + (lane >> 4);
-    const double a = A[(lane & 15) * ar + k * ac];
-    const double b = B[k * br + (lane & 15) * bc];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  for (int kq = 0; kq < 4; kq += 2) {
+    const int k0 = kq * 4 + (lane >> 4), k1 = k0 + 4;
+    c0 = mfma64(A[(lane & 15) * ar + k0 * ac], B[k0 * br + (lane & 15) * bc], c0);
+    c1 = mfma64(A[(lane & 15) * ar + k1 * ac], B[k1 * br + (lane & 15) * bc], c1);
   }
-  return acc;
+  return c0 + c1;
+}
+
+// A * S with A a 16x16 block in LDS and S a 16x16 MFMA result in registers:
+// element kq of lane l of an FP64 result is S(4kq + l/16, l%16), which is
+// exactly lane l's B operand of k-step kq
+__device__ __forceinline__ v4d mma16r(const double* A, int ar, int ac, const v4d& S, int lane) {
+  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+  for (int kq = 0; kq < 4; kq += 2) {
+    const int k0 = kq * 4 + (lane >> 4), k1 = k0 + 4;
+    c0 = mfma64(A[(lane & 15) * ar + k0 * ac], S[kq], c0);
+    c1 = mfma64(A[(lane & 15) * ar + k1 * ac], S[kq + 1], c1);
+  }
+  return c0 + c1;
 }
 
 // element v of lane l of a 16x16 FP64 MFMA result is D(4v + l/16, l%16)
@@ -103,194 +136,228 @@ __device__ __forceinline__ void st16(double* D, const v4d& acc, int lane, double
   for (int v = 0; v < 4; ++v) D[(4 * v + (lane >> 4)) * TP + (lane & 15)] = scale * acc[v];
 }
 
-__global__ __launch_bounds__(64) void k_potrf(const PanelTile* __restrict__ tiles,
-                                              double* __restrict__ L, int* __restrict__ status) {
+// T(q, p) -= L(q, b) * L(p, b)^T for 16x16 blocks of the tile
+__device__ __forceinline__ void syrk16(double* T, int q, int p, int b, int lane) {
+  const v4d acc = mma16(&T[16 * q * TP + 16 * b], TP, 1, &T[16 * p * TP + 16 * b], 1, TP, lane);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    T[(16 * q + 4 * v + (lane >> 4)) * TP + 16 * p + (lane & 15)] -= acc[v];
+}
+
+// inverse of the 16x16 lower-triangular block at (o, o) of T into I; lane r
+// (< 16) forms column r by forward substitution, reading row i of L with
+// same-address LDS loads
+__device__ __forceinline__ void inv16(const double* T, double* I, int o, int lane) {
+  const int r = lane & 15;
+  const double rr = 1.0 / T[(o + r) * TP + o + r];
+  const double* Lo = T + o * TP + o;
+  double yv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double q0 = (i == r) ? 1.0 : 0.0, q1 = 0.0;
+#pragma unroll
+    for (int k = 0; k + 1 < i; k += 2) {
+      q0 = fma(-Lo[i * TP + k], yv[k], q0);
+      q1 = fma(-Lo[i * TP + k + 1], yv[k + 1], q1);
+    }
+    if (i & 1) q0 = fma(-Lo[i * TP + i - 1], yv[i - 1], q0);
+    yv[i] = (q0 + q1) * lane_bcast(rr, i);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = yv[i];
+  }
+}
+
+// right-looking factorization of the 64 x 16 column block at column o of T,
+// one wavefront, lane = row; Lc (16 x 64) receives the scaled columns for
+// the broadcasts. A non-positive pivot is not patched on the way (its NaN or
+// Inf only reaches later columns of this supernode and its ancestors, whose
+// column indices are larger); afterwards each pivot lane checks its own raw
+// pivot and the smallest failing column (1-based, factored order) is
+// returned, or INT_MAX.
+__device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int col0, int lane) {
+  double v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = T[lane * TP + o + j];
+  double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const double d = lane_bcast(v[c], o + c);
+    dg = (lane == o + c) ? d : dg;
+    double y = __builtin_amdgcn_rsq(d);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
+    const double l = v[c] * y;
+    v[c] = l;
+    if (c < 15) {
+      Lc[c * 64 + lane] = l;
+      v[c + 1] = fma(-l, lane_bcast(l, o + c + 1), v[c + 1]);
+#pragma unroll
+      for (int j = c + 2; j < 16; ++j) v[j] = fma(-l, Lc[c * 64 + o + j], v[j]);
+    }
+  }
+  const double sq = sqrt(dg);
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    T[lane * TP + o + j] = lane > o + j ? v[j] : (lane == o + j ? sq : 0.0);
+  const unsigned long long fails =
+      __ballot(lane >= o && lane < o + 16 && lane < nb && !(dg > 0.0));
+  return fails ? col0 + __ffsll((long long)fails) : 0x7fffffff;
+}
+
+__global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ tiles,
+                                               double* __restrict__ L, int* __restrict__ status,
+                                               int* __restrict__ counters) {
   const PanelTile t = tiles[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int nb = t.nb;
-  const int ldi = t.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = t.nb, ldi = t.ld;
+  const int nr = min(64, t.nrows - t.row0);  // rows of this member's tile (may be <= 0)
   double* D = L + t.diag;
   __shared__ double T[64 * TP];   // the tile, row-major: T[i*TP + j]
   __shared__ double I[64 * TP];   // inv(L), row-major
-  // stage the lower triangle (identity beyond nb); unconditional clamped loads
+  __shared__ double sA[64 * AP];  // the row tile, k-major
+  __shared__ double Lc[16 * 64];  // finished columns of the current 16-column block
+  __shared__ int s_last;
+  // stage: thread (row, cg) loads columns cg, cg+4, ..., all 32 loads in flight;
+  // addresses are clamped so every load is in bounds
   {
-    const int li = min(lane, nb - 1);
-    double v[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) v[j] = D[min(j, nb - 1) * ldi + li];  // all loads in flight
-#pragma unroll
-    for (int j = 0; j < 64; ++j)
-      T[lane * TP + j] = (lane < nb && j < nb && j <= lane) ? v[j] : (j == lane ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  int bad = 0x7fffffff;
-  const int nbb = (nb + 15) >> 4;  // base blocks that hold columns of the tile
-  for (int b = 0; b < nbb; ++b) {
-    const int o = 16 * b;
-    // (1) base POTRF of T[o:o+16, o:o+16]: lanes 0..15 hold its rows
-    // (lanes 16..63 mirror them). Left-looking, four partial sums per dot
-    // product; the column below each pivot is scaled by 1/L(c,c) from one rsq
-    // with two Newton steps, while L(c,c) itself is the correctly rounded sqrt.
-    const int r = lane & 15;
-    double blk[16], rinv[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) blk[j] = T[(o + r) * TP + o + j];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-      for (int k = 0; k + 3 < c; k += 4) {
-        p0 += blk[k] * lane_bcast(blk[k], c);
-        p1 += blk[k + 1] * lane_bcast(blk[k + 1], c);
-        p2 += blk[k + 2] * lane_bcast(blk[k + 2], c);
-        p3 += blk[k + 3] * lane_bcast(blk[k + 3], c);
-      }
-#pragma unroll
-      for (int k = c & ~3; k < c; ++k) p0 += blk[k] * lane_bcast(blk[k], c);
-      const double v = blk[c] - ((p0 + p1) + (p2 + p3));
-      double piv = lane_bcast(v, c);
-      if (!(piv > 0.0)) {
-        if (o + c < nb) bad = min(bad, t.col + o + c + 1);
-        piv = 1.0;
-      }
-      double y = __builtin_amdgcn_rsq(piv);
-      y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
-      y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
-      rinv[c] = y;
-      blk[c] = (r == c) ? sqrt(piv) : (r > c ? v * y : 0.0);
-    }
-    // (2) base inverse: lane j < 16 forms column j of inv(L_bb) by substitution
-    double yv[16];
+    const int row = lane, cg = wave;
+    const int dr = min(row, nb - 1);
+    const int arow = min(t.row0 + max(0, min(row, nr - 1)), t.nrows - 1);
+    double dv[16], av[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      double q0 = (i == r) ? 1.0 : 0.0, q1 = 0.0;
-#pragma unroll
-      for (int k = 0; k + 1 < i; k += 2) {
-        q0 -= lane_bcast(blk[k], i) * yv[k];
-        q1 -= lane_bcast(blk[k + 1], i) * yv[k + 1];
-      }
-      if (i & 1) q0 -= lane_bcast(blk[i - 1], i) * yv[i - 1];
-      yv[i] = (q0 + q1) * rinv[i];
+      const int j = min(cg + 4 * i, nb - 1);
+      dv[i] = D[(int64_t)j * ldi + dr];
+      av[i] = D[(int64_t)j * ldi + arow];
     }
-    if (lane < 16) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) T[(o + r) * TP + o + j] = blk[j];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = yv[i];
+    for (int i = 0; i < 16; ++i) {
+      const int j = cg + 4 * i;
+      T[row * TP + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+      sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
     }
-    __syncthreads();
-    // (3) panel below the base block: L(q, bb) = T(q, bb) * inv(L_bb)^T
-    for (int qb = b + 1; qb < nbb; ++qb) {
-      v4d acc = {0, 0, 0, 0};
-      acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &I[o * TP + o], 1, TP, acc, lane);
-      __syncthreads();
-      st16(&T[(16 * qb) * TP + o], acc, lane, 1.0);
-    }
-    __syncthreads();
-    // (4) trailing SYRK: T(q, p) -= L(q, bb) * L(p, bb)^T for b < p <= q
-    for (int qb = b + 1; qb < nbb; ++qb)
-      for (int pb = b + 1; pb <= qb; ++pb) {
-        v4d acc = {0, 0, 0, 0};
-        acc = mma16(&T[(16 * qb) * TP + o], TP, 1, &T[(16 * pb) * TP + o], 1, TP, acc, lane);
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          T[(16 * qb + 4 * v + (lane >> 4)) * TP + 16 * pb + (lane & 15)] -= acc[v];
-      }
-    __syncthreads();
-  }
-  // (5) block forward substitution for the off-diagonal blocks of inv(L):
-  //     inv(L)(i,j) = -inv(L_ii) * sum_{j<=k<i} L(i,k) * inv(L)(k,j)
-  for (int jb = 0; jb + 1 < nbb; ++jb)
-    for (int ib = jb + 1; ib < nbb; ++ib) {
-      v4d s = {0, 0, 0, 0};
-      for (int kb = jb; kb < ib; ++kb)
-        s = mma16(&T[(16 * ib) * TP + 16 * kb], TP, 1, &I[(16 * kb) * TP + 16 * jb], TP, 1, s,
-                  lane);
-      __syncthreads();
-      // stage S into the (ib, jb) block of I, then multiply by -inv(L_ii)
-      st16(&I[(16 * ib) * TP + 16 * jb], s, lane, 1.0);
-      __syncthreads();
-      v4d u = {0, 0, 0, 0};
-      u = mma16(&I[(16 * ib) * TP + 16 * ib], TP, 1, &I[(16 * ib) * TP + 16 * jb], TP, 1, u, lane);
-      __syncthreads();
-      st16(&I[(16 * ib) * TP + 16 * jb], u, lane, -1.0);
-      __syncthreads();
-    }
-  if (lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
-  // (6) L to the lower triangle, strict lower of inv(L) transposed to the
-  //     strict upper triangle (only inside the nb x nb tile)
-  {
-    double w[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) w[j] = (j <= lane) ? T[lane * TP + j] : I[j * TP + lane];
-    if (lane < nb) {
-#pragma unroll
-      for (int j = 0; j < 64; ++j)
-        if (j < nb) D[j * ldi + lane] = w[j];
-    }
-  }
-}
-
-// X = A * inv(L)^T for up to 64 rows below the diagonal tile, in place.
-__global__ __launch_bounds__(256) void k_trsm(const PanelTile* __restrict__ tiles,
-                                              double* __restrict__ L) {
-  const PanelTile t = tiles[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = t.nb;
-  const int ldi = t.ld;
-  const int nr = min(64, t.nrows - t.row0);
-  if (nr <= 0) return;
-  double* D = L + t.diag;
-  __shared__ double sA[64][64];   // sA[k][r] = A(row0 + r, k)
-  __shared__ double sV[64][64];   // sV[k][j] = inv(L)(j, k)
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int k = e >> 6, r = e & 63;  // consecutive threads: consecutive rows
-    const double a = D[min(k, nb - 1) * ldi + t.row0 + min(r, nr - 1)];
-    sA[k][r] = (k < nb && r < nr) ? a : 0.0;
-  }
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int j = e >> 6, k = e & 63;  // inv(L)(j,k) for j > k sits at D[j*ld + k]
-    const int jj = min(j, nb - 1), kk = min(k, nb - 1);
-    const double u = D[jj * ldi + kk];
-    double v = 0.0;
-    if (j < nb && k < nb) v = (j > k) ? u : (j == k ? 1.0 / u : 0.0);
-    sV[k][j] = v;
   }
   __syncthreads();
-  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
-  v4d acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
-#pragma unroll 4
-  for (int kq = 0; kq < 16; ++kq) {
-    const int k = kq * 4 + (lane >> 4);
-    const double a0 = sV[k][wc + (lane & 15)], a1 = sV[k][wc + 16 + (lane & 15)];
-    const double b0 = sA[k][wr + (lane & 15)], b1 = sA[k][wr + 16 + (lane & 15)];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  if (tid == 0) {
+    const int old = atomicAdd(&counters[t.grp], 1);
+    const int last = (old == t.gcnt - 1);
+    if (last) atomicExch(&counters[t.grp], 0);
+    s_last = last;
   }
-  // D = V * A^T: element v of lane l of block (bj, bi) is X(row wr+16bi+l%16,
-  // column wc+16bj+4v+l/16)
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + (lane & 15);
-        const int col = wc + 16 * bj + 4 * v + (lane >> 4);
-        if (row < nr && col < nb) D[col * ldi + t.row0 + row] = acc[bj][bi][v];
+  const int nbb = (nb + 15) >> 4;
+  int bad = 0x7fffffff;
+  for (int r = 0; r < nbb; ++r) {
+    if (wave == 0) {
+      bad = min(bad, panel16(T, Lc, 16 * r, nb, t.col, lane));
+    } else if (r >= 1) {
+      if (wave == 3) {
+        inv16(T, I, 16 * (r - 1), lane);
+      } else {
+        // block r-1's updates of column blocks p >= r+1
+        int idx = 0;
+        for (int p = r + 1; p < nbb; ++p)
+          for (int q = p; q < nbb; ++q, ++idx)
+            if ((idx & 1) == wave - 1) syrk16(T, q, p, r - 1, lane);
       }
+    }
+    __syncthreads();
+    // column block r+1 from block r
+    if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, r + 1 + wave, r + 1, r, lane);
+    __syncthreads();
+  }
+  if (wave == 0) inv16(T, I, 16 * (nbb - 1), lane);
+  __syncthreads();
+  // inv(L), level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
+  {
+    const int i1 = wave == 0 ? 1 : 3;
+    if ((wave == 0 && nbb >= 2) || (wave == 1 && nbb >= 4)) {
+      const v4d s = mma16(&T[16 * i1 * TP + 16 * (i1 - 1)], TP, 1,
+                          &I[16 * (i1 - 1) * TP + 16 * (i1 - 1)], TP, 1, lane);
+      const v4d u = mma16r(&I[16 * i1 * TP + 16 * i1], TP, 1, s, lane);
+      st16(&I[16 * i1 * TP + 16 * (i1 - 1)], u, lane, -1.0);
+    }
+  }
+  __syncthreads();
+  // level 2 (nbb >= 3): for i in [2, nbb), j in {0, 1}:
+  //   S(i,j) = L(i,0) inv(0,j) + L(i,1) inv(1,j)   (wave 2(i-2)+j, via LDS: T's
+  //   unused block (j, i)), then inv(i,j) = -sum_{2 <= l <= i} inv(i,l) S(l,j)
+  const int i2 = 2 + (wave >> 1), j2 = wave & 1;
+  const bool p2 = nbb >= 3 && i2 < nbb;
+  if (p2) {
+    v4d s = mma16(&T[16 * i2 * TP + 16], TP, 1, &I[16 * TP + 16 * j2], TP, 1, lane);
+    if (j2 == 0) s += mma16(&T[16 * i2 * TP], TP, 1, &I[0], TP, 1, lane);
+    st16(&T[16 * j2 * TP + 16 * i2], s, lane, 1.0);
+  }
+  __syncthreads();
+  if (p2) {
+    v4d u = {0, 0, 0, 0};
+    for (int l = 2; l <= i2; ++l)
+      u += mma16(&I[16 * i2 * TP + 16 * l], TP, 1, &T[16 * j2 * TP + 16 * l], TP, 1, lane);
+    st16(&I[16 * i2 * TP + 16 * j2], u, lane, -1.0);
+  }
+  __syncthreads();
+  // the last reader writes the factored tile: L below and on the diagonal,
+  // inv(L) strict lower part transposed above it
+  if (s_last) {
+    if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
+    const int i = lane;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = wave + 4 * q;
+      const double val = (i >= j) ? T[i * TP + j] : I[j * TP + i];
+      if (i < nb && j < nb) D[(int64_t)j * ldi + i] = val;
+    }
+  }
+  if (nr <= 0) return;
+  // X = A * inv(L)^T. Wave w: row blocks 2(w&1), 2(w&1)+1; column blocks
+  // {0,3} or {1,2} (equal MFMA counts, since column block c needs k < 16(c+1)).
+  // D = V * A^T per 16x16 block: element v of lane l is X(row 16rb + l%16,
+  // column 16cb + 4v + l/16), so stores are coalesced along the rows.
+  const int rb0 = 2 * (wave & 1);
+  const int kpad = (nb + 3) & ~3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int cb = (wave >> 1) ? 1 + h : 3 * h;
+    const int nk = min(16 * (cb + 1), kpad) >> 2;  // k-steps of 4
+    v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+    for (int s = 0; s < nk; s += 4) {
+      double vv[4], b0[4], b1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * (s + u) + (lane >> 4);  // < 64 for every s + u < 16
+        vv[u] = I[(16 * cb + (lane & 15)) * TP + k];
+        b0[u] = sA[k * AP + 16 * rb0 + (lane & 15)];
+        b1[u] = sA[k * AP + 16 * (rb0 + 1) + (lane & 15)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (s + u < nk) {
+          a0 = mfma64(vv[u], b0[u], a0);
+          a1 = mfma64(vv[u], b1[u], a1);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * cb + 4 * v + (lane >> 4);
+      const int r0 = 16 * rb0 + (lane & 15), r1 = r0 + 16;
+      if (c < nb) {
+        if (r0 < nr) D[(int64_t)c * ldi + t.row0 + r0] = a0[v];
+        if (r1 < nr) D[(int64_t)c * ldi + t.row0 + r1] = a1[v];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// C -= X * Y^T on one <=64x64 tile. 256 threads = 4 wavefronts in a 2x2
-// arrangement, each owning a 32x32 quarter = 2x2 MFMA 16x16 blocks. K is
-// staged through LDS in chunks of 16 (column-major, as in factor storage).
+// Update of one <=64x64 target tile: C -= sum over its contributions of
+// X * Y^T. 256 threads = 4 wavefronts in a 2x2 arrangement, each owning a
+// 32x32 quarter = 2x2 MFMA 16x16 blocks; K is staged through LDS in chunks of
+// 16 (column-major, as in factor storage), the next chunk's loads in flight
+// while the current one is multiplied. A tile with one owner is read once at
+// the start and written once at the end; the parts of a split tile are added
+// with atomics.
 //
 // MFMA 16x16x4 operand layout (lane l): A[l%16][l/16] and B[l/16][l%16]. The
 // accumulator layout differs by type: for FP64 element v of lane l is
@@ -321,21 +388,38 @@ constexpr int KC = 16;  // K chunk staged per LDS buffer
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles,
+                                                const UpdSeg* __restrict__ segs,
                                                 double* __restrict__ L) {
   typedef typename Mfma<T>::acc_t acc_t;
   const UpdTile t = tiles[blockIdx.x];
-  __shared__ T sX[2][KC][64];
-  __shared__ T sY[2][KC][64];
+  __shared__ T sX[2][KC][64];  // [k][tile row]
+  __shared__ T sY[2][KC][64];  // [k][tile column]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32;   // rows of this wave's quarter
   const int wc = (wave >> 1) * 32;  // columns of this wave's quarter
-  const double* __restrict__ X = L + t.x;
-  const double* __restrict__ Y = L + t.y;
-  const int64_t lds = t.lds;
-  const int K = t.k;
-  const int lr = tid & 63;  // row this thread stages
-  const int lk = tid >> 6;  // first k this thread stages (then +4, +8, +12)
+  const int lr = tid & 63;  // tile row / column this thread stages
+  const int lk = tid >> 6;  // first k this thread stages (then +4, +8, ...)
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+
+  // the target values of a tile with a single owner, loaded up front (no
+  // other workgroup of the launch writes it); addresses clamped into the tile
+  double cv[2][2][4];
+  if (!atomic) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
+          cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        }
+  }
 
   acc_t acc[2][2];
 #pragma unroll
@@ -343,53 +427,111 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  double xr[4], yr[4];
-  auto fetch = [&](int k0) {
+  // chunks: (contribution e, k0) in order; rows outside a contribution's
+  // rectangle and k beyond its inner dimension are staged as zeros. The loads
+  // are unconditional (clamped addresses) and the zero mask is applied when
+  // the chunk is written to LDS, so the loads stay in flight during the
+  // multiplication of the previous chunk.
+  double xr[KC / 4], yr[KC / 4];
+  bool xin = false, yin = false;
+  int kvalid = 0;  // k offsets (relative to this thread's first k) still inside the contribution
+  auto fetch = [&](const UpdSeg& g, int k0) {
+    xin = lr >= g.ra && lr < g.rb;
+    yin = lr >= g.ca && lr < g.cb;
+    kvalid = g.k - k0 - lk;
+    const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+    const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = k0 + lk + 4 * q;
-      xr[q] = (k < K && lr < t.m) ? X[(int64_t)k * lds + lr] : 0.0;
-      yr[q] = (k < K && lr < t.n) ? Y[(int64_t)k * lds + lr] : 0.0;
+    for (int q = 0; q < KC / 4; ++q) {
+      const int64_t kk = min(k0 + lk + 4 * q, g.k - 1);
+      xr[q] = L[xo + kk * g.lds];
+      yr[q] = L[yo + kk * g.lds];
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      sX[buf][lk + 4 * q][lr] = (T)xr[q];
-      sY[buf][lk + 4 * q][lr] = (T)yr[q];
+    for (int q = 0; q < KC / 4; ++q) {
+      const bool kin = 4 * q < kvalid;
+      sX[buf][lk + 4 * q][lr] = (T)((kin && xin) ? xr[q] : 0.0);
+      sY[buf][lk + 4 * q][lr] = (T)((kin && yin) ? yr[q] : 0.0);
     }
   };
-  fetch(0);
+  // the tile's contribution records, staged once (the first SEGS_LDS of them)
+  constexpr int SEGS_LDS = 64;
+  __shared__ UpdSeg sg[SEGS_LDS];
+  {
+    const int words = min(t.nseg, SEGS_LDS) * (int)(sizeof(UpdSeg) / 8);
+    const int64_t* src = reinterpret_cast<const int64_t*>(segs + t.seg0);
+    int64_t* dst = reinterpret_cast<int64_t*>(sg);
+    for (int w = tid; w < words; w += 256) dst[w] = src[w];
+  }
+  __syncthreads();
+  auto seg_at = [&](int i) { return i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]; };
+  int e = 0, k0 = 0;
+  UpdSeg g = seg_at(0);
+  fetch(g, 0);
   stash(0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    const bool more = k0 + KC < K;
-    if (more) fetch(k0 + KC);
+  for (;;) {
+    // this wave's 16x16 blocks that meet the contribution's rectangle
+    bool use[2][2];
 #pragma unroll
-    for (int kq = 0; kq < KC / 4; ++kq) {
-      const int kk = kq * 4 + (lane >> 4);
-      const T a0 = sY[buf][kk][wc + (lane & 15)];
-      const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
-      const T b0 = sX[buf][kk][wr + (lane & 15)];
-      const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
-      acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        use[bj][bi] = wr + 16 * bi < g.rb && wr + 16 * bi + 16 > g.ra &&
+                      wc + 16 * bj < g.cb && wc + 16 * bj + 16 > g.ca;
+    const bool all4 = use[0][0] && use[0][1] && use[1][0] && use[1][1];
+    // next chunk
+    int ne = e, nk0 = k0 + KC;
+    if (nk0 >= g.k) {
+      ne = e + 1;
+      nk0 = 0;
     }
+    const bool more = ne < t.nseg;
+    UpdSeg gn = g;
     if (more) {
-      stash(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+      if (ne != e) gn = seg_at(ne);
+      fetch(gn, nk0);
     }
+    if (all4) {
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const T a0 = sY[buf][kk][wc + (lane & 15)];
+        const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const T b0 = sX[buf][kk][wr + (lane & 15)];
+        const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      }
+    } else if (use[0][0] || use[0][1] || use[1][0] || use[1][1]) {
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const T a0 = sY[buf][kk][wc + (lane & 15)];
+        const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const T b0 = sX[buf][kk][wr + (lane & 15)];
+        const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        if (use[0][0]) acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+        if (use[0][1]) acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+        if (use[1][0]) acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+        if (use[1][1]) acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      }
+    }
+    if (!more) break;
+    stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    e = ne;
+    k0 = nk0;
+    g = gn;
   }
   // epilogue: acc[bj][bi][v] is the update of target row wr+16*bi+(lane&15),
   // target column wc+16*bj+drow(lane,v)
-  double* __restrict__ C = L + t.c;
-  const int64_t ldc = t.ldc;
-  const bool diag = t.flags & 1;
-  const bool atomic = t.flags & 2;
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
@@ -400,17 +542,16 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
         const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
         if (row < t.m && col < t.n && (!diag || row >= col)) {
           double* p = C + (int64_t)col * ldc + row;
-          const double u = (double)acc[bj][bi][v];
           if (atomic)
-            atomicAdd(p, -u);
+            atomicAdd(p, -(double)acc[bj][bi][v]);
           else
-            *p -= u;
+            *p = cv[bj][bi][v] - (double)acc[bj][bi][v];
         }
       }
 }
 
-template __global__ void k_update<double>(const UpdTile*, double*);
-template __global__ void k_update<float>(const UpdTile*, double*);
+template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
+template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
 
 // ---------------------------------------------------------------------------
 // supernodal solves, one workgroup per supernode of a level.
@@ -661,8 +802,9 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
 }
-void launch_init_status(int* status, int count, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_status, dim3(grid_for(count, 256)), dim3(256), 0, st, status, count);
+void launch_init_status(int* status, int count, int* counters, int ncounters, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_status, dim3(grid_for(std::max(count, ncounters), 256)), dim3(256), 0,
+                     st, status, count, counters, ncounters);
 }
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count);
@@ -679,21 +821,20 @@ void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int
   hipLaunchKernelGGL(k_scatter_batch, dim3(grid_for(total, 256, INT32_MAX)), dim3(256), 0, st,
                      vals, nnz_ptr, count, total, amap, L);
 }
-void launch_potrf(const PanelTile* tiles, int64_t count, double* L, int* status, hipStream_t st) {
+void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
+                  hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_potrf, dim3((unsigned)count), dim3(64), 0, st, tiles, L, status);
+  hipLaunchKernelGGL(k_panel, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
+                     counters);
 }
-void launch_trsm(const PanelTile* tiles, int64_t count, double* L, hipStream_t st) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_trsm, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
-}
-void launch_update(const UpdTile* tiles, int64_t count, double* L, int precision,
-                   hipStream_t st) {
+void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
+                   int precision, hipStream_t st) {
   if (count <= 0) return;
   if (precision == 1)
-    hipLaunchKernelGGL(k_update<float>, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
+    hipLaunchKernelGGL(k_update<float>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs, L);
   else
-    hipLaunchKernelGGL(k_update<double>, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
+    hipLaunchKernelGGL(k_update<double>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs,
+                       L);
 }
 void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
                 const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st) {

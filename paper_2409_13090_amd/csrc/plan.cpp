@@ -14,11 +14,13 @@
 //     block k inside the same supernode, and (b) for every supernode whose last
 //     column block was k, all of its SYRK/GEMM updates written straight into
 //     the ancestors' factor storage (Alg. 5 lines 7-18).
-// Siblings of one level may write the same target entries; a tile is marked
-// atomic exactly when another supernode of its launch touches one of its
-// target columns.
+// Siblings of one level may write the same target entries: the update launch
+// gives every 64x64 target tile to one workgroup, which sums the
+// contributions of all supernodes that touch the tile and writes it once.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <tuple>
 
 #include "symbolic.h"
 
@@ -30,6 +32,8 @@ constexpr int TM = 64;   // update tile rows
 constexpr int TN = 64;   // update tile columns
 constexpr int FLAG_DIAG = 1;
 constexpr int FLAG_ATOMIC = 2;
+constexpr int KCH = 16;        // K chunk of the update kernel
+constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a tile is split
 
 // One rectangle of the ancestor update: target rows [r0, r0+mr) and columns
 // [c0, c0+nc) of Lnz(P); source rows [sx, ..) and [sy, ..) of Lnz(J).
@@ -38,40 +42,21 @@ struct Rect {
   bool diag;
 };
 
-// entries a tile writes: the full rectangle, or its lower triangle part when
-// the tile sits on the diagonal of a SYRK target
-double tile_entries(int64_t m, int64_t n, bool diag) {
-  if (!diag) return (double)m * (double)n;
+// entries a contribution writes: its full rectangle, or the part with
+// row >= col when the target tile sits on the diagonal of its supernode
+double seg_entries(int64_t ra, int64_t rb, int64_t ca, int64_t cb, bool diag) {
+  if (!diag) return (double)(rb - ra) * (double)(cb - ca);
   double e = 0;
-  for (int64_t c = 0; c < n; ++c) e += (double)std::max<int64_t>(0, m - c);
+  for (int64_t c = ca; c < cb; ++c) e += (double)std::max<int64_t>(0, rb - std::max(ra, c));
   return e;
 }
 
-void cut_rect(const Symbolic& s, Plan& p, int64_t J, const Rect& r, int32_t atomic,
-              std::vector<UpdTile>& out, double& flops) {
-  int64_t mP = s.gl_ptr[r.P + 1] - s.gl_ptr[r.P];
-  int64_t mJ = s.gl_ptr[J + 1] - s.gl_ptr[J];
-  int64_t wJ = s.sn_ptr[J + 1] - s.sn_ptr[J];
-  for (int64_t tj = 0; tj < r.nc; tj += TN) {
-    int64_t tn = std::min<int64_t>(TN, r.nc - tj);
-    for (int64_t ti = r.diag ? tj : 0; ti < r.mr; ti += TM) {
-      int64_t tm = std::min<int64_t>(TM, r.mr - ti);
-      UpdTile t;
-      t.c = p.off[r.P] + (r.c0 + tj) * mP + (r.r0 + ti);
-      t.x = p.off[J] + r.sx + ti;
-      t.y = p.off[J] + r.sy + tj;
-      t.ldc = (int32_t)mP;
-      t.lds = (int32_t)mJ;
-      t.m = (int32_t)tm;
-      t.n = (int32_t)tn;
-      t.k = (int32_t)wJ;
-      t.flags = ((r.diag && ti == tj) ? FLAG_DIAG : 0) | atomic;
-      t.src = (int32_t)J;
-      out.push_back(t);
-      flops += 2.0 * (double)tm * (double)tn * (double)wJ;
-      p.flops_upd_alg += 2.0 * (double)wJ * tile_entries(tm, tn, r.diag && ti == tj);
-    }
-  }
+// flops the kernel executes for a contribution: the 16x16 blocks of the
+// 64x64 tile that meet its rectangle, over k rounded up to the K chunk
+double seg_exec_flops(int64_t ra, int64_t rb, int64_t ca, int64_t cb, int64_t k) {
+  int64_t br = (rb - 1) / 16 - ra / 16 + 1, bc = (cb - 1) / 16 - ca / 16 + 1;
+  int64_t kp = (k + 15) / 16 * 16;
+  return 2.0 * (double)(br * 16) * (double)(bc * 16) * (double)kp;
 }
 
 }  // namespace
@@ -192,17 +177,16 @@ int build_plan(Symbolic& s, std::string& err) {
   }
 
   // launches
-  std::vector<int32_t> colcnt(n, 0);
   p.flops_tiles = 0;
   for (int32_t h = 0; h < p.nlevels; ++h) {
     int64_t steps = 0;
     for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
       steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
     for (int64_t k = 0; k < steps; ++k) {
-      // POTRF (and the TRSM of blocks with at most one row tile), then the
-      // TRSM row tiles of the taller blocks against their factored tiles
-      Launch lp{LAUNCH_POTRF, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
-      std::vector<PanelTile> trsm;
+      // PANEL: one group per supernode with a column block k, one tile per
+      // 64 rows below the diagonal tile (a single tile when there are none)
+      Launch lp{LAUNCH_PANEL, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
+      int32_t ngroups = 0;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         if (k * NB >= w) continue;
@@ -212,35 +196,26 @@ int build_plan(Symbolic& s, std::string& err) {
         // counts nb..1) plus TRSM of the rows below (nb^2 per row)
         for (int64_t t = 0; t < nb; ++t) p.flops_panel += (double)(nb - t) * (double)(nb - t);
         p.flops_panel += (double)below * (double)nb * (double)nb;
-        int64_t nt = (below + 63) / 64;  // TRSM row tiles of 64 rows
+        int64_t nt = std::max<int64_t>(1, (below + 63) / 64);
         PanelTile pt;
         pt.diag = p.off[J] + c0 * m + c0;
         pt.ld = (int32_t)m;
         pt.nb = (int32_t)nb;
         pt.nrows = (int32_t)nrows;
-        pt.row0 = (int32_t)nb;
         pt.col = (int32_t)(s.sn_ptr[J] + c0);
         pt.slot = 0;
-        pt.pad = 0;
-        pt.mode = 1;
-        p.panels.push_back(pt);
-        if (nt > 0) {
-          for (int64_t t = 0; t < nt; ++t) {
-            PanelTile tt = pt;
-            tt.mode = 2;
-            tt.row0 = (int32_t)(nb + 64 * t);
-            trsm.push_back(tt);
-          }
+        pt.grp = ngroups++;
+        pt.gcnt = (int32_t)nt;
+        for (int64_t t = 0; t < nt; ++t) {
+          pt.row0 = (int32_t)(nb + 64 * t);
+          p.panels.push_back(pt);
         }
       }
       lp.count = (int64_t)p.panels.size() - lp.start;
       if (lp.count) p.launches.push_back(lp);
-      if (!trsm.empty()) {
-        Launch lt{LAUNCH_TRSM, h, (int32_t)k, 0, (int64_t)p.panels.size(), (int64_t)trsm.size()};
-        p.panels.insert(p.panels.end(), trsm.begin(), trsm.end());
-        p.launches.push_back(lt);
-      }
-      // UPDATE: trailing updates of step k, ancestor updates of finished supernodes
+      p.max_groups = std::max(p.max_groups, ngroups);
+      // UPDATE: trailing updates of step k, ancestor updates of finished
+      // supernodes; one target tile per workgroup with all its contributions
       Launch lu{LAUNCH_UPDATE, h, (int32_t)k, 0, (int64_t)p.updates.size(), 0};
       std::vector<int64_t> finished;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
@@ -252,47 +227,138 @@ int build_plan(Symbolic& s, std::string& err) {
             int64_t tn = std::min<int64_t>(TN, w - tj0);
             for (int64_t ti0 = tj0; ti0 < m; ti0 += TM) {
               int64_t tm = std::min<int64_t>(TM, m - ti0);
+              bool diag = ti0 == tj0;
               UpdTile t;
               t.c = p.off[J] + tj0 * m + ti0;
-              t.x = p.off[J] + c0 * m + ti0;
-              t.y = p.off[J] + c0 * m + tj0;
               t.ldc = (int32_t)m;
-              t.lds = (int32_t)m;
               t.m = (int32_t)tm;
               t.n = (int32_t)tn;
-              t.k = (int32_t)nb;
-              t.flags = (ti0 == tj0) ? FLAG_DIAG : 0;
-              t.src = (int32_t)J;
+              t.flags = diag ? FLAG_DIAG : 0;
+              t.seg0 = (int32_t)p.segs.size();
+              t.nseg = 1;
+              UpdSeg g;
+              g.x = p.off[J] + c0 * m + ti0;
+              g.y = p.off[J] + c0 * m + tj0;
+              g.lds = (int32_t)m;
+              g.k = (int32_t)nb;
+              g.ra = 0;
+              g.rb = (int32_t)tm;
+              g.ca = 0;
+              g.cb = (int32_t)tn;
+              g.src = (int32_t)J;
+              g.pad = 0;
               p.updates.push_back(t);
-              p.flops_tiles += 2.0 * tm * tn * nb;
-              p.flops_upd_alg += 2.0 * (double)nb * tile_entries(tm, tn, ti0 == tj0);
+              p.segs.push_back(g);
+              p.flops_tiles += seg_exec_flops(0, tm, 0, tn, nb);
+              p.flops_upd_alg += 2.0 * (double)nb * seg_entries(0, tm, 0, tn, diag);
             }
           }
         } else {
           finished.push_back(J);
         }
       }
-      // conflicts: columns of an ancestor touched by two supernodes of this launch
-      for (int64_t J : finished)
-        for (const Rect& r : rects[J])
-          if (r.diag)
-            for (int64_t c = 0; c < r.nc; ++c) colcnt[s.sn_ptr[r.P] + r.c0 + c]++;
-      for (int64_t J : finished)
+      // ancestor updates: cut every rectangle by the 64x64 tile grid of its
+      // target supernode and group the pieces by target tile (key: target,
+      // tile column, tile row), in ascending source order
+      std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<UpdSeg>> by_tile;
+      for (int64_t J : finished) {
+        int64_t mJ = M(J), wJ = W(J);
         for (const Rect& r : rects[J]) {
-          int32_t atomic = 0;
-          for (int64_t c = 0; c < r.nc; ++c)
-            if (colcnt[s.sn_ptr[r.P] + r.c0 + c] > 1) {
-              atomic = FLAG_ATOMIC;
-              break;
+          int64_t mP = M(r.P), wP = W(r.P);
+          for (int64_t TJ = r.c0 / TN; TJ * TN < r.c0 + r.nc; ++TJ)
+            for (int64_t TI = std::max(TJ, r.r0 / TM); TI * TM < r.r0 + r.mr; ++TI) {
+              int64_t rlo = std::max(r.r0, TI * TM), rhi = std::min({r.r0 + r.mr, TI * TM + TM, mP});
+              int64_t clo = std::max(r.c0, TJ * TN), chi = std::min({r.c0 + r.nc, TJ * TN + TN, wP});
+              if (rlo >= rhi || clo >= chi) continue;
+              if (TI == TJ && rhi - 1 < clo) continue;  // entirely above the diagonal
+              UpdSeg g;
+              g.x = p.off[J] + r.sx + (rlo - r.r0);
+              g.y = p.off[J] + r.sy + (clo - r.c0);
+              g.lds = (int32_t)mJ;
+              g.k = (int32_t)wJ;
+              g.ra = (int32_t)(rlo - TI * TM);
+              g.rb = (int32_t)(rhi - TI * TM);
+              g.ca = (int32_t)(clo - TJ * TN);
+              g.cb = (int32_t)(chi - TJ * TN);
+              g.src = (int32_t)J;
+              g.pad = 0;
+              by_tile[std::make_tuple(r.P, TJ, TI)].push_back(g);
             }
-          size_t before = p.updates.size();
-          cut_rect(s, p, J, r, atomic, p.updates, p.flops_tiles);
-          if (atomic) p.n_atomic_tiles += (int64_t)(p.updates.size() - before);
         }
-      for (int64_t J : finished)
-        for (const Rect& r : rects[J])
-          if (r.diag)
-            for (int64_t c = 0; c < r.nc; ++c) colcnt[s.sn_ptr[r.P] + r.c0 + c] = 0;
+      }
+      for (auto& kv : by_tile) {
+        int64_t P = std::get<0>(kv.first), TJ = std::get<1>(kv.first), TI = std::get<2>(kv.first);
+        int64_t mP = M(P), wP = W(P);
+        bool diag = TI == TJ;
+        UpdTile t;
+        t.c = p.off[P] + TJ * TN * mP + TI * TM;
+        t.ldc = (int32_t)mP;
+        t.m = (int32_t)std::min<int64_t>(TM, mP - TI * TM);
+        t.n = (int32_t)std::min<int64_t>(TN, wP - TJ * TN);
+        t.flags = diag ? FLAG_DIAG : 0;
+        if (kv.second.size() > 1) p.n_merged_tiles++;
+        for (const UpdSeg& g : kv.second) {
+          p.flops_tiles += seg_exec_flops(g.ra, g.rb, g.ca, g.cb, g.k);
+          p.flops_upd_alg += 2.0 * (double)g.k * seg_entries(g.ra, g.rb, g.ca, g.cb, diag);
+        }
+        // one workgroup while the tile's K chunks fit the budget; otherwise
+        // consecutive pieces of its contribution list (cut inside a
+        // contribution's k range where needed), each added atomically
+        int64_t chunks = 0;
+        for (const UpdSeg& g : kv.second) chunks += (g.k + KCH - 1) / KCH;
+        if (chunks <= WG_CHUNKS) {
+          t.seg0 = (int32_t)p.segs.size();
+          t.nseg = (int32_t)kv.second.size();
+          p.segs.insert(p.segs.end(), kv.second.begin(), kv.second.end());
+          p.updates.push_back(t);
+          continue;
+        }
+        t.flags |= FLAG_ATOMIC;
+        t.seg0 = (int32_t)p.segs.size();
+        t.nseg = 0;
+        int64_t used = 0;
+        for (const UpdSeg& g : kv.second) {
+          for (int64_t k0 = 0; k0 < g.k;) {
+            int64_t take = std::min<int64_t>(g.k - k0, (WG_CHUNKS - used) * KCH);
+            UpdSeg piece = g;
+            piece.x += k0 * g.lds;
+            piece.y += k0 * g.lds;
+            piece.k = (int32_t)take;
+            p.segs.push_back(piece);
+            t.nseg++;
+            used += (take + KCH - 1) / KCH;
+            k0 += take;
+            if (used >= WG_CHUNKS) {
+              p.updates.push_back(t);
+              p.n_split_tiles++;
+              t.seg0 = (int32_t)p.segs.size();
+              t.nseg = 0;
+              used = 0;
+            }
+          }
+        }
+        if (t.nseg) {
+          p.updates.push_back(t);
+          p.n_split_tiles++;
+        }
+      }
+      // the heaviest workgroups first
+      {
+        std::vector<std::pair<int64_t, size_t>> order;
+        for (size_t i = (size_t)lu.start; i < p.updates.size(); ++i) {
+          int64_t ch = 0;
+          for (int32_t e = 0; e < p.updates[i].nseg; ++e)
+            ch += (p.segs[p.updates[i].seg0 + e].k + KCH - 1) / KCH;
+          order.push_back({-ch, i});
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<int64_t, size_t>& a, const std::pair<int64_t, size_t>& b) {
+                           return a.first < b.first;
+                         });
+        std::vector<UpdTile> sorted;
+        for (auto& o : order) sorted.push_back(p.updates[o.second]);
+        std::copy(sorted.begin(), sorted.end(), p.updates.begin() + lu.start);
+      }
       lu.count = (int64_t)p.updates.size() - lu.start;
       if (lu.count) p.launches.push_back(lu);
     }

@@ -19,24 +19,40 @@ struct AnalyzeOptions {
   int tile_policy = 0;
 };
 
-// One dense update C -= X * Y^T into factor storage, cut to at most a 64x64
-// output tile. Offsets are element offsets into the factor buffer.
+// One 64x64 (or smaller) target tile of factor storage and the list of its
+// contributions C -= X * Y^T in one update launch. A target tile of a launch
+// is normally owned by one workgroup, which sums all contributions (from the
+// trailing update of the tile's own supernode, or from the SYRK/GEMM updates
+// of every supernode of the launch that touches the tile) and writes the tile
+// once; a tile with more work than one workgroup should take is cut into
+// several entries that add their parts atomically. Offsets are element
+// offsets into the factor buffer.
 struct UpdTile {
-  int64_t c;        // target tile origin
-  int64_t x;        // first source row of X at its first column
-  int64_t y;        // first source row of Y at its first column
-  int32_t ldc;      // leading dimension of the target panel
-  int32_t lds;      // leading dimension of the source panel
-  int32_t m, n, k;  // tile rows, tile columns, inner dimension
-  int32_t flags;    // bit0: diagonal tile (write only row >= col); bit1: atomic
-  int32_t src;      // source supernode (for per-panel scales)
+  int64_t c;     // target tile origin
+  int32_t ldc;   // leading dimension of the target panel
+  int32_t m, n;  // tile rows, tile columns
+  int32_t flags; // bit0: tile on the diagonal of its supernode (write only row >= col);
+                 // bit1: one of several workgroups of a split tile (adds atomically)
+  int32_t seg0;  // first contribution
+  int32_t nseg;  // number of contributions
 };
-static_assert(sizeof(UpdTile) == 56, "UpdTile layout");
+static_assert(sizeof(UpdTile) == 32, "UpdTile layout");
 
-// Work item of the cdiv of a <=64-wide column block.
-//   mode 1: POTRF of the diagonal tile, written back in place
-//   mode 2: TRSM of rows [row0, row0+64) below the tile against the factored
-//           tile (a later launch than the block's mode-1 item)
+// One source supernode's contribution to a target tile: tile rows [ra, rb)
+// and columns [ca, cb) receive X * Y^T, where X row r is source row
+// x + (r - ra) and Y row c is source row y + (c - ca), over k source columns.
+struct UpdSeg {
+  int64_t x;     // source offset of the X row that meets tile row ra, column 0
+  int64_t y;     // source offset of the Y row that meets tile column ca, column 0
+  int32_t lds;   // leading dimension of the source panel
+  int32_t k;     // inner dimension (source columns)
+  int32_t ra, rb, ca, cb;
+  int32_t src;   // source supernode (for per-panel scales)
+  int32_t pad;
+};
+static_assert(sizeof(UpdSeg) == 48, "UpdSeg layout");
+
+// Work item of the cdiv of a <=64-wide column block (see k_panel).
 struct PanelTile {
   int64_t diag;       // offset of the diagonal tile's top-left element
   int32_t ld;         // leading dimension of the panel
@@ -45,15 +61,14 @@ struct PanelTile {
   int32_t row0;       // first row handled here, relative to the diagonal tile
   int32_t col;        // factored-order index of the block's first column
   int32_t slot;       // status slot (matrix index in a batch)
-  int32_t mode;
-  int32_t pad;
+  int32_t grp;        // counter of the group of tiles sharing this diagonal tile
+  int32_t gcnt;       // number of tiles in the group
 };
 static_assert(sizeof(PanelTile) == 40, "PanelTile layout");
 
 // launch kinds, in execution order inside one (level, step)
-constexpr int32_t LAUNCH_POTRF = 0;
-constexpr int32_t LAUNCH_TRSM = 1;
-constexpr int32_t LAUNCH_UPDATE = 2;
+constexpr int32_t LAUNCH_PANEL = 0;
+constexpr int32_t LAUNCH_UPDATE = 1;
 
 struct Launch {
   int32_t kind;   // LAUNCH_*
@@ -71,6 +86,7 @@ struct Plan {
   std::vector<int64_t> amap;  // input CSC entry -> position in factor storage
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
+  std::vector<UpdSeg> segs;
   std::vector<Launch> launches;
   int32_t nlevels = 0;
   std::vector<int32_t> level;       // height of every supernode
@@ -80,8 +96,10 @@ struct Plan {
   std::vector<int64_t> a_rowptr;
   std::vector<int32_t> a_col;
   std::vector<int64_t> a_src;
-  int64_t n_atomic_tiles = 0;
-  double flops_tiles = 0;  // flops the update tiles execute (full 64x64 MFMA work)
+  int64_t n_merged_tiles = 0;  // target tiles that sum contributions of several supernodes
+  int64_t n_split_tiles = 0;   // workgroups of target tiles split for load balance
+  int32_t max_groups = 0;  // largest number of tile groups in one panel launch
+  double flops_tiles = 0;  // flops the update tiles execute (the 16x16 MFMA blocks they touch)
   double flops_upd_alg = 0;  // algorithmic flops of the update tiles (entries written x 2k)
   double flops_panel = 0;    // flops of the POTRF + TRSM column blocks
 };

@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
                 ("flops_exact", ctypes.c_double), ("flops_padded", ctypes.c_double)] + [
                 (k, ctypes.c_int64) for k in
                 ("n_blocks", "n_pairs", "n_calls", "merge_added", "merge_base", "factor_bytes",
-                 "n_panel_tiles", "n_update_tiles", "n_atomic_tiles", "n_launches")] + [
+                 "n_panel_tiles", "n_update_tiles", "n_merged_tiles", "n_split_tiles",
+                 "n_launches")] + [
                 ("flops_tiles", ctypes.c_double), ("flops_upd_alg", ctypes.c_double),
                 ("flops_panel", ctypes.c_double)]
 

@@ -54,9 +54,8 @@ struct DevPlan {
   UpdTile* updates = nullptr;
   UpdSeg* segs = nullptr;
   int64_t* amap = nullptr;
-  SnMeta* meta = nullptr;
+  SolveTile* stiles = nullptr;
   int32_t* gl = nullptr;
-  int32_t* lvl_sn = nullptr;
   int64_t* perm = nullptr;
   int64_t* a_rowptr = nullptr;
   int32_t* a_col = nullptr;
@@ -66,9 +65,8 @@ struct DevPlan {
     dfree(updates);
     dfree(segs);
     dfree(amap);
-    dfree(meta);
+    dfree(stiles);
     dfree(gl);
-    dfree(lvl_sn);
     dfree(perm);
     dfree(a_rowptr);
     dfree(a_col);
@@ -76,25 +74,13 @@ struct DevPlan {
   }
 };
 
-std::vector<SnMeta> make_meta(const Symbolic& s, int64_t base) {
-  int64_t S = (int64_t)s.sn_ptr.size() - 1;
-  std::vector<SnMeta> meta(S);
-  for (int64_t J = 0; J < S; ++J) {
-    meta[J].off = base + s.plan.off[J];
-    meta[J].f = (int32_t)s.sn_ptr[J];
-    meta[J].w = (int32_t)(s.sn_ptr[J + 1] - s.sn_ptr[J]);
-    meta[J].m = (int32_t)(s.gl_ptr[J + 1] - s.gl_ptr[J]);
-    meta[J].gl = (int32_t)s.gl_ptr[J];
-  }
-  return meta;
-}
-
 // solve/refine data (no factor tiles)
 rlb_status upload_solve(const Symbolic& s, int64_t base, DevPlan& d) {
   rlb_status st;
-  if ((st = upload(&d.meta, make_meta(s, base)))) return st;
+  std::vector<SolveTile> tiles = s.plan.stiles;
+  for (SolveTile& t : tiles) t.off += base;
+  if ((st = upload(&d.stiles, tiles))) return st;
   if ((st = upload(&d.gl, s.gl))) return st;
-  if ((st = upload(&d.lvl_sn, s.plan.lvl_sn))) return st;
   if ((st = upload(&d.perm, s.perm))) return st;
   if ((st = upload(&d.a_rowptr, s.plan.a_rowptr))) return st;
   if ((st = upload(&d.a_col, s.plan.a_col))) return st;
@@ -104,7 +90,9 @@ rlb_status upload_solve(const Symbolic& s, int64_t base, DevPlan& d) {
 
 // scratch for the solves and the refinement of one matrix
 struct SolveScratch {
-  double* y = nullptr;  // n x SOLVE_MAXRHS
+  double* y = nullptr;  // n x SOLVE_MAXRHS: right-hand side in the factored order
+  double* z = nullptr;  // forward solution
+  double* x = nullptr;  // backward solution
   double* r = nullptr;
   double* d = nullptr;
   unsigned long long* norms = nullptr;  // 3*SOLVE_MAXRHS + 1
@@ -115,6 +103,8 @@ struct SolveScratch {
     n = n_;
     size_t bytes = (size_t)std::max<int64_t>(n, 1) * SOLVE_MAXRHS * sizeof(double);
     HIP_OK(hipMalloc((void**)&y, bytes));
+    HIP_OK(hipMalloc((void**)&z, bytes));
+    HIP_OK(hipMalloc((void**)&x, bytes));
     HIP_OK(hipMalloc((void**)&r, bytes));
     HIP_OK(hipMalloc((void**)&d, bytes));
     HIP_OK(hipMalloc((void**)&norms, (3 * SOLVE_MAXRHS + 1) * sizeof(unsigned long long)));
@@ -122,6 +112,8 @@ struct SolveScratch {
   }
   void release() {
     dfree(y);
+    dfree(z);
+    dfree(x);
     dfree(r);
     dfree(d);
     dfree(norms);
@@ -129,16 +121,18 @@ struct SolveScratch {
 };
 
 // forward then backward supernodal solve of nrhs (<= SOLVE_MAXRHS) columns
-// already gathered into y (factored order, ld = n)
-void enqueue_solve_levels(const Symbolic& s, const DevPlan& d, const double* L, double* y,
+// already gathered into sc.y (factored order, ld = n); the solution ends in sc.x
+void enqueue_solve_levels(const Symbolic& s, const DevPlan& d, const double* L, SolveScratch& sc,
                           int nrhs, hipStream_t st) {
-  const Plan& p = s.plan;
-  for (int32_t h = 0; h < p.nlevels; ++h)
-    launch_fwd(d.lvl_sn + p.lvl_ptr[h], p.lvl_ptr[h + 1] - p.lvl_ptr[h], d.meta, d.gl, L, y,
-               nrhs, s.n, st);
-  for (int32_t h = p.nlevels - 1; h >= 0; --h)
-    launch_bwd(d.lvl_sn + p.lvl_ptr[h], p.lvl_ptr[h + 1] - p.lvl_ptr[h], d.meta, d.gl, L, y,
-               nrhs, s.n, st);
+  for (const SolveLaunch& l : s.plan.slaunches) {
+    const SolveTile* t = d.stiles + l.start;
+    if (l.kind == SOLVE_FWD)
+      launch_fwd_step(t, l.count, d.gl, L, sc.y, sc.z, nrhs, s.n, st);
+    else if (l.kind == SOLVE_BELOW)
+      launch_bwd_below(t, l.count, d.gl, L, sc.x, sc.z, nrhs, s.n, st);
+    else
+      launch_bwd_step(t, l.count, L, sc.z, sc.x, nrhs, s.n, st);
+  }
 }
 
 rlb_status solve_into(const Symbolic& s, const DevPlan& d, SolveScratch& sc, const double* L,
@@ -149,8 +143,8 @@ rlb_status solve_into(const Symbolic& s, const DevPlan& d, SolveScratch& sc, con
   for (int64_t c0 = 0; c0 < nrhs; c0 += SOLVE_MAXRHS) {
     int nr = (int)std::min<int64_t>(SOLVE_MAXRHS, nrhs - c0);
     launch_perm_in(d.perm, B + c0 * ldb, ldb, sc.y, s.n, s.n, nr, st);
-    enqueue_solve_levels(s, d, L, sc.y, nr, st);
-    launch_perm_out(d.perm, sc.y, s.n, X + c0 * ldx, ldx, s.n, nr, st);
+    enqueue_solve_levels(s, d, L, sc, nr, st);
+    launch_perm_out(d.perm, sc.x, s.n, X + c0 * ldx, ldx, s.n, nr, st);
   }
   HIP_OK(hipGetLastError());
   return RLB_OK;
@@ -405,6 +399,16 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       int64_t v[7] = {t.c, t.ldc, t.m, t.n, t.flags, t.seg0, t.nseg};
       tmp.insert(tmp.end(), v, v + 7);
     }
+  } else if (w == "solve_tiles") {  // off, ld, f, w, gl, c0, nb, r0, r1, flags, pad per tile
+    for (const SolveTile& t : s.plan.stiles) {
+      int64_t v[11] = {t.off, t.ld, t.f, t.w, t.gl, t.c0, t.nb, t.r0, t.r1, t.flags, t.pad};
+      tmp.insert(tmp.end(), v, v + 11);
+    }
+  } else if (w == "solve_launches") {  // kind, level, first tile, tile count per launch
+    for (const SolveLaunch& l : s.plan.slaunches) {
+      int64_t v[4] = {l.kind, l.level, l.start, l.count};
+      tmp.insert(tmp.end(), v, v + 4);
+    }
   } else if (w == "update_segs") {  // x, y, lds, k, ra, rb, ca, cb, src per contribution
     for (const UpdSeg& g : s.plan.segs) {
       int64_t v[9] = {g.x, g.y, g.lds, g.k, g.ra, g.rb, g.ca, g.cb, g.src};
@@ -607,8 +611,8 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
     }
     // d = solve(r), X += d  (r = B - A X was left in the scratch by backward_errors)
     launch_perm_in(h->d.perm, h->sc.r, s.n, h->sc.y, s.n, s.n, (int)nrhs, st);
-    enqueue_solve_levels(s, h->d, h->L, h->sc.y, (int)nrhs, st);
-    launch_perm_out(h->d.perm, h->sc.y, s.n, h->sc.d, s.n, s.n, (int)nrhs, st);
+    enqueue_solve_levels(s, h->d, h->L, h->sc, (int)nrhs, st);
+    launch_perm_out(h->d.perm, h->sc.x, s.n, h->sc.d, s.n, s.n, (int)nrhs, st);
     launch_axpy(X, ld, h->sc.d, s.n, s.n, (int)nrhs, st);
     HIP_OK(hipGetLastError());
     ++it;

@@ -7,13 +7,6 @@
 
 namespace rlb {
 
-struct SnMeta {
-  int64_t off;  // Lnz(J) offset in factor storage
-  int32_t f;    // first column
-  int32_t w;    // width
-  int32_t m;    // rows
-  int32_t gl;   // offset of glbind(J) in the index array
-};
 
 constexpr int SOLVE_MAXRHS = 16;
 
@@ -27,10 +20,12 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, hipStream_t st);
-void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
-                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st);
-void launch_bwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
-                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st);
+void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
+                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st);
+void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
+                      const double* x, double* z, int nrhs, int64_t ldy, hipStream_t st);
+void launch_bwd_step(const SolveTile* tiles, int64_t count, const double* L, double* z, double* x,
+                     int nrhs, int64_t ldy, hipStream_t st);
 void launch_perm_in(const int64_t* perm, const double* b, int64_t ldb, double* y, int64_t ldy,
                     int64_t n, int nrhs, hipStream_t st);
 void launch_perm_out(const int64_t* perm, const double* y, int64_t ldy, double* x, int64_t ldx,

@@ -10,7 +10,9 @@
 //    storage: the in-supernode trailing update and the SYRK/GEMM updates
 //    written directly into ancestors (Alg. 5 lines 11-16), on MFMA 16x16x4
 //    (FP64, or FP32 operands with FP32 accumulation in the mixed form).
-//  * solves, SpMV residual, norms.
+//  * k_fwd_step / k_bwd_below / k_bwd_step -- supernodal solves in 64-column
+//    steps, the diagonal chunks as products with the stored inv(L_kk).
+//  * SpMV residual, norms.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -554,172 +556,217 @@ template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
 
 // ---------------------------------------------------------------------------
-// supernodal solves, one workgroup per supernode of a level.
-// y is n x nrhs column-major (ld = ldy) in the factored order.
+// Supernodal solves L z = y and L^T x = z in the factored order (vectors
+// n x nrhs column-major, nrhs <= 16), in the 64-column steps of the
+// factorization. The diagonal chunk of a step is solved as a product with
+// inv(L_kk), which the factorization left in the chunk's unused strict upper
+// triangle (inv(L)(i,j), i > j, at row j of column i) together with 1/L(i,i).
+// Every workgroup of a step forms the chunk's solution itself from the
+// finished right-hand side, so the step needs no second launch; the first
+// workgroup of the supernode also stores it.
 
-static_assert(sizeof(SnMeta) == 24, "SnMeta layout");
-
-constexpr int SB = 64;  // columns per in-LDS triangular chunk of the solves
 constexpr int MAXRHS = SOLVE_MAXRHS;
+constexpr int VP = 65;  // LDS pitch of a staged 64x64 block
 
-// Stage the nb x nb diagonal chunk of L at (c0, c0) into Ld (identity beyond nb).
-__device__ __forceinline__ void stage_chunk(double (*Ld)[SB + 1], const double* Lj, int64_t ld,
-                                            int c0, int nb, int tid) {
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int col = e / SB, row = e % SB;
-    double v = (row == col) ? 1.0 : 0.0;
-    if (row < nb && col < nb && row >= col) v = Lj[(int64_t)(c0 + col) * ld + c0 + row];
-    Ld[row][col] = v;
+// inv(L_kk) of the chunk at (c0, c0) into V, row-major: V[i*VP + j] = inv(i,j),
+// zero above the diagonal and beyond nb. 256 threads, coalesced loads.
+__device__ __forceinline__ void stage_inv(double* V, const double* Lj, int64_t ld, int c0,
+                                          int nb, int tid) {
+  const int row = tid & 63, cg = tid >> 6;
+  const int rr = min(row, nb - 1);
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int col = min(cg + 4 * q, nb - 1);
+    v[q] = Lj[(int64_t)(c0 + col) * ld + c0 + rr];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int col = cg + 4 * q;
+    double e = 0.0;
+    if (row < nb && col < nb) e = row < col ? v[q] : (row == col ? 1.0 / v[q] : 0.0);
+    V[col * VP + row] = e;  // stored (row, col), row < col, is inv(col, row)
   }
 }
 
-// Forward solve L y = b for the supernodes of one level, one workgroup each.
-// Per 64-column chunk: triangle in LDS (one wavefront per right-hand side,
-// lane = row, pivots broadcast with readlane), then a coalesced GEMV for every
-// row below the chunk (own rows plainly, ancestor rows with atomics).
-__global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ sns,
-                                             const SnMeta* __restrict__ meta,
-                                             const int32_t* __restrict__ gl,
-                                             const double* __restrict__ L,
-                                             double* __restrict__ y, int nrhs, int64_t ldy) {
-  const SnMeta s = meta[sns[blockIdx.x]];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double* Lj = L + s.off;
-  const int64_t ld = s.m;
-  const int32_t* g = gl + s.gl;
-  __shared__ double Ld[SB][SB + 1];
-  __shared__ double xs[MAXRHS][SB];
-  for (int c0 = 0; c0 < s.w; c0 += SB) {
-    const int nb = min(SB, s.w - c0);
-    stage_chunk(Ld, Lj, ld, c0, nb, tid);
-    for (int e = tid; e < SB * nrhs; e += 256) {
-      const int c = e % SB, r = e / SB;
-      xs[r][c] = c < nb ? y[(int64_t)r * ldy + s.f + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int r = wave; r < nrhs; r += 4) {
-      double yj = xs[r][lane];
-      for (int c = 0; c < nb; ++c) {
-        const double xc = lane_bcast(yj, c) / Ld[c][c];
-        if (lane == c) yj = xc;
-        if (lane > c) yj -= Ld[lane][c] * xc;
-      }
-      xs[r][lane] = yj;
-    }
-    __syncthreads();
-    for (int e = tid; e < nb * nrhs; e += 256) {
-      const int c = e % nb, r = e / nb;
-      y[(int64_t)r * ldy + s.f + c0 + c] = xs[r][c];
-    }
-    const int q0 = c0 + nb;
-    for (int q = q0 + tid; q < s.m + 255; q += 256) {
-      // one row per thread; all 64 column loads in flight (coalesced across
-      // threads), clamped to valid slots
-      const int qq = min(q, s.m - 1);
-      const double* lq = Lj + qq;
-      double l[SB];
+// forward step: x_k = inv(L_kk) y_k (stored into z by the writer), then
+// y(rows r0..r1 of the supernode) -= L(rows, chunk) x_k, one row per thread;
+// own rows plainly, ancestor rows (through glbind) with atomics
+__global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ tiles,
+                                                  const int32_t* __restrict__ gl,
+                                                  const double* __restrict__ L,
+                                                  double* __restrict__ y, double* __restrict__ z,
+                                                  int nrhs, int64_t ldy) {
+  const SolveTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double* Lj = L + t.off;
+  const int64_t ld = t.ld;
+  __shared__ double V[64 * VP];
+  __shared__ double ys[MAXRHS][64];
+  __shared__ double xs[MAXRHS][64];
+  // this thread's row of the GEMV: all 64 loads issued before the chunk solve
+  const int q = t.r0 + tid;
+  const int qq = min(q, t.ld - 1);
+  double l[64];
 #pragma unroll
-      for (int c = 0; c < SB; ++c) l[c] = lq[(int64_t)(c0 + min(c, nb - 1)) * ld];
-      if (q < s.m) {
-        const int gq = g[q];
-        for (int r = 0; r < nrhs; ++r) {
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-          for (int c = 0; c < SB; c += 2) {
-            a0 += l[c] * xs[r][c];         // xs is 0 beyond nb
-            a1 += l[c + 1] * xs[r][c + 1];
-          }
-          const double acc = a0 + a1;
-          if (q < s.w)
-            y[(int64_t)r * ldy + gq] -= acc;
-          else
-            atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
-        }
-      }
+  for (int c = 0; c < 64; ++c) l[c] = Lj[(int64_t)(t.c0 + min(c, t.nb - 1)) * ld + qq];
+  stage_inv(V, Lj, ld, t.c0, t.nb, tid);
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int i = e & 63, r = e >> 6;
+    ys[r][i] = i < t.nb ? y[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int i = e & 63, r = e >> 6;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < 64; j += 2) {
+      a0 += V[i * VP + j] * ys[r][j];
+      a1 += V[i * VP + j + 1] * ys[r][j + 1];
     }
-    __syncthreads();
+    xs[r][i] = a0 + a1;
+  }
+  __syncthreads();
+  if (t.flags & 1)
+    for (int e = tid; e < 64 * nrhs; e += 256) {
+      const int i = e & 63, r = e >> 6;
+      if (i < t.nb) z[(int64_t)r * ldy + t.f + t.c0 + i] = xs[r][i];
+    }
+  if (q < t.r1) {
+    const int gq = gl[t.gl + q];
+    for (int r = 0; r < nrhs; ++r) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 64; c += 2) {
+        a0 += l[c] * xs[r][c];  // xs is 0 beyond nb
+        a1 += l[c + 1] * xs[r][c + 1];
+      }
+      const double acc = a0 + a1;
+      if (q < t.w)
+        y[(int64_t)r * ldy + gq] -= acc;
+      else
+        atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
+    }
   }
 }
 
-// Backward solve L^T x = y, levels from the root down, one workgroup per
-// supernode. Chunks from the last: every column of the chunk first subtracts
-// its dot product with the already final x of all rows below the chunk (own
-// rows and ancestors alike, both read through glbind), one wavefront per
-// column with a wave reduction; then the chunk's triangle is solved in LDS.
-__global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ sns,
-                                             const SnMeta* __restrict__ meta,
-                                             const int32_t* __restrict__ gl,
-                                             const double* __restrict__ L,
-                                             double* __restrict__ y, int nrhs, int64_t ldy) {
-  const SnMeta s = meta[sns[blockIdx.x]];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double* Lj = L + s.off;
-  const int64_t ld = s.m;
-  const int32_t* g = gl + s.gl;
-  __shared__ double Ld[SB][SB + 1];
-  __shared__ double xs[MAXRHS][SB];
-  __shared__ double part[4][MAXRHS][SB];
-  const int nchunks = (s.w + SB - 1) / SB;
-  for (int ch = nchunks - 1; ch >= 0; --ch) {
-    const int c0 = ch * SB, nb = min(SB, s.w - c0), q0 = c0 + nb;
-    stage_chunk(Ld, Lj, ld, c0, nb, tid);
-    // column dot products over the rows below the chunk: lane = column, each
-    // wave walks a quarter of the rows (8 rows in flight per iteration); the
-    // four partial sums meet in LDS
-    {
-      const int c = min(lane, nb - 1);
-      const double* col = Lj + (int64_t)(c0 + c) * ld;
-      const int rows = s.m - q0;
-      const int per = (rows + 3) / 4;
-      const int qa = q0 + wave * per, qe = min(s.m, qa + per);
-      double acc[MAXRHS];
+// backward, ancestor rows: z(chunk columns) -= L(rows r0..r1, chunk)^T x(glbind rows),
+// 64-row blocks staged in LDS (the next block's loads in flight), added atomically
+__global__ __launch_bounds__(256) void k_bwd_below(const SolveTile* __restrict__ tiles,
+                                                   const int32_t* __restrict__ gl,
+                                                   const double* __restrict__ L,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ z, int nrhs,
+                                                   int64_t ldy) {
+  const SolveTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6;
+  const double* Lj = L + t.off;
+  const int64_t ld = t.ld;
+  __shared__ double Lb[64][VP];      // Lb[row][col] = L(q0 + row, c0 + col)
+  __shared__ double xr[MAXRHS][64];  // x of the block's rows
+  double acc[MAXRHS / 4];
 #pragma unroll
-      for (int r = 0; r < MAXRHS; ++r) acc[r] = 0.0;
-      for (int q = qa; q < qe; q += 8) {
-        double l[8];
-        int gq[8];
+  for (int s = 0; s < MAXRHS / 4; ++s) acc[s] = 0.0;
+  double v[16], xv[MAXRHS / 4];
+  auto fetch = [&](int q0) {
+    const int nrow = min(64, t.r1 - q0);
+    const int qq = q0 + min(row, nrow - 1);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int qq = min(q + u, qe - 1);
-          l[u] = (q + u < qe) ? col[qq] : 0.0;
-          gq[u] = g[qq];
+    for (int s = 0; s < 16; ++s) v[s] = Lj[(int64_t)(t.c0 + min(cg + 4 * s, t.nb - 1)) * ld + qq];
+    const int gq = gl[t.gl + qq];
+#pragma unroll
+    for (int s = 0; s < MAXRHS / 4; ++s) {
+      const int r = cg + 4 * s;
+      xv[s] = r < nrhs ? x[(int64_t)r * ldy + gq] : 0.0;
+    }
+  };
+  fetch(t.r0);
+  for (int q0 = t.r0; q0 < t.r1; q0 += 64) {
+    const int nrow = min(64, t.r1 - q0);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) Lb[row][cg + 4 * s] = (row < nrow && cg + 4 * s < t.nb) ? v[s] : 0.0;
+#pragma unroll
+    for (int s = 0; s < MAXRHS / 4; ++s) xr[cg + 4 * s][row] = row < nrow ? xv[s] : 0.0;
+    __syncthreads();
+    if (q0 + 64 < t.r1) fetch(q0 + 64);
+#pragma unroll
+    for (int s = 0; s < MAXRHS / 4; ++s) {
+      const int r = cg + 4 * s;
+      if (r < nrhs) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < 64; i += 2) {
+          a0 += Lb[i][row] * xr[r][i];
+          a1 += Lb[i + 1][row] * xr[r][i + 1];
         }
-#pragma unroll
-        for (int r = 0; r < MAXRHS; ++r) {
-          if (r < nrhs) {
-            double yv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) yv[u] = y[(int64_t)r * ldy + gq[u]];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc[r] += l[u] * yv[u];
-          }
-        }
+        acc[s] += a0 + a1;
       }
-      for (int r = 0; r < nrhs; ++r) part[wave][r][lane] = acc[r];
-    }
-    __syncthreads();
-    for (int e = tid; e < nb * nrhs; e += 256) {
-      const int c = e % nb, r = e / nb;
-      const double d = (part[0][r][c] + part[1][r][c]) + (part[2][r][c] + part[3][r][c]);
-      xs[r][c] = y[(int64_t)r * ldy + s.f + c0 + c] - d;
-    }
-    __syncthreads();
-    for (int r = wave; r < nrhs; r += 4) {
-      double yj = lane < nb ? xs[r][lane] : 0.0;
-      for (int c = nb - 1; c >= 0; --c) {
-        const double xc = lane_bcast(yj, c) / Ld[c][c];
-        if (lane == c) yj = xc;
-        if (lane < c) yj -= Ld[c][lane] * xc;
-      }
-      if (lane < nb) xs[r][lane] = yj;
-    }
-    __syncthreads();
-    for (int e = tid; e < nb * nrhs; e += 256) {
-      const int c = e % nb, r = e / nb;
-      y[(int64_t)r * ldy + s.f + c0 + c] = xs[r][c];
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int s = 0; s < MAXRHS / 4; ++s) {
+    const int r = cg + 4 * s;
+    if (r < nrhs && row < t.nb) atomicAdd(&z[(int64_t)r * ldy + t.f + t.c0 + row], -acc[s]);
+  }
+}
+
+// backward step: x_k = inv(L_kk)^T z_k (stored into x by the writer), then
+// z(columns r0..r1) -= L(chunk rows, r0..r1)^T x_k for one earlier chunk
+__global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ tiles,
+                                                  const double* __restrict__ L,
+                                                  double* __restrict__ z, double* __restrict__ x,
+                                                  int nrhs, int64_t ldy) {
+  const SolveTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6;
+  const double* Lj = L + t.off;
+  const int64_t ld = t.ld;
+  const bool push = t.r1 > t.r0;
+  __shared__ double V[64 * VP];
+  __shared__ double Lb[64][VP];  // Lb[i][c] = L(c0 + i, r0 + c)
+  __shared__ double zs[MAXRHS][64];
+  __shared__ double xs[MAXRHS][64];
+  if (push) {
+    double v[16];
+    const int ii = min(row, t.nb - 1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = Lj[(int64_t)(t.r0 + cg + 4 * s) * ld + t.c0 + ii];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) Lb[row][cg + 4 * s] = row < t.nb ? v[s] : 0.0;
+  }
+  stage_inv(V, Lj, ld, t.c0, t.nb, tid);
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int i = e & 63, r = e >> 6;
+    zs[r][i] = i < t.nb ? z[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int i = e & 63, r = e >> 6;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < 64; m += 2) {
+      a0 += V[m * VP + i] * zs[r][m];
+      a1 += V[(m + 1) * VP + i] * zs[r][m + 1];
+    }
+    xs[r][i] = a0 + a1;
+  }
+  __syncthreads();
+  if (t.flags & 1)
+    for (int e = tid; e < 64 * nrhs; e += 256) {
+      const int i = e & 63, r = e >> 6;
+      if (i < t.nb) x[(int64_t)r * ldy + t.f + t.c0 + i] = xs[r][i];
+    }
+  if (push)
+    for (int e = tid; e < 64 * nrhs; e += 256) {
+      const int c = e & 63, r = e >> 6;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < 64; i += 2) {
+        a0 += Lb[i][c] * xs[r][i];
+        a1 += Lb[i + 1][c] * xs[r][i + 1];
+      }
+      z[(int64_t)r * ldy + t.f + t.r0 + c] -= a0 + a1;
+    }
 }
 
 // y[k] = b[perm[k]] (gather into the factored order) and back
@@ -836,16 +883,22 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     hipLaunchKernelGGL(k_update<double>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs,
                        L);
 }
-void launch_fwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
-                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st) {
+void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
+                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_fwd, dim3((unsigned)count), dim3(256), 0, st, sns, meta, gl, L, y, nrhs,
-                     ldy);
+  hipLaunchKernelGGL(k_fwd_step, dim3((unsigned)count), dim3(256), 0, st, tiles, gl, L, y, z,
+                     nrhs, ldy);
 }
-void launch_bwd(const int32_t* sns, int64_t count, const SnMeta* meta, const int32_t* gl,
-                const double* L, double* y, int nrhs, int64_t ldy, hipStream_t st) {
+void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
+                      const double* x, double* z, int nrhs, int64_t ldy, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_bwd, dim3((unsigned)count), dim3(256), 0, st, sns, meta, gl, L, y, nrhs,
+  hipLaunchKernelGGL(k_bwd_below, dim3((unsigned)count), dim3(256), 0, st, tiles, gl, L, x, z,
+                     nrhs, ldy);
+}
+void launch_bwd_step(const SolveTile* tiles, int64_t count, const double* L, double* z, double* x,
+                     int nrhs, int64_t ldy, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_bwd_step, dim3((unsigned)count), dim3(256), 0, st, tiles, L, z, x, nrhs,
                      ldy);
 }
 void launch_perm_in(const int64_t* perm, const double* b, int64_t ldb, double* y, int64_t ldy,

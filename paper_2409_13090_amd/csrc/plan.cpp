@@ -363,6 +363,85 @@ int build_plan(Symbolic& s, std::string& err) {
       if (lu.count) p.launches.push_back(lu);
     }
   }
+  // solves: forward by level and 64-column step (row tiles of 256 below the
+  // chunk), backward by level from the root: first every column chunk against
+  // the ancestor rows (segments of 512 rows), then the steps from the last
+  // chunk down, each pushing into the earlier chunks of its supernode
+  {
+    auto base_tile = [&](int64_t J) {
+      SolveTile t;
+      t.off = p.off[J];
+      t.ld = (int32_t)M(J);
+      t.f = (int32_t)s.sn_ptr[J];
+      t.w = (int32_t)W(J);
+      t.gl = (int32_t)s.gl_ptr[J];
+      t.c0 = t.nb = t.r0 = t.r1 = t.flags = t.pad = 0;
+      return t;
+    };
+    auto push_launch = [&](int32_t kind, int32_t h, int64_t start) {
+      int64_t cnt = (int64_t)p.stiles.size() - start;
+      if (cnt) p.slaunches.push_back(SolveLaunch{kind, h, start, cnt});
+    };
+    for (int32_t h = 0; h < p.nlevels; ++h) {
+      int64_t steps = 0;
+      for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
+        steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
+      for (int64_t k = 0; k < steps; ++k) {
+        int64_t start = (int64_t)p.stiles.size();
+        for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+          int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
+          if (k * NB >= w) continue;
+          SolveTile t = base_tile(J);
+          t.c0 = (int32_t)(k * NB);
+          t.nb = (int32_t)std::min<int64_t>(NB, w - k * NB);
+          int64_t lo = t.c0 + t.nb;
+          int64_t nt = std::max<int64_t>(1, (m - lo + 255) / 256);
+          for (int64_t i = 0; i < nt; ++i) {
+            t.r0 = (int32_t)std::min<int64_t>(m, lo + 256 * i);
+            t.r1 = (int32_t)std::min<int64_t>(m, lo + 256 * (i + 1));
+            t.flags = i == 0 ? 1 : 0;
+            p.stiles.push_back(t);
+          }
+        }
+        push_launch(SOLVE_FWD, h, start);
+      }
+    }
+    for (int32_t h = p.nlevels - 1; h >= 0; --h) {
+      int64_t start = (int64_t)p.stiles.size();
+      int64_t steps = 0;
+      for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+        int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
+        steps = std::max<int64_t>(steps, (w + NB - 1) / NB);
+        for (int64_t c0 = 0; c0 < w && m > w; c0 += NB)
+          for (int64_t r = w; r < m; r += 512) {
+            SolveTile t = base_tile(J);
+            t.c0 = (int32_t)c0;
+            t.nb = (int32_t)std::min<int64_t>(NB, w - c0);
+            t.r0 = (int32_t)r;
+            t.r1 = (int32_t)std::min<int64_t>(m, r + 512);
+            p.stiles.push_back(t);
+          }
+      }
+      push_launch(SOLVE_BELOW, h, start);
+      for (int64_t k = steps - 1; k >= 0; --k) {
+        start = (int64_t)p.stiles.size();
+        for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+          int64_t J = p.lvl_sn[q], w = W(J);
+          if (k * NB >= w) continue;
+          SolveTile t = base_tile(J);
+          t.c0 = (int32_t)(k * NB);
+          t.nb = (int32_t)std::min<int64_t>(NB, w - k * NB);
+          for (int64_t j = 0; j < std::max<int64_t>(k, 1); ++j) {
+            t.r0 = (int32_t)(j * NB);
+            t.r1 = (int32_t)(k == 0 ? 0 : j * NB + NB);  // an empty range: only the solve
+            t.flags = j == 0 ? 1 : 0;
+            p.stiles.push_back(t);
+          }
+        }
+        push_launch(SOLVE_BWD, h, start);
+      }
+    }
+  }
   // full symmetric A in the original order, CSR, with the source entry of each value
   p.a_rowptr.assign(n + 1, 0);
   for (int64_t j = 0; j < n; ++j)

@@ -66,6 +66,34 @@ struct PanelTile {
 };
 static_assert(sizeof(PanelTile) == 40, "PanelTile layout");
 
+// Work item of the supernodal solves, one workgroup each (see k_fwd_step,
+// k_bwd_below, k_bwd_step). Columns and rows are relative to the supernode.
+struct SolveTile {
+  int64_t off;   // Lnz(J) offset in factor storage
+  int32_t ld;    // m_J
+  int32_t f;     // first column of J (factored order)
+  int32_t w;     // w_J
+  int32_t gl;    // offset of glbind(J)
+  int32_t c0;    // first column of the chunk solved here
+  int32_t nb;    // chunk width (<= 64)
+  int32_t r0;    // forward / below: first row handled; backward step: first column
+  int32_t r1;    //   of the earlier chunk updated here (end of the range)
+  int32_t flags; // bit0: writes the chunk's solution
+  int32_t pad;
+};
+static_assert(sizeof(SolveTile) == 48, "SolveTile layout");
+
+constexpr int32_t SOLVE_FWD = 0;    // forward step: chunk solve + rows below
+constexpr int32_t SOLVE_BELOW = 1;  // backward: columns against the ancestor rows
+constexpr int32_t SOLVE_BWD = 2;    // backward step: chunk solve + earlier chunks
+
+struct SolveLaunch {
+  int32_t kind;
+  int32_t level;
+  int64_t start;
+  int64_t count;
+};
+
 // launch kinds, in execution order inside one (level, step)
 constexpr int32_t LAUNCH_PANEL = 0;
 constexpr int32_t LAUNCH_UPDATE = 1;
@@ -87,6 +115,8 @@ struct Plan {
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
   std::vector<UpdSeg> segs;
+  std::vector<SolveTile> stiles;      // solve work items, launch by launch
+  std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
   std::vector<Launch> launches;
   int32_t nlevels = 0;
   std::vector<int32_t> level;       // height of every supernode

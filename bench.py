@@ -39,6 +39,7 @@ WORKLOAD_TEXT = {
 }
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_16BIT_TFLOPS = 2516.6  # dense BF16/FP16 MFMA
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by the same counters on a 256 MiB device copy; valid
 # only for the kernel source they were taken on (first 16 hex digits of the
@@ -106,6 +107,8 @@ def main():
                     help="only copy 256 MiB device to device (calibrates the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed", choices=["fp32", "bf16", "fp16"], default=None,
+                    help="update operands of the refined form (default: fp32, bf16 for elast3_40)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the factor's kernels one by one instead of replaying a HIP graph")
     ap.add_argument("--prof-reps", type=int, default=3,
@@ -237,10 +240,14 @@ def main():
     }
 
     if not args.no_mixed:
-        num32 = rlb.Numeric(sym, rlb.RLB_PREC_FP32_UPDATES)
+        mixed = args.mixed or ("bf16" if args.workload == "elast3_40" else "fp32")
+        prec = {"fp32": rlb.RLB_PREC_FP32_UPDATES, "bf16": rlb.RLB_PREC_BF16_UPDATES,
+                "fp16": rlb.RLB_PREC_FP16_UPDATES}[mixed]
+        num32 = rlb.Numeric(sym, prec)
         num32.set_graph_mode(graph)
         ws32 = torch.empty_like(ws)
         ms32, its, tts, be32 = [], [], [], []
+        pcg_from = None
         info32 = 0
         for rep in range(3):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -254,11 +261,12 @@ def main():
             if info32 != 0:
                 break
             X32 = torch.zeros_like(B).T.contiguous().T
-            r = num32.refine(B, X32, tol=1e-14, max_iter=30)
+            r = num32.refine(B, X32, tol=1e-14, max_iter=50)
             torch.cuda.synchronize()
             tts.append(time.perf_counter() - t0)
             ms32.append(e0.elapsed_time(e1))
             its.append(r["iterations"])
+            pcg_from = r["pcg_from"]
             be32.append(max(r["backward_error"]))
         if info32 != 0:
             ms32 = [e0.elapsed_time(e1)] * 2
@@ -275,10 +283,15 @@ def main():
         num.backward_error(B, X)
         torch.cuda.synchronize()
         tts64 = time.perf_counter() - t0
-        out["fp32_ir"] = {"factor_info": info32,
+        peak_m = PEAK_FP32_TFLOPS if mixed == "fp32" else PEAK_16BIT_TFLOPS
+        out["mixed_ir"] = {"precision": f"{mixed} update operands, FP32 accumulation, FP64 "
+                                        "POTRF/TRSM/storage, FP64 refinement",
+                          "factor_info": info32,
+                          "pivots_patched": num32.pivots_patched() if info32 == 0 else None,
                           "converged": bool(be32[-1] <= 1e-14),
                           "factor_gflops": round(F / t32 / 1e9, 2),
-                          "pct_fp32_peak": round(F / t32 / 1e12 / PEAK_FP32_TFLOPS * 100, 3),
+                          "pct_update_precision_peak": round(F / t32 / 1e12 / peak_m * 100, 3),
+                          "pcg_from": pcg_from,
                           "factor_ms": round(t32 * 1e3, 3),
                           "ir_iterations": its[-1],
                           "backward_error": float(f"{max(be32):.3e}"),

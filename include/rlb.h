@@ -52,7 +52,9 @@ typedef int32_t rlb_status;
 
 /* Arithmetic of the bulk SYRK/GEMM updates (POTRF and TRSM are FP64 always). */
 #define RLB_PREC_FP64 0
-#define RLB_PREC_FP32_UPDATES 1
+#define RLB_PREC_FP32_UPDATES 1 /* SYRK/GEMM operands in FP32, FP32 accumulation */
+#define RLB_PREC_BF16_UPDATES 2 /* operands BF16 with per-panel power-of-two scales */
+#define RLB_PREC_FP16_UPDATES 3 /* operands FP16 with per-panel power-of-two scales */
 
 typedef struct rlb_options {
   int32_t struct_size;      /* sizeof(rlb_options) */
@@ -129,7 +131,11 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
 void rlb_symbolic_free(rlb_symbolic sym);
 
 /* Upload the work plan of `sym` to the current HIP device. The numeric handle
- * borrows `sym`, which must outlive it. precision: RLB_PREC_*.
+ * borrows `sym`, which must outlive it. precision: RLB_PREC_*. In every form
+ * the 64x64 diagonal-tile POTRF, the panel TRSM, the factor storage and the
+ * solves are FP64; the reduced forms change the operands of the SYRK/GEMM
+ * updates (the in-supernode trailing updates and the updates written into
+ * ancestors), which accumulate in FP32 and are added to FP64 targets.
  * Errors: RLB_ERR_HIP, RLB_ERR_ALLOC, RLB_ERR_ARG. */
 rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* out);
 
@@ -150,6 +156,14 @@ rlb_status rlb_factor(rlb_numeric num, const double* values, void* workspace,
  * pivot, 1-based column of the factored order); *info receives the same. */
 rlb_status rlb_factor_status(rlb_numeric num, int64_t* info);
 
+/* Reduced-precision forms: the number of pivots of the last factorization
+ * that fell to u * A_jj or below (u: unit roundoff of the update operands)
+ * and were replaced by u * max_i A_ii, so that the FP64 POTRF of the diagonal
+ * tile continues; the refinement then works against the patched factor.
+ * Always 0 in the FP64 form. Synchronizes the factor's stream.
+ * Errors: RLB_ERR_ARG, RLB_ERR_STATE (no factorization enqueued), RLB_ERR_HIP. */
+rlb_status rlb_factor_pivots_patched(rlb_numeric num, int64_t* count);
+
 /* Solve A X = B in place with the computed factor (forward solve with L,
  * backward solve with L^T, Section 1 step 4).
  *   B : (device) n x nrhs column-major FP64 in the ORIGINAL order, ld = ldb
@@ -162,11 +176,17 @@ typedef struct rlb_refine_report {
   int32_t converged;        /* 1 if every column reached tol */
   double backward_error[16];/* final ||b - A x||_inf / (||A||_inf ||x||_inf) per column */
   double history[64];       /* max backward error after the first solve and each step */
+  int32_t pcg_from;         /* step at which PCG took over, or -1 */
+  int32_t reserved;
 } rlb_refine_report;
 
 /* Iterative refinement in FP64 on the device (the mixed forms): X = solve(B),
  * then repeat r = B - A X (FP64 residual), d = solve(r), X += d until every
- * column's backward error is <= tol or max_iter steps were taken.
+ * column's backward error is <= tol or max_iter steps were taken. When the
+ * correction fails to halve (max over columns of ||d||_2) at two steps, the
+ * iteration continues as conjugate gradients in FP64 preconditioned by the
+ * computed factor (M = L L^T), per column, from the current iterate (residual
+ * by recurrence; the stopping test always uses the true residual B - A X).
  *   values : (device) the same FP64 values that were factored (for A X)
  *   B, X   : (device) n x nrhs column-major, ORIGINAL order, ld = ld; nrhs <= 16
  * Returns RLB_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not met. */

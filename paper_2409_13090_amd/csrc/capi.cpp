@@ -93,8 +93,12 @@ struct SolveScratch {
   double* y = nullptr;  // n x SOLVE_MAXRHS: right-hand side in the factored order
   double* z = nullptr;  // forward solution
   double* x = nullptr;  // backward solution
-  double* r = nullptr;
-  double* d = nullptr;
+  double* r = nullptr;   // residual B - A X (original order)
+  double* d = nullptr;   // correction M^-1 r
+  double* p = nullptr;   // PCG search direction
+  double* rr = nullptr;  // PCG residual by recurrence
+  double* q = nullptr;   // -A p
+  double* dots = nullptr;  // SOLVE_MAXRHS column dot products
   unsigned long long* norms = nullptr;  // 3*SOLVE_MAXRHS + 1
   int64_t n = 0;
   rlb_status ensure(int64_t n_) {
@@ -107,6 +111,10 @@ struct SolveScratch {
     HIP_OK(hipMalloc((void**)&x, bytes));
     HIP_OK(hipMalloc((void**)&r, bytes));
     HIP_OK(hipMalloc((void**)&d, bytes));
+    HIP_OK(hipMalloc((void**)&p, bytes));
+    HIP_OK(hipMalloc((void**)&rr, bytes));
+    HIP_OK(hipMalloc((void**)&q, bytes));
+    HIP_OK(hipMalloc((void**)&dots, SOLVE_MAXRHS * sizeof(double)));
     HIP_OK(hipMalloc((void**)&norms, (3 * SOLVE_MAXRHS + 1) * sizeof(unsigned long long)));
     return RLB_OK;
   }
@@ -116,6 +124,10 @@ struct SolveScratch {
     dfree(x);
     dfree(r);
     dfree(d);
+    dfree(p);
+    dfree(rr);
+    dfree(q);
+    dfree(dots);
     dfree(norms);
   }
 };
@@ -194,8 +206,13 @@ struct rlb_numeric_s {
   int device = 0;
   DevPlan d;
   int* status = nullptr;
-  int* counters = nullptr;  // panel group counters (zero between launches)
-  int ncounters = 0;
+  int* counters = nullptr;  // panel group counters (zero between launches), then the
+  int ncounters = 0;         // count of patched pivots
+  // reduced-precision forms: pivot thresholds, largest diagonal entry, panel maxima
+  double* thr = nullptr;
+  int64_t* dsrc = nullptr;
+  unsigned long long* amax = nullptr;
+  unsigned long long* smax = nullptr;
   double* L = nullptr;
   bool factored = false;
   hipStream_t stream = nullptr;
@@ -220,6 +237,10 @@ struct rlb_numeric_s {
     sc.release();
     dfree(status);
     dfree(counters);
+    dfree(thr);
+    dfree(dsrc);
+    dfree(amax);
+    dfree(smax);
   }
 };
 
@@ -309,7 +330,8 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
       return fail(RLB_ERR_ARG, "rlb_options.struct_size mismatch");
     if (opt->ordering < 0 || opt->ordering > 2) return fail(RLB_ERR_ARG, "bad ordering");
     if (!(opt->merge_cap >= 0) || opt->merge_cap > 10) return fail(RLB_ERR_ARG, "bad merge_cap");
-    if (opt->precision < 0 || opt->precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+    if (opt->precision < RLB_PREC_FP64 || opt->precision > RLB_PREC_FP16_UPDATES)
+      return fail(RLB_ERR_ARG, "bad precision");
     ao.ordering = opt->ordering;
     ao.user_perm = opt->user_perm;
     for (int k = 0; k < 4; ++k) ao.grid[k] = opt->grid[k];
@@ -433,9 +455,20 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
 
 void rlb_symbolic_free(rlb_symbolic sym) { delete sym; }
 
+// unit roundoff of the update operands of each form: the pivot threshold factor
+static double update_unit_roundoff(int precision) {
+  switch (precision) {
+    case RLB_PREC_FP32_UPDATES: return std::ldexp(1.0, -24);
+    case RLB_PREC_BF16_UPDATES: return std::ldexp(1.0, -8);
+    case RLB_PREC_FP16_UPDATES: return std::ldexp(1.0, -11);
+    default: return 0.0;
+  }
+}
+
 rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* out) {
   if (!sym || !out) return fail(RLB_ERR_ARG, "null argument");
-  if (precision < 0 || precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+  if (precision < RLB_PREC_FP64 || precision > RLB_PREC_FP16_UPDATES)
+    return fail(RLB_ERR_ARG, "bad precision");
   *out = nullptr;
   std::unique_ptr<rlb_numeric_s> h(new rlb_numeric_s());
   h->sym = sym;
@@ -450,8 +483,15 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
   h->ncounters = std::max<int32_t>(1, s.plan.max_groups);
-  HIP_OK(hipMalloc((void**)&h->counters, sizeof(int) * h->ncounters));
-  HIP_OK(hipMemset(h->counters, 0, sizeof(int) * h->ncounters));
+  HIP_OK(hipMalloc((void**)&h->counters, sizeof(int) * (h->ncounters + 1)));
+  HIP_OK(hipMemset(h->counters, 0, sizeof(int) * (h->ncounters + 1)));
+  if (precision != RLB_PREC_FP64) {
+    if ((st = upload(&h->dsrc, s.plan.diag_src))) return st;
+    HIP_OK(hipMalloc((void**)&h->thr, sizeof(double) * std::max<int64_t>(1, s.n)));
+    HIP_OK(hipMalloc((void**)&h->amax, sizeof(unsigned long long)));
+    HIP_OK(hipMalloc((void**)&h->smax,
+                     sizeof(unsigned long long) * std::max<int32_t>(1, s.plan.n_scale_slots)));
+  }
   *out = h.release();
   return RLB_OK;
 }
@@ -460,16 +500,25 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
                            bool timed) {
   const Symbolic& s = h->sym->s;
   const Plan& p = s.plan;
-  launch_init_status(h->status, 1, h->counters, h->ncounters, st);
+  launch_init_status(h->status, 1, h->counters, h->ncounters + 1, st);
   launch_fill(L, p.l_elems, 0.0, st);
   launch_scatter_a(values, h->d.amap, s.nnz_a, L, st);
+  const double u = update_unit_roundoff(h->precision);
+  unsigned int* nfixed = reinterpret_cast<unsigned int*>(h->counters + h->ncounters);
+  if (h->precision != RLB_PREC_FP64) {
+    launch_zero_u64(h->amax, 1, st);
+    if (h->precision >= RLB_PREC_BF16_UPDATES) launch_zero_u64(h->smax, p.n_scale_slots, st);
+    launch_pivthr(values, h->dsrc, s.n, u, h->thr, h->amax, st);
+  }
+  const int pmode = h->precision == RLB_PREC_FP64 ? 0 : (h->precision == RLB_PREC_FP32_UPDATES ? 1 : 2);
   size_t ei = 0;
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, st);
+      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax, st);
     else
-      launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, st);
+      launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, h->thr,
+                   h->amax, u, h->smax, nfixed, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
 }
@@ -553,6 +602,17 @@ rlb_status rlb_factor_status(rlb_numeric h, int64_t* info) {
   return (rlb_status)*info;
 }
 
+rlb_status rlb_factor_pivots_patched(rlb_numeric h, int64_t* count) {
+  if (!h || !count) return fail(RLB_ERR_ARG, "null argument");
+  if (!h->L) return fail(RLB_ERR_STATE, "no factorization enqueued");
+  unsigned int v = 0;
+  HIP_OK(hipMemcpyAsync(&v, h->counters + h->ncounters, sizeof(v), hipMemcpyDeviceToHost,
+                        h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  *count = v;
+  return RLB_OK;
+}
+
 rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* stream) {
   if (!h || nrhs < 0 || (nrhs > 0 && !B)) return fail(RLB_ERR_ARG, "bad argument");
   const Symbolic& s = h->sym->s;
@@ -589,36 +649,97 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
   if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
   if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
   hipStream_t st = (hipStream_t)stream;
+  const int nr = (int)nrhs;
+  const int64_t n = s.n;
+  SolveScratch& sc = h->sc;
   rlb_refine_report r;
   std::memset(&r, 0, sizeof(r));
-  rlb_status e = solve_into(s, h->d, h->sc, h->L, nrhs, B, ld, X, ld, st);
+  r.pcg_from = -1;
+  rlb_status e = solve_into(s, h->d, sc, h->L, nrhs, B, ld, X, ld, st);
   if (e) return e;
   if (h->anorm_vals != values) {
     h->anorm = -1.0;
     h->anorm_vals = values;
   }
-  double be[SOLVE_MAXRHS];
-  int it = 0;
+  // column scalars: r.z, p.(-Ap) and |d| of the last correction
+  auto dots = [&](const double* x, const double* y, double* out) -> rlb_status {
+    launch_zero_u64(reinterpret_cast<unsigned long long*>(sc.dots), SOLVE_MAXRHS, st);
+    launch_dot_cols(x, n, y, n, n, nr, sc.dots, st);
+    HIP_OK(hipMemcpyAsync(out, sc.dots, sizeof(double) * nr, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return RLB_OK;
+  };
+  auto solve_r = [&](const double* rv) {  // d = M^-1 rv with M = L L^T
+    launch_perm_in(h->d.perm, rv, n, sc.y, n, n, nr, st);
+    enqueue_solve_levels(s, h->d, h->L, sc, nr, st);
+    launch_perm_out(h->d.perm, sc.x, n, sc.d, n, n, nr, st);
+  };
+  double be[SOLVE_MAXRHS], rz[SOLVE_MAXRHS] = {0}, dd[SOLVE_MAXRHS], prev_dn = -1.0;
+  int strikes = 0, it = 0;
+  bool pcg = false;
+  ColCoef one, zero;
+  for (int k = 0; k < SOLVE_MAXRHS; ++k) {
+    one.v[k] = 1.0;
+    zero.v[k] = 0.0;
+  }
   for (;;) {
-    e = backward_errors(s, h->d, h->sc, values, (int)nrhs, B, X, ld, st, be, &h->anorm);
+    e = backward_errors(s, h->d, sc, values, nr, B, X, ld, st, be, &h->anorm);
     if (e) return e;
     double worst = 0;
-    for (int k = 0; k < nrhs; ++k) worst = std::max(worst, be[k]);
+    for (int k = 0; k < nr; ++k) worst = std::max(worst, be[k]);
     if (it < 64) r.history[it] = worst;
     if (worst <= tol || it >= max_iter) {
       r.converged = worst <= tol;
       break;
     }
-    // d = solve(r), X += d  (r = B - A X was left in the scratch by backward_errors)
-    launch_perm_in(h->d.perm, h->sc.r, s.n, h->sc.y, s.n, s.n, (int)nrhs, st);
-    enqueue_solve_levels(s, h->d, h->L, h->sc, (int)nrhs, st);
-    launch_perm_out(h->d.perm, h->sc.x, s.n, h->sc.d, s.n, s.n, (int)nrhs, st);
-    launch_axpy(X, ld, h->sc.d, s.n, s.n, (int)nrhs, st);
+    if (!pcg) {
+      solve_r(sc.r);  // sc.d = M^-1 (B - A X)
+      // classic refinement: X += d; switch to PCG after the correction fails
+      // to halve twice
+      if ((e = dots(sc.d, sc.d, dd))) return e;
+      double dn = 0;
+      for (int k = 0; k < nr; ++k) dn = std::max(dn, std::sqrt(dd[k]));
+      if (prev_dn >= 0 && dn > 0.5 * prev_dn) ++strikes;
+      prev_dn = dn;
+      if (strikes < 2) {
+        launch_axpy(X, ld, sc.d, n, n, nr, st);
+        HIP_OK(hipGetLastError());
+        ++it;
+        continue;
+      }
+      // PCG from the current iterate: rr = B - A X, z = M^-1 rr, p = z
+      pcg = true;
+      r.pcg_from = it;
+      launch_axpby_cols(sc.rr, n, sc.r, n, n, nr, one, zero, st);
+      if ((e = dots(sc.rr, sc.d, rz))) return e;
+      launch_axpby_cols(sc.p, n, sc.d, n, n, nr, one, zero, st);
+    } else {
+      // z = M^-1 rr; beta = (rr.z) / (rr.z)_old; p = z + beta p
+      solve_r(sc.rr);
+      double rzn[SOLVE_MAXRHS];
+      if ((e = dots(sc.rr, sc.d, rzn))) return e;
+      ColCoef beta;
+      for (int k = 0; k < SOLVE_MAXRHS; ++k) {
+        beta.v[k] = (k < nr && rz[k] != 0.0) ? rzn[k] / rz[k] : 0.0;
+        if (k < nr) rz[k] = rzn[k];
+      }
+      launch_axpby_cols(sc.p, n, sc.d, n, n, nr, one, beta, st);
+    }
+    // q = -A p; alpha = (rr.z) / (p.A p); X += alpha p; rr -= alpha A p
+    launch_residual(n, h->d.a_rowptr, h->d.a_col, h->d.a_src, values, sc.p, n, nullptr, 0, sc.q,
+                    n, nr, st);
+    double pq[SOLVE_MAXRHS];
+    if ((e = dots(sc.p, sc.q, pq))) return e;
+    ColCoef alpha;
+    for (int k = 0; k < SOLVE_MAXRHS; ++k)
+      alpha.v[k] = (k < nr && pq[k] != 0.0) ? rz[k] / -pq[k] : 0.0;
+    launch_axpby_cols(X, ld, sc.p, n, n, nr, alpha, one, st);
+    launch_axpby_cols(sc.rr, n, sc.q, n, n, nr, alpha, one, st);
     HIP_OK(hipGetLastError());
     ++it;
   }
   r.iterations = it;
-  for (int k = 0; k < nrhs; ++k) r.backward_error[k] = be[k];
+  for (int k = 0; k < nr; ++k) r.backward_error[k] = be[k];
   if (rep) *rep = r;
   return r.converged ? RLB_OK : fail(RLB_ERR_NOT_CONVERGED, "refinement did not reach tol");
 }
@@ -677,7 +798,10 @@ rlb_status rlb_last_profile(rlb_numeric h, double* update_ms, double* panel_ms, 
 rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t precision,
                             rlb_batch* out, int64_t* ws_bytes) {
   if (count < 1 || !syms || !out) return fail(RLB_ERR_ARG, "bad argument");
-  if (precision < 0 || precision > 1) return fail(RLB_ERR_ARG, "bad precision");
+  if (precision < RLB_PREC_FP64 || precision > RLB_PREC_FP16_UPDATES)
+    return fail(RLB_ERR_ARG, "bad precision");
+  if (precision > RLB_PREC_FP32_UPDATES)
+    return fail(RLB_ERR_UNSUPPORTED, "16-bit update forms are single-matrix only");
   *out = nullptr;
   std::unique_ptr<rlb_batch_s> b(new rlb_batch_s());
   b->precision = precision;
@@ -788,9 +912,10 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   launch_scatter_batch(b->d_vals, b->d_nnz_ptr, count, b->nnz_ptr[count], b->d_amap, L, st);
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, st);
+      launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr, st);
     else
-      launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, st);
+      launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, nullptr, nullptr,
+                   0.0, nullptr, nullptr, st);
   }
 }
 

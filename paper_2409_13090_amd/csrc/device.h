@@ -10,6 +10,11 @@ namespace rlb {
 
 constexpr int SOLVE_MAXRHS = 16;
 
+// one coefficient per right-hand-side column, passed by value
+struct ColCoef {
+  double v[SOLVE_MAXRHS];
+};
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_init_status(int* status, int count, int* counters, int ncounters, hipStream_t st);
 void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, double* L,
@@ -17,9 +22,12 @@ void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, doub
 void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
                           int64_t total, const int64_t* amap, double* L, hipStream_t st);
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  hipStream_t st);
+                  int precision, const double* thr, const unsigned long long* amax, double ufix,
+                  unsigned long long* smax, unsigned int* nfixed, hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, hipStream_t st);
+                   int precision, const unsigned long long* smax, hipStream_t st);
+void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
+                   unsigned long long* amax, hipStream_t st);
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                      double* y, double* z, int nrhs, int64_t ldy, hipStream_t st);
 void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
@@ -39,6 +47,10 @@ void launch_anorm(int64_t n, const int64_t* rp, const int64_t* src, const double
                   unsigned long long* out, hipStream_t st);
 void launch_axpy(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
                  hipStream_t st);
+void launch_dot_cols(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
+                     int nrhs, double* out, hipStream_t st);
+void launch_axpby_cols(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
+                       const ColCoef& a, const ColCoef& b, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
 
 }  // namespace rlb

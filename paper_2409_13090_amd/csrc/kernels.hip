@@ -178,14 +178,26 @@ __device__ __forceinline__ void inv16(const double* T, double* I, int o, int lan
 // column indices are larger); afterwards each pivot lane checks its own raw
 // pivot and the smallest failing column (1-based, factored order) is
 // returned, or INT_MAX.
-__device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int col0, int lane) {
+//
+// FIX (reduced-precision update forms): a pivot at or below thr (this lane's
+// column threshold, u times the column's diagonal entry of A) is replaced by
+// rep, and the replacements are counted in *nfix.
+template <bool FIX>
+__device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int col0, int lane,
+                                       double thr, double rep, int* nfix) {
   double v[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = T[lane * TP + o + j];
   double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    const double d = lane_bcast(v[c], o + c);
+    double d = lane_bcast(v[c], o + c);
+    if (FIX) {
+      if (d <= lane_bcast(thr, o + c) && o + c < nb) {
+        d = rep;
+        ++*nfix;
+      }
+    }
     dg = (lane == o + c) ? d : dg;
     double y = __builtin_amdgcn_rsq(d);
     y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
@@ -208,9 +220,18 @@ __device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int
   return fails ? col0 + __ffsll((long long)fails) : 0x7fffffff;
 }
 
+// MODE 0: FP64 form. MODE 1: reduced-precision updates (pivot patching).
+// MODE 2: 16-bit updates (pivot patching, and the largest |entry| of the row
+// tile, overall and in the rows below the diagonal block, into the scale
+// slots of the column block and of the supernode).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ tiles,
                                                double* __restrict__ L, int* __restrict__ status,
-                                               int* __restrict__ counters) {
+                                               int* __restrict__ counters,
+                                               const double* __restrict__ thr,
+                                               const unsigned long long* __restrict__ amax,
+                                               double ufix, unsigned long long* __restrict__ smax,
+                                               unsigned int* __restrict__ nfixed) {
   const PanelTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = t.nb, ldi = t.ld;
@@ -221,6 +242,7 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   __shared__ double sA[64 * AP];  // the row tile, k-major
   __shared__ double Lc[16 * 64];  // finished columns of the current 16-column block
   __shared__ int s_last;
+  __shared__ unsigned long long s_max[2];
   // stage: thread (row, cg) loads columns cg, cg+4, ..., all 32 loads in flight;
   // addresses are clamped so every load is in bounds
   {
@@ -250,9 +272,18 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   }
   const int nbb = (nb + 15) >> 4;
   int bad = 0x7fffffff;
+  int nfix = 0;
+  double cthr = 0.0, crep = 0.0;
+  if (MODE >= 1) {
+    cthr = thr[t.col + min(lane, nb - 1)];
+    double am;
+    __builtin_memcpy(&am, amax, sizeof(double));
+    crep = ufix * am;
+    if (tid < 2) s_max[tid] = 0ull;
+  }
   for (int r = 0; r < nbb; ++r) {
     if (wave == 0) {
-      bad = min(bad, panel16(T, Lc, 16 * r, nb, t.col, lane));
+      bad = min(bad, panel16<(MODE >= 1)>(T, Lc, 16 * r, nb, t.col, lane, cthr, crep, &nfix));
     } else if (r >= 1) {
       if (wave == 3) {
         inv16(T, I, 16 * (r - 1), lane);
@@ -304,6 +335,7 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   // inv(L) strict lower part transposed above it
   if (s_last) {
     if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
+    if (MODE >= 1 && wave == 0 && lane == 0 && nfix) atomicAdd(nfixed + t.slot, (unsigned)nfix);
     const int i = lane;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -319,6 +351,7 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   // column 16cb + 4v + l/16), so stores are coalesced along the rows.
   const int rb0 = 2 * (wave & 1);
   const int kpad = (nb + 3) & ~3;
+  double mx_step = 0.0, mx_anc = 0.0;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int cb = (wave >> 1) ? 1 + h : 3 * h;
@@ -348,6 +381,23 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
         if (r0 < nr) D[(int64_t)c * ldi + t.row0 + r0] = a0[v];
         if (r1 < nr) D[(int64_t)c * ldi + t.row0 + r1] = a1[v];
       }
+      if (MODE == 2) {
+        // |x| of a non-negative double orders like its bit pattern
+        const double x0 = (c < nb && r0 < nr) ? fabs(a0[v]) : 0.0;
+        const double x1 = (c < nb && r1 < nr) ? fabs(a1[v]) : 0.0;
+        const double xa0 = t.row0 + r0 >= t.rw ? x0 : 0.0, xa1 = t.row0 + r1 >= t.rw ? x1 : 0.0;
+        mx_step = fmax(mx_step, fmax(x0, x1));
+        mx_anc = fmax(mx_anc, fmax(xa0, xa1));
+      }
+    }
+  }
+  if (MODE == 2) {
+    atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mx_step));
+    atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mx_anc));
+    __syncthreads();
+    if (tid == 0) {
+      atomicMax(smax + t.s_step, s_max[0]);
+      if (s_max[1]) atomicMax(smax + t.s_anc, s_max[1]);
     }
   }
 }
@@ -554,6 +604,205 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 
 template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
+
+// 16-bit operand form of the update. Every contribution's X and Y are scaled
+// by the power of two s = 2^e of its source panel (e chosen so that the
+// panel's largest |entry| times s lies in [2^13, 2^14)), rounded to FP16 or
+// BF16 (round to nearest even, through FP32) and multiplied on MFMA 16x16x16
+// with FP32 accumulation; a contribution's sum is scaled back by 2^-2e into an
+// FP64 accumulator before the next contribution starts. Staging as in
+// k_update, but each thread stages 4 consecutive k of one row, stored
+// row-major so that a lane's 4-element MFMA operand is one 8-byte LDS read.
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct Half;
+template <>
+struct Half<3> {  // FP16
+  typedef v4h vec;
+  static __device__ __forceinline__ unsigned short cvt(double x) {
+    const _Float16 h = (_Float16)(float)x;
+    unsigned short b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
+  }
+  static __device__ __forceinline__ v4f op(vec a, vec b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Half<2> {  // BF16
+  typedef v4s vec;
+  static __device__ __forceinline__ unsigned short cvt(double x) {
+    const __bf16 h = (__bf16)(float)x;
+    unsigned short b;
+    __builtin_memcpy(&b, &h, 2);
+    return b;
+  }
+  static __device__ __forceinline__ v4f op(vec a, vec b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+
+// the scale exponent e of a panel from its largest |entry| (bit pattern)
+__device__ __forceinline__ int panel_scale_exp(unsigned long long mbits) {
+  if (mbits == 0ull) return 0;
+  const int E = (int)((mbits >> 52) & 0x7ff) - 1023;  // floor(log2(max)) for normal max
+  return min(max(13 - E, -960), 960);
+}
+
+constexpr int KP16 = 20;  // LDS row pitch of the 16-bit stage (elements)
+
+template <int P>
+__global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ tiles,
+                                                  const UpdSeg* __restrict__ segs,
+                                                  double* __restrict__ L,
+                                                  const unsigned long long* __restrict__ smax) {
+  typedef typename Half<P>::vec vec;
+  const UpdTile t = tiles[blockIdx.x];
+  __shared__ __align__(16) unsigned short sX[2][64][KP16];  // [tile row][k]
+  __shared__ __align__(16) unsigned short sY[2][64][KP16];  // [tile column][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int lr = tid & 63;  // row this thread stages
+  const int lk = tid >> 6;  // it stages k = 4*lk .. 4*lk+3 of the chunk
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+  double cv[2][2][4];
+  if (!atomic) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + 4 * (lane >> 4) + v, t.n - 1);
+          cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        }
+  }
+  v4f acc[2][2];
+  double accd[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc[a][b] = v4f{0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accd[a][b][v] = 0.0;
+    }
+  constexpr int SEGS_LDS = 64;
+  __shared__ UpdSeg sg[SEGS_LDS];
+  {
+    const int words = min(t.nseg, SEGS_LDS) * (int)(sizeof(UpdSeg) / 8);
+    const int64_t* src = reinterpret_cast<const int64_t*>(segs + t.seg0);
+    int64_t* dst = reinterpret_cast<int64_t*>(sg);
+    for (int w = tid; w < words; w += 256) dst[w] = src[w];
+  }
+  __syncthreads();
+  auto seg_at = [&](int i) { return i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]; };
+  double xr[4], yr[4];
+  bool xin = false, yin = false;
+  int kvalid = 0;
+  double fscale = 1.0;  // scale of the fetched chunk's contribution
+  auto fetch = [&](const UpdSeg& g, int k0) {
+    xin = lr >= g.ra && lr < g.rb;
+    yin = lr >= g.ca && lr < g.cb;
+    kvalid = g.k - k0 - 4 * lk;
+    fscale = ldexp(1.0, panel_scale_exp(smax[g.sslot]));
+    const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+    const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kk = min(k0 + 4 * lk + q, g.k - 1);
+      xr[q] = L[xo + kk * g.lds];
+      yr[q] = L[yo + kk * g.lds];
+    }
+  };
+  auto stash = [&](int buf) {
+    unsigned long long px = 0, py = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool kin = q < kvalid;
+      px |= (unsigned long long)Half<P>::cvt((kin && xin) ? xr[q] * fscale : 0.0) << (16 * q);
+      py |= (unsigned long long)Half<P>::cvt((kin && yin) ? yr[q] * fscale : 0.0) << (16 * q);
+    }
+    *reinterpret_cast<unsigned long long*>(&sX[buf][lr][4 * lk]) = px;
+    *reinterpret_cast<unsigned long long*>(&sY[buf][lr][4 * lk]) = py;
+  };
+  int e = 0, k0 = 0;
+  UpdSeg g = seg_at(0);
+  fetch(g, 0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (;;) {
+    int ne = e, nk0 = k0 + 16;
+    if (nk0 >= g.k) {
+      ne = e + 1;
+      nk0 = 0;
+    }
+    const bool more = ne < t.nseg;
+    UpdSeg gn = g;
+    if (more) {
+      if (ne != e) gn = seg_at(ne);
+      fetch(gn, nk0);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const vec a = *reinterpret_cast<const vec*>(&sY[buf][wc + 16 * bj + (lane & 15)][4 * (lane >> 4)]);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const vec b = *reinterpret_cast<const vec*>(&sX[buf][wr + 16 * bi + (lane & 15)][4 * (lane >> 4)]);
+        acc[bj][bi] = Half<P>::op(a, b, acc[bj][bi]);
+      }
+    }
+    if (ne != e || !more) {
+      // end of a contribution: undo its scale into the FP64 accumulator
+      const double inv2 = ldexp(1.0, -2 * panel_scale_exp(smax[g.sslot]));
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) accd[bj][bi][v] += (double)acc[bj][bi][v] * inv2;
+          acc[bj][bi] = v4f{0, 0, 0, 0};
+        }
+    }
+    if (!more) break;
+    stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    e = ne;
+    k0 = nk0;
+    g = gn;
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + 4 * (lane >> 4) + v;
+        if (row < t.m && col < t.n && (!diag || row >= col)) {
+          double* p = C + (int64_t)col * ldc + row;
+          if (atomic)
+            atomicAdd(p, -accd[bj][bi][v]);
+          else
+            *p = cv[bj][bi][v] - accd[bj][bi][v];
+        }
+      }
+}
+
+template __global__ void k_update16<2>(const UpdTile*, const UpdSeg*, double*,
+                                       const unsigned long long*);
+template __global__ void k_update16<3>(const UpdTile*, const UpdSeg*, double*,
+                                       const unsigned long long*);
 
 // ---------------------------------------------------------------------------
 // Supernodal solves L z = y and L^T x = z in the factored order (vectors
@@ -797,7 +1046,33 @@ __global__ void k_residual(int64_t n, const int64_t* __restrict__ rp, const int3
   int64_t row = i % n, k = i / n;
   double acc = 0.0;
   for (int64_t e = rp[row]; e < rp[row + 1]; ++e) acc += vals[src[e]] * x[k * ldx + ci[e]];
-  r[k * ldr + row] = b[k * ldb + row] - acc;
+  r[k * ldr + row] = (b ? b[k * ldb + row] : 0.0) - acc;
+}
+
+// out[k] += sum_i x[i + k*ldx] * y[i + k*ldy] (block sums added atomically)
+__global__ void k_dot_cols(const double* __restrict__ x, int64_t ldx, const double* __restrict__ y,
+                           int64_t ldy, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.y;
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    a += x[k * ldx + i] * y[k * ldy + i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out + k, red[0]);
+}
+
+// y[:, k] = a[k] * x[:, k] + b[k] * y[:, k]
+__global__ void k_axpby_cols(double* __restrict__ y, int64_t ldy, const double* __restrict__ x,
+                             int64_t ldx, int64_t n, int nrhs, ColCoef a, ColCoef b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t row = i % n, k = i / n;
+  y[k * ldy + row] = a.v[k] * x[k * ldx + row] + b.v[k] * y[k * ldy + row];
 }
 
 // out[k] = max(out[k], max_i |v[i + k*ld]|) via the ordering of non-negative
@@ -869,19 +1144,48 @@ void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int
                      vals, nnz_ptr, count, total, amap, L);
 }
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  hipStream_t st) {
+                  int precision, const double* thr, const unsigned long long* amax, double ufix,
+                  unsigned long long* smax, unsigned int* nfixed, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_panel, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
-                     counters);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_panel<0>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
+                       counters, thr, amax, ufix, smax, nfixed);
+  else if (precision == 1)
+    hipLaunchKernelGGL(k_panel<1>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
+                       counters, thr, amax, ufix, smax, nfixed);
+  else
+    hipLaunchKernelGGL(k_panel<2>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
+                       counters, thr, amax, ufix, smax, nfixed);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, hipStream_t st) {
+                   int precision, const unsigned long long* smax, hipStream_t st) {
   if (count <= 0) return;
+  const dim3 g((unsigned)count), b(256);
   if (precision == 1)
-    hipLaunchKernelGGL(k_update<float>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs, L);
+    hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L);
+  else if (precision == 2)
+    hipLaunchKernelGGL(k_update16<2>, g, b, 0, st, tiles, segs, L, smax);
+  else if (precision == 3)
+    hipLaunchKernelGGL(k_update16<3>, g, b, 0, st, tiles, segs, L, smax);
   else
-    hipLaunchKernelGGL(k_update<double>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs,
-                       L);
+    hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L);
+}
+// pivot thresholds of the reduced-precision forms: thr[j] = u * A_jj, and the
+// largest diagonal entry (bit pattern; all positive on an SPD input)
+__global__ void k_pivthr(const double* __restrict__ vals, const int64_t* __restrict__ dsrc,
+                         int64_t n, double u, double* __restrict__ thr,
+                         unsigned long long* __restrict__ amax) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double a = vals[dsrc[j]];
+  thr[j] = u * a;
+  if (a > 0.0) atomicMax(amax, (unsigned long long)__double_as_longlong(a));
+}
+void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
+                   unsigned long long* amax, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pivthr, dim3(grid_for(n, 256, INT32_MAX)), dim3(256), 0, st, vals, dsrc,
+                     n, u, thr, amax);
 }
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                      double* y, double* z, int nrhs, int64_t ldy, hipStream_t st) {
@@ -934,6 +1238,19 @@ void launch_anorm(int64_t n, const int64_t* rp, const int64_t* src, const double
   if (n <= 0) return;
   hipLaunchKernelGGL(k_anorm, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, rp, src, vals,
                      out);
+}
+void launch_dot_cols(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
+                     int nrhs, double* out, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_dot_cols, dim3(grid_for(n, 256, 512), nrhs), dim3(256), 0, st, x, ldx, y,
+                     ldy, n, out);
+}
+void launch_axpby_cols(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
+                       const ColCoef& a, const ColCoef& b, hipStream_t st) {
+  int64_t tot = n * nrhs;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_axpby_cols, dim3(grid_for(tot, 256, INT32_MAX)), dim3(256), 0, st, y, ldy,
+                     x, ldx, n, nrhs, a, b);
 }
 void launch_axpy(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
                  hipStream_t st) {

@@ -118,6 +118,19 @@ int build_plan(Symbolic& s, std::string& err) {
     for (int64_t J = 0; J < S; ++J) p.lvl_sn[fill[p.level[J]]++] = (int32_t)J;
   }
 
+  // scale slots of the 16-bit update forms: one per 64-column block of every
+  // supernode (its rows below the block's diagonal tile), then one per
+  // supernode (its rows below its diagonal block)
+  std::vector<int32_t> sbase(S + 1, 0);
+  for (int64_t J = 0; J < S; ++J) sbase[J + 1] = sbase[J] + (int32_t)((W(J) + NB - 1) / NB) + 1;
+  p.n_scale_slots = sbase[S];
+  auto anc_slot = [&](int64_t J) { return sbase[J + 1] - 1; };
+  // input entry of the diagonal of every factored column
+  p.diag_src.assign(n, -1);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t e = s.colptr[j]; e < s.colptr[j + 1]; ++e)
+      if (s.rowidx[e] == j) p.diag_src[inv[j]] = e;
+
   // ancestor-update rectangles of every supernode, from its blocks and relindB
   std::vector<std::vector<Rect>> rects(S);
   for (int64_t J = 0; J < S; ++J) {
@@ -206,6 +219,10 @@ int build_plan(Symbolic& s, std::string& err) {
         pt.slot = 0;
         pt.grp = ngroups++;
         pt.gcnt = (int32_t)nt;
+        pt.s_step = sbase[J] + (int32_t)k;
+        pt.s_anc = anc_slot(J);
+        pt.rw = (int32_t)(w - c0);
+        pt.pad = 0;
         for (int64_t t = 0; t < nt; ++t) {
           pt.row0 = (int32_t)(nb + 64 * t);
           p.panels.push_back(pt);
@@ -246,7 +263,7 @@ int build_plan(Symbolic& s, std::string& err) {
               g.ca = 0;
               g.cb = (int32_t)tn;
               g.src = (int32_t)J;
-              g.pad = 0;
+              g.sslot = sbase[J] + (int32_t)k;
               p.updates.push_back(t);
               p.segs.push_back(g);
               p.flops_tiles += seg_exec_flops(0, tm, 0, tn, nb);
@@ -281,7 +298,7 @@ int build_plan(Symbolic& s, std::string& err) {
               g.ca = (int32_t)(clo - TJ * TN);
               g.cb = (int32_t)(chi - TJ * TN);
               g.src = (int32_t)J;
-              g.pad = 0;
+              g.sslot = anc_slot(J);
               by_tile[std::make_tuple(r.P, TJ, TI)].push_back(g);
             }
         }

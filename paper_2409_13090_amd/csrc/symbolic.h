@@ -47,8 +47,8 @@ struct UpdSeg {
   int32_t lds;   // leading dimension of the source panel
   int32_t k;     // inner dimension (source columns)
   int32_t ra, rb, ca, cb;
-  int32_t src;   // source supernode (for per-panel scales)
-  int32_t pad;
+  int32_t src;   // source supernode
+  int32_t sslot; // scale slot of the source panel (16-bit update forms)
 };
 static_assert(sizeof(UpdSeg) == 48, "UpdSeg layout");
 
@@ -63,8 +63,12 @@ struct PanelTile {
   int32_t slot;       // status slot (matrix index in a batch)
   int32_t grp;        // counter of the group of tiles sharing this diagonal tile
   int32_t gcnt;       // number of tiles in the group
+  int32_t s_step;     // scale slot of this column block (16-bit update forms)
+  int32_t s_anc;      // scale slot of the supernode's rows below its diagonal block
+  int32_t rw;         // first row, relative to the diagonal tile, below the diagonal block
+  int32_t pad;
 };
-static_assert(sizeof(PanelTile) == 40, "PanelTile layout");
+static_assert(sizeof(PanelTile) == 56, "PanelTile layout");
 
 // Work item of the supernodal solves, one workgroup each (see k_fwd_step,
 // k_bwd_below, k_bwd_step). Columns and rows are relative to the supernode.
@@ -115,6 +119,8 @@ struct Plan {
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
   std::vector<UpdSeg> segs;
+  int32_t n_scale_slots = 0;     // per column block of every supernode, plus one per supernode
+  std::vector<int64_t> diag_src; // input entry of the diagonal of every factored column
   std::vector<SolveTile> stiles;      // solve work items, launch by launch
   std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
   std::vector<Launch> launches;

@@ -20,6 +20,8 @@ RLB_ORDER_GRID_ND = 1
 RLB_ORDER_USER = 2
 RLB_PREC_FP64 = 0
 RLB_PREC_FP32_UPDATES = 1
+RLB_PREC_BF16_UPDATES = 2
+RLB_PREC_FP16_UPDATES = 3
 
 _c_i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
@@ -57,7 +59,8 @@ class Info(ctypes.Structure):
 
 class RefineReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("backward_error", ctypes.c_double * 16), ("history", ctypes.c_double * 64)]
+                ("backward_error", ctypes.c_double * 16), ("history", ctypes.c_double * 64),
+                ("pcg_from", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 EXPORTED = [
@@ -66,7 +69,7 @@ EXPORTED = [
     "rlb_refine", "rlb_backward_error", "rlb_factor_export", "rlb_numeric_free",
     "rlb_batch_create", "rlb_batch_factor", "rlb_batch_status", "rlb_batch_solve",
     "rlb_batch_free", "rlb_set_graph_mode", "rlb_batch_set_graph_mode", "rlb_set_profiling",
-    "rlb_last_profile", "rlb_status_string", "rlb_last_error",
+    "rlb_last_profile", "rlb_status_string", "rlb_last_error", "rlb_factor_pivots_patched",
 ]
 
 _lib = None
@@ -104,6 +107,7 @@ def lib():
         "rlb_batch_set_graph_mode": [_vp, i32],
         "rlb_set_profiling": [_vp, i32],
         "rlb_last_profile": [_vp, _vp, _vp, _vp, _vp],
+        "rlb_factor_pivots_patched": [_vp, ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -239,6 +243,11 @@ class Numeric:
         _check(st, allow_positive=True)
         return int(info.value)
 
+    def pivots_patched(self):
+        c = ctypes.c_int64()
+        _check(lib().rlb_factor_pivots_patched(self.h, ctypes.byref(c)))
+        return int(c.value)
+
     def solve(self, B, stream=None):
         """In place; B is an (n, nrhs) or (n,) float64 device tensor, column-major
         storage expected (use B.T.contiguous().T for an (n, nrhs) tensor)."""
@@ -256,7 +265,8 @@ class Numeric:
             _check(st)
         return {"converged": bool(rep.converged), "iterations": rep.iterations,
                 "backward_error": list(rep.backward_error)[:nrhs],
-                "history": list(rep.history)[:rep.iterations + 1]}
+                "history": list(rep.history)[:rep.iterations + 1],
+                "pcg_from": rep.pcg_from}
 
     def backward_error(self, B, X, values=None, stream=None):
         nrhs, ld = _cm(B)

@@ -180,6 +180,39 @@ def test_fp32_updates_with_refinement_reach_1e14():
     assert max(rep["backward_error"]) <= 1e-14
 
 
+@pytest.mark.parametrize("prec,name", [(rlb.RLB_PREC_BF16_UPDATES, "bf16"),
+                                       (rlb.RLB_PREC_FP16_UPDATES, "fp16")])
+@pytest.mark.parametrize("case", ["lap3d7_15", "elast_8x8x8"])
+def test_16bit_updates_with_refinement_reach_1e14(prec, name, case):
+    """Scaled BF16/FP16 update operands with FP32 accumulation; the FP64
+    refinement (IR, then factor-preconditioned CG if IR stalls) reaches 1e-14."""
+    torch = _torch()
+    if case == "lap3d7_15":
+        A = W.small_grid("7pt", (15, 15, 15), seed=31, lo=0.1, hi=10.0, shift=1e-4, nrhs=4)
+    else:
+        rng = np.random.default_rng(32)
+        A = W.elasticity_like((8, 8, 8), rng, 1e-6)
+        A.rhs = W.draw_rhs(rng, A.n, 4)
+    print(f"[case] {case} {name} n={A.n}", flush=True)
+    s = rlb.Symbolic.from_matrix(A)
+    num = rlb.Numeric(s, prec)
+    vals = torch.from_numpy(A.values).cuda()
+    assert num.factor(vals) == 0
+    patched = num.pivots_patched()
+    # close to the FP64 oracle at the operands' precision, not equal
+    o, f = oracle_factor(A)
+    err = compare_factor(num.export(), f, A.n, tol=0.5)
+    print(f"[case] factor rel err {err:.2e}, patched pivots {patched}", flush=True)
+    assert err > 1e-10
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).cuda().T.contiguous().T
+    X = torch.zeros_like(B).T.contiguous().T
+    rep = num.refine(B, X, tol=1e-14, max_iter=60)
+    print(f"[case] iterations {rep['iterations']} pcg_from {rep['pcg_from']} "
+          f"be {max(rep['backward_error']):.2e}", flush=True)
+    assert rep["converged"], rep
+    assert max(rep["backward_error"]) <= 1e-14
+
+
 @pytest.mark.timeout(600)
 def test_full_size_lap3d7_48_sampled_and_properties():
     """The 48^3 workload in the launch configuration the benchmark times."""

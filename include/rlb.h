@@ -68,7 +68,8 @@ typedef struct rlb_options {
                                (Section 1, Fig. 2; Section 3.1), 0 = none */
   int32_t maximal_blocks;   /* 1 = merge contiguous GEMM blocks (Alg. 5, "maximal") */
   int32_t precision;        /* RLB_PREC_* used by rlb_numeric_create */
-  int32_t reserved;
+  int32_t panel_spread;     /* panel launches with more 64-row tiles than this give a
+                               workgroup several consecutive row tiles; 0 = 512 */
 } rlb_options;
 
 typedef struct rlb_info {
@@ -122,8 +123,9 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* out);
  * target offset, ldc, m, n, flags, first contribution, contribution count),
  * "update_segs" (9 per contribution: X and Y source offsets, source ld, k,
  * tile rows [ra, rb), tile columns [ca, cb), source supernode),
- * "panel_tiles" (9 per tile: diagonal offset, ld, nb, nrows, row0, column,
- * status slot, group counter, group size) and "launches" (5 per launch:
+ * "panel_tiles" (11 per workgroup: diagonal offset, ld, nb, nrows, row0,
+ * column, status slot, group counter, group size, first row below the
+ * diagonal block, number of 64-row tiles from row0) and "launches" (5 per launch:
  * kind 0 panel (POTRF+TRSM) / 1 update, level, step, first tile, tile
  * count). If out is NULL only *len is set. All arrays are returned as int64. */
 rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out, int64_t* len);

@@ -339,6 +339,8 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     ao.reorder = opt->reorder;
     ao.maximal_blocks = opt->maximal_blocks;
     ao.precision = opt->precision;
+    if (opt->panel_spread < 0) return fail(RLB_ERR_ARG, "bad panel_spread");
+    ao.panel_spread = opt->panel_spread ? opt->panel_spread : 512;
   } else {
     ao.ordering = 0;
   }
@@ -436,10 +438,11 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       int64_t v[9] = {g.x, g.y, g.lds, g.k, g.ra, g.rb, g.ca, g.cb, g.src};
       tmp.insert(tmp.end(), v, v + 9);
     }
-  } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, grp, gcnt
+  } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, grp, gcnt, rw, nrt
     for (const PanelTile& t : s.plan.panels) {
-      int64_t v[9] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.grp, t.gcnt};
-      tmp.insert(tmp.end(), v, v + 9);
+      int64_t v[11] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.grp, t.gcnt, t.rw,
+                       t.nrt};
+      tmp.insert(tmp.end(), v, v + 11);
     }
   } else if (w == "launches") {  // kind, level, step, start, count per launch
     for (const Launch& l : s.plan.launches) {

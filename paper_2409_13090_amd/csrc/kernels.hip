@@ -69,9 +69,10 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 // fused with the TRSM of every row below it, in one launch.
 //
 // A group is the set of workgroups that share one diagonal tile: one per 64
-// rows below it (or a single one when there are none). Every member stages
+// rows below it (or a single one when there are none), or one per few
+// consecutive 64-row tiles in launches that hold many. Every member stages
 // the unfactored tile into LDS, factors it there redundantly, forms inv(L) of
-// the tile and overwrites its own 64-row tile A with X = A * inv(L)^T. After
+// the tile and overwrites its own row tiles A with X = A * inv(L)^T. After
 // staging, each member increments the group's counter; the member that brings
 // it to the group size is the last reader of the unfactored tile, and only it
 // writes the factored tile back (L in the lower triangle, the strict lower
@@ -189,9 +190,10 @@ __device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = T[lane * TP + o + j];
   double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
+  double dn = lane_bcast(v[0], o);  // the next pivot, before any patching
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
-    double d = lane_bcast(v[c], o + c);
+    double d = dn;
     if (FIX) {
       if (d <= lane_bcast(thr, o + c) && o + c < nb) {
         d = rep;
@@ -205,6 +207,9 @@ __device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int
     const double l = v[c] * y;
     v[c] = l;
     if (c < 15) {
+      // the pivot row's own entries give the next pivot without waiting for
+      // the broadcast of its multiplier
+      dn = lane_bcast(fma(-l, l, v[c + 1]), o + c + 1);
       Lc[c * 64 + lane] = l;
       v[c + 1] = fma(-l, lane_bcast(l, o + c + 1), v[c + 1]);
 #pragma unroll
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   const PanelTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = t.nb, ldi = t.ld;
-  const int nr = min(64, t.nrows - t.row0);  // rows of this member's tile (may be <= 0)
+  const int nr = min(64, t.nrows - t.row0);  // rows of the first row tile (may be <= 0)
   double* D = L + t.diag;
   __shared__ double T[64 * TP];   // the tile, row-major: T[i*TP + j]
   __shared__ double I[64 * TP];   // inv(L), row-major
@@ -344,54 +349,73 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
       if (i < nb && j < nb) D[(int64_t)j * ldi + i] = val;
     }
   }
-  if (nr <= 0) return;
-  // X = A * inv(L)^T. Wave w: row blocks 2(w&1), 2(w&1)+1; column blocks
-  // {0,3} or {1,2} (equal MFMA counts, since column block c needs k < 16(c+1)).
-  // D = V * A^T per 16x16 block: element v of lane l is X(row 16rb + l%16,
-  // column 16cb + 4v + l/16), so stores are coalesced along the rows.
+  // X = A * inv(L)^T for each of this member's row tiles (the first was
+  // staged with the diagonal tile). Wave w: row blocks 2(w&1), 2(w&1)+1;
+  // column blocks {0,3} or {1,2} (equal MFMA counts, since column block c
+  // needs k < 16(c+1)). D = V * A^T per 16x16 block: element v of lane l is
+  // X(row 16rb + l%16, column 16cb + 4v + l/16), so stores are coalesced along
+  // the rows.
   const int rb0 = 2 * (wave & 1);
   const int kpad = (nb + 3) & ~3;
   double mx_step = 0.0, mx_anc = 0.0;
+  for (int rt = 0; rt < t.nrt; ++rt) {
+    const int row0 = t.row0 + 64 * rt;
+    const int nrt_rows = min(64, t.nrows - row0);
+    if (rt > 0) {
+      __syncthreads();  // the previous tile's reads of sA are done
+      const int row = lane, cg = wave;
+      const int arow = row0 + min(row, nrt_rows - 1);
+      double av[16];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int cb = (wave >> 1) ? 1 + h : 3 * h;
-    const int nk = min(16 * (cb + 1), kpad) >> 2;  // k-steps of 4
-    v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-    for (int s = 0; s < nk; s += 4) {
-      double vv[4], b0[4], b1[4];
+      for (int i = 0; i < 16; ++i) av[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + arow];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = 4 * (s + u) + (lane >> 4);  // < 64 for every s + u < 16
-        vv[u] = I[(16 * cb + (lane & 15)) * TP + k];
-        b0[u] = sA[k * AP + 16 * rb0 + (lane & 15)];
-        b1[u] = sA[k * AP + 16 * (rb0 + 1) + (lane & 15)];
+      for (int i = 0; i < 16; ++i) {
+        const int j = cg + 4 * i;
+        sA[j * AP + row] = (row < nrt_rows && j < nb) ? av[i] : 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (s + u < nk) {
-          a0 = mfma64(vv[u], b0[u], a0);
-          a1 = mfma64(vv[u], b1[u], a1);
-        }
+      __syncthreads();
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int c = 16 * cb + 4 * v + (lane >> 4);
-      const int r0 = 16 * rb0 + (lane & 15), r1 = r0 + 16;
-      if (c < nb) {
-        if (r0 < nr) D[(int64_t)c * ldi + t.row0 + r0] = a0[v];
-        if (r1 < nr) D[(int64_t)c * ldi + t.row0 + r1] = a1[v];
+    for (int h = 0; h < 2; ++h) {
+      const int cb = (wave >> 1) ? 1 + h : 3 * h;
+      const int nk = min(16 * (cb + 1), kpad) >> 2;  // k-steps of 4
+      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+      for (int s = 0; s < nk; s += 4) {
+        double vv[4], b0[4], b1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = 4 * (s + u) + (lane >> 4);  // < 64 for every s + u < 16
+          vv[u] = I[(16 * cb + (lane & 15)) * TP + k];
+          b0[u] = sA[k * AP + 16 * rb0 + (lane & 15)];
+          b1[u] = sA[k * AP + 16 * (rb0 + 1) + (lane & 15)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (s + u < nk) {
+            a0 = mfma64(vv[u], b0[u], a0);
+            a1 = mfma64(vv[u], b1[u], a1);
+          }
       }
-      if (MODE == 2) {
-        // |x| of a non-negative double orders like its bit pattern
-        const double x0 = (c < nb && r0 < nr) ? fabs(a0[v]) : 0.0;
-        const double x1 = (c < nb && r1 < nr) ? fabs(a1[v]) : 0.0;
-        const double xa0 = t.row0 + r0 >= t.rw ? x0 : 0.0, xa1 = t.row0 + r1 >= t.rw ? x1 : 0.0;
-        mx_step = fmax(mx_step, fmax(x0, x1));
-        mx_anc = fmax(mx_anc, fmax(xa0, xa1));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * cb + 4 * v + (lane >> 4);
+        const int r0 = 16 * rb0 + (lane & 15), r1 = r0 + 16;
+        if (c < nb) {
+          if (r0 < nrt_rows) D[(int64_t)c * ldi + row0 + r0] = a0[v];
+          if (r1 < nrt_rows) D[(int64_t)c * ldi + row0 + r1] = a1[v];
+        }
+        if (MODE == 2) {
+          // |x| of a non-negative double orders like its bit pattern
+          const double x0 = (c < nb && r0 < nrt_rows) ? fabs(a0[v]) : 0.0;
+          const double x1 = (c < nb && r1 < nrt_rows) ? fabs(a1[v]) : 0.0;
+          const double xa0 = row0 + r0 >= t.rw ? x0 : 0.0, xa1 = row0 + r1 >= t.rw ? x1 : 0.0;
+          mx_step = fmax(mx_step, fmax(x0, x1));
+          mx_anc = fmax(mx_anc, fmax(xa0, xa1));
+        }
       }
     }
   }
-  if (MODE == 2) {
+  if (MODE == 2 && t.nrt > 0) {
     atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mx_step));
     atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mx_anc));
     __syncthreads();

@@ -196,10 +196,22 @@ int build_plan(Symbolic& s, std::string& err) {
     for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
       steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
     for (int64_t k = 0; k < steps; ++k) {
-      // PANEL: one group per supernode with a column block k, one tile per
-      // 64 rows below the diagonal tile (a single tile when there are none)
+      // PANEL: one group per supernode with a column block k, one workgroup
+      // per 64 rows below the diagonal tile (a single one when there are
+      // none); in launches with more than panel_spread row tiles a
+      // workgroup takes several consecutive row tiles, so that the redundant
+      // factorization of the diagonal tile is not repeated needlessly
       Launch lp{LAUNCH_PANEL, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
       int32_t ngroups = 0;
+      int64_t ntiles = 0;
+      for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+        int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
+        if (k * NB >= w) continue;
+        int64_t c0 = k * NB, nb = std::min<int64_t>(NB, w - c0);
+        ntiles += std::max<int64_t>(1, (m - c0 - nb + 63) / 64);
+      }
+      const int64_t spread = std::max(1, s.opt.panel_spread);
+      const int64_t per = std::max<int64_t>(1, (ntiles + spread - 1) / spread);
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         if (k * NB >= w) continue;
@@ -209,7 +221,8 @@ int build_plan(Symbolic& s, std::string& err) {
         // counts nb..1) plus TRSM of the rows below (nb^2 per row)
         for (int64_t t = 0; t < nb; ++t) p.flops_panel += (double)(nb - t) * (double)(nb - t);
         p.flops_panel += (double)below * (double)nb * (double)nb;
-        int64_t nt = std::max<int64_t>(1, (below + 63) / 64);
+        int64_t nt = (below + 63) / 64;  // row tiles
+        int64_t nwg = std::max<int64_t>(1, (nt + per - 1) / per);
         PanelTile pt;
         pt.diag = p.off[J] + c0 * m + c0;
         pt.ld = (int32_t)m;
@@ -218,13 +231,13 @@ int build_plan(Symbolic& s, std::string& err) {
         pt.col = (int32_t)(s.sn_ptr[J] + c0);
         pt.slot = 0;
         pt.grp = ngroups++;
-        pt.gcnt = (int32_t)nt;
+        pt.gcnt = (int32_t)nwg;
         pt.s_step = sbase[J] + (int32_t)k;
         pt.s_anc = anc_slot(J);
         pt.rw = (int32_t)(w - c0);
-        pt.pad = 0;
-        for (int64_t t = 0; t < nt; ++t) {
-          pt.row0 = (int32_t)(nb + 64 * t);
+        for (int64_t g = 0; g < nwg; ++g) {
+          pt.row0 = (int32_t)(nb + 64 * per * g);
+          pt.nrt = (int32_t)std::min<int64_t>(per, std::max<int64_t>(0, nt - per * g));
           p.panels.push_back(pt);
         }
       }

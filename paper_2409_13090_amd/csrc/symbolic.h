@@ -16,7 +16,7 @@ struct AnalyzeOptions {
   int reorder = 1;
   int maximal_blocks = 1;
   int precision = 0;
-  int tile_policy = 0;
+  int panel_spread = 512;  // row tiles a panel launch spreads over workgroups
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its
@@ -66,7 +66,7 @@ struct PanelTile {
   int32_t s_step;     // scale slot of this column block (16-bit update forms)
   int32_t s_anc;      // scale slot of the supernode's rows below its diagonal block
   int32_t rw;         // first row, relative to the diagonal tile, below the diagonal block
-  int32_t pad;
+  int32_t nrt;        // 64-row tiles handled, from row0 on
 };
 static_assert(sizeof(PanelTile) == 56, "PanelTile layout");
 

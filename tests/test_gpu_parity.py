@@ -72,6 +72,19 @@ def test_supernode_wider_than_many_panels():
     compare_factor(num.export(), f, A.n)
 
 
+def test_panel_workgroups_with_several_row_tiles():
+    """Panel launches whose workgroups each take several consecutive 64-row
+    tiles (the spread of busy launches, forced low here)."""
+    A = W.small_grid("7pt", (17, 17, 17), seed=33, shift=1e-4)
+    s = rlb.Symbolic.from_matrix(A, panel_spread=3)
+    assert s.array("panel_tiles").reshape(-1, 11)[:, 10].max() > 1
+    o, f = oracle_factor(A)
+    s2, num, vals, info = gpu_factor(A, panel_spread=3)
+    assert info == 0
+    compare_factor(num.export(), f, A.n)
+    solve_check(num, A)
+
+
 def test_edge_cases_tiny_diagonal_chain():
     torch = _torch()
     # n = 1

@@ -123,6 +123,7 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* out);
  * target offset, ldc, m, n, flags, first contribution, contribution count),
  * "update_segs" (9 per contribution: X and Y source offsets, source ld, k,
  * tile rows [ra, rb), tile columns [ca, cb), source supernode),
+ * "diag_tiles" (3 per 64-column step: diagonal offset, ld, nb),
  * "panel_tiles" (11 per workgroup: diagonal offset, ld, nb, nrows, row0,
  * column, status slot, group counter, group size, first row below the
  * diagonal block, number of 64-row tiles from row0) and "launches" (5 per launch:

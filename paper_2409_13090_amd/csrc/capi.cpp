@@ -53,6 +53,7 @@ struct DevPlan {
   PanelTile* panels = nullptr;
   UpdTile* updates = nullptr;
   UpdSeg* segs = nullptr;
+  DiagTile* dtiles = nullptr;
   int64_t* amap = nullptr;
   SolveTile* stiles = nullptr;
   int32_t* gl = nullptr;
@@ -64,6 +65,7 @@ struct DevPlan {
     dfree(panels);
     dfree(updates);
     dfree(segs);
+    dfree(dtiles);
     dfree(amap);
     dfree(stiles);
     dfree(gl);
@@ -254,6 +256,8 @@ struct rlb_batch_s {
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
   std::vector<UpdSeg> segs;
+  std::vector<DiagTile> dtiles;
+  DiagTile* d_dtiles = nullptr;
   PanelTile* d_panels = nullptr;
   UpdTile* d_updates = nullptr;
   UpdSeg* d_segs = nullptr;
@@ -278,6 +282,7 @@ struct rlb_batch_s {
     dfree(d_panels);
     dfree(d_updates);
     dfree(d_segs);
+    dfree(d_dtiles);
     dfree(d_amap);
     dfree(d_nnz_ptr);
     if (d_vals) (void)hipFree((void*)d_vals);
@@ -423,6 +428,11 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       int64_t v[7] = {t.c, t.ldc, t.m, t.n, t.flags, t.seg0, t.nseg};
       tmp.insert(tmp.end(), v, v + 7);
     }
+  } else if (w == "diag_tiles") {  // diag, ld, nb per diagonal tile
+    for (const DiagTile& t : s.plan.dtiles) {
+      int64_t v[3] = {t.diag, t.ld, t.nb};
+      tmp.insert(tmp.end(), v, v + 3);
+    }
   } else if (w == "solve_tiles") {  // off, ld, f, w, gl, c0, nb, r0, r1, flags, pad per tile
     for (const SolveTile& t : s.plan.stiles) {
       int64_t v[11] = {t.off, t.ld, t.f, t.w, t.gl, t.c0, t.nb, t.r0, t.r1, t.flags, t.pad};
@@ -482,6 +492,7 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if ((st = upload(&h->d.panels, s.plan.panels))) return st;
   if ((st = upload(&h->d.updates, s.plan.updates))) return st;
   if ((st = upload(&h->d.segs, s.plan.segs))) return st;
+  if ((st = upload(&h->d.dtiles, s.plan.dtiles))) return st;
   if ((st = upload(&h->d.amap, s.plan.amap))) return st;
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
@@ -524,6 +535,7 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
                    h->amax, u, h->smax, nfixed, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
+  launch_tile_inverse(h->d.dtiles, (int64_t)p.dtiles.size(), L, st);
 }
 
 rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size_t ws_bytes,
@@ -893,6 +905,12 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
   if ((st = upload(&b->d_panels, b->panels))) return st;
   if ((st = upload(&b->d_updates, b->updates))) return st;
   if ((st = upload(&b->d_segs, b->segs))) return st;
+  for (int32_t i = 0; i < count; ++i)
+    for (DiagTile d : syms[i]->s.plan.dtiles) {
+      d.diag += b->base[i];
+      b->dtiles.push_back(d);
+    }
+  if ((st = upload(&b->d_dtiles, b->dtiles))) return st;
   if ((st = upload(&b->d_amap, amap))) return st;
   if ((st = upload(&b->d_nnz_ptr, b->nnz_ptr))) return st;
   HIP_OK(hipMalloc((void**)&b->d_vals, sizeof(double*) * count));
@@ -920,6 +938,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
       launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, nullptr, nullptr,
                    0.0, nullptr, nullptr, st);
   }
+  launch_tile_inverse(b->d_dtiles, (int64_t)b->dtiles.size(), L, st);
 }
 
 rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* workspace,

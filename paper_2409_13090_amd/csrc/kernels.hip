@@ -71,13 +71,11 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 // A group is the set of workgroups that share one diagonal tile: one per 64
 // rows below it (or a single one when there are none), or one per few
 // consecutive 64-row tiles in launches that hold many. Every member stages
-// the unfactored tile into LDS, factors it there redundantly, forms inv(L) of
-// the tile and overwrites its own row tiles A with X = A * inv(L)^T. After
-// staging, each member increments the group's counter; the member that brings
-// it to the group size is the last reader of the unfactored tile, and only it
-// writes the factored tile back (L in the lower triangle, the strict lower
-// part of inv(L) transposed into the unused strict upper triangle, where the
-// solves read it). It also resets the counter for the next launch.
+// the unfactored tile into LDS, factors it there redundantly and overwrites
+// its own row tiles A with X = A * L^-T. After staging, each member
+// increments the group's counter; the member that brings it to the group
+// size is the last reader of the unfactored tile, and only it writes the
+// factored tile back. It also resets the counter for the next launch.
 //
 // Factorization of the tile T (identity beyond nb) in 16-column rounds. In
 // round r, wavefront 0 factors the 64 x 16 column block r in registers
@@ -88,9 +86,9 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 // inverts the 16 x 16 diagonal block r-1; then all wavefronts update column
 // block r+1 with block r on MFMA. The pivot reciprocal is an rsq with two
 // Newton steps; the stored diagonal is the correctly rounded square root.
-// inv(L) follows from the 16 x 16 inverses by two levels of the 2 x 2 block
-// formula [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1]. X = A * inv(L)^T is a
-// 64x64 MFMA product that skips inv(L)^T's zero lower part.
+// The row tiles are solved by block forward substitution with the 16 x 16
+// inverses, on MFMA. The inverse of the whole tile, which the solves use, is
+// formed after the factorization by k_tile_inverse.
 
 __device__ __forceinline__ double lane_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -305,39 +303,10 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
     if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, r + 1 + wave, r + 1, r, lane);
     __syncthreads();
   }
-  if (wave == 0) inv16(T, I, 16 * (nbb - 1), lane);
-  __syncthreads();
-  // inv(L), level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
-  {
-    const int i1 = wave == 0 ? 1 : 3;
-    if ((wave == 0 && nbb >= 2) || (wave == 1 && nbb >= 4)) {
-      const v4d s = mma16(&T[16 * i1 * TP + 16 * (i1 - 1)], TP, 1,
-                          &I[16 * (i1 - 1) * TP + 16 * (i1 - 1)], TP, 1, lane);
-      const v4d u = mma16r(&I[16 * i1 * TP + 16 * i1], TP, 1, s, lane);
-      st16(&I[16 * i1 * TP + 16 * (i1 - 1)], u, lane, -1.0);
-    }
-  }
-  __syncthreads();
-  // level 2 (nbb >= 3): for i in [2, nbb), j in {0, 1}:
-  //   S(i,j) = L(i,0) inv(0,j) + L(i,1) inv(1,j)   (wave 2(i-2)+j, via LDS: T's
-  //   unused block (j, i)), then inv(i,j) = -sum_{2 <= l <= i} inv(i,l) S(l,j)
-  const int i2 = 2 + (wave >> 1), j2 = wave & 1;
-  const bool p2 = nbb >= 3 && i2 < nbb;
-  if (p2) {
-    v4d s = mma16(&T[16 * i2 * TP + 16], TP, 1, &I[16 * TP + 16 * j2], TP, 1, lane);
-    if (j2 == 0) s += mma16(&T[16 * i2 * TP], TP, 1, &I[0], TP, 1, lane);
-    st16(&T[16 * j2 * TP + 16 * i2], s, lane, 1.0);
-  }
-  __syncthreads();
-  if (p2) {
-    v4d u = {0, 0, 0, 0};
-    for (int l = 2; l <= i2; ++l)
-      u += mma16(&I[16 * i2 * TP + 16 * l], TP, 1, &T[16 * j2 * TP + 16 * l], TP, 1, lane);
-    st16(&I[16 * i2 * TP + 16 * j2], u, lane, -1.0);
-  }
-  __syncthreads();
-  // the last reader writes the factored tile: L below and on the diagonal,
-  // inv(L) strict lower part transposed above it
+  // the last base inverse (wave 3) alongside the first column blocks of the
+  // row tiles' solves
+  if (wave == 3) inv16(T, I, 16 * (nbb - 1), lane);
+  // the last reader writes the factored tile (lower triangle)
   if (s_last) {
     if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
     if (MODE >= 1 && wave == 0 && lane == 0 && nfix) atomicAdd(nfixed + t.slot, (unsigned)nfix);
@@ -345,18 +314,16 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
-      const double val = (i >= j) ? T[i * TP + j] : I[j * TP + i];
-      if (i < nb && j < nb) D[(int64_t)j * ldi + i] = val;
+      if (i < nb && j < nb && i >= j) D[(int64_t)j * ldi + i] = T[i * TP + j];
     }
   }
-  // X = A * inv(L)^T for each of this member's row tiles (the first was
-  // staged with the diagonal tile). Wave w: row blocks 2(w&1), 2(w&1)+1;
-  // column blocks {0,3} or {1,2} (equal MFMA counts, since column block c
-  // needs k < 16(c+1)). D = V * A^T per 16x16 block: element v of lane l is
-  // X(row 16rb + l%16, column 16cb + 4v + l/16), so stores are coalesced along
-  // the rows.
-  const int rb0 = 2 * (wave & 1);
-  const int kpad = (nb + 3) & ~3;
+  // X = A * L^-T for each of this member's row tiles (the first was staged
+  // with the diagonal tile), by block forward substitution over the column
+  // blocks: X_b = (A_b - sum_{c<b} X_c L_bc^T) inv(L_bb)^T. Wave w owns rows
+  // 16w..16w+15 of the tile and keeps its X_c^T blocks in MFMA result layout
+  // (element v of lane l is X(16w + l%16, 16c + 4v + l/16)), which is also
+  // the B-operand layout of the next products, so X never goes through LDS.
+  const int rb = wave;
   double mx_step = 0.0, mx_anc = 0.0;
   for (int rt = 0; rt < t.nrt; ++rt) {
     const int row0 = t.row0 + 64 * rt;
@@ -375,46 +342,43 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
       }
       __syncthreads();
     }
+    v4d X[4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cb = (wave >> 1) ? 1 + h : 3 * h;
-      const int nk = min(16 * (cb + 1), kpad) >> 2;  // k-steps of 4
-      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-      for (int s = 0; s < nk; s += 4) {
-        double vv[4], b0[4], b1[4];
+    for (int b = 0; b < 4; ++b) {
+      if (b == nbb - 1 && rt == 0) __syncthreads();  // inv(L_bb) of the last block is ready
+      X[b] = v4d{0, 0, 0, 0};
+      if (b < nbb) {
+        v4d r;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = 4 * (s + u) + (lane >> 4);  // < 64 for every s + u < 16
-          vv[u] = I[(16 * cb + (lane & 15)) * TP + k];
-          b0[u] = sA[k * AP + 16 * rb0 + (lane & 15)];
-          b1[u] = sA[k * AP + 16 * (rb0 + 1) + (lane & 15)];
-        }
+        for (int v = 0; v < 4; ++v)
+          r[v] = sA[(16 * b + 4 * v + (lane >> 4)) * AP + 16 * rb + (lane & 15)];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (s + u < nk) {
-            a0 = mfma64(vv[u], b0[u], a0);
-            a1 = mfma64(vv[u], b1[u], a1);
+        for (int c = 0; c < b; ++c)
+#pragma unroll
+          for (int kq = 0; kq < 4; ++kq)
+            r = mfma64(-T[(16 * b + (lane & 15)) * TP + 16 * c + 4 * kq + (lane >> 4)], X[c][kq], r);
+        v4d x = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+          x = mfma64(I[(16 * b + (lane & 15)) * TP + 16 * b + 4 * kq + (lane >> 4)], r[kq], x);
+        X[b] = x;
+        const int rr = 16 * rb + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * b + 4 * v + (lane >> 4);
+          const bool ok = c < nb && rr < nrt_rows;
+          if (ok) D[(int64_t)c * ldi + row0 + rr] = x[v];
+          if (MODE == 2) {
+            // |x| of a non-negative double orders like its bit pattern
+            const double ax = ok ? fabs(x[v]) : 0.0;
+            mx_step = fmax(mx_step, ax);
+            mx_anc = fmax(mx_anc, row0 + rr >= t.rw ? ax : 0.0);
           }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = 16 * cb + 4 * v + (lane >> 4);
-        const int r0 = 16 * rb0 + (lane & 15), r1 = r0 + 16;
-        if (c < nb) {
-          if (r0 < nrt_rows) D[(int64_t)c * ldi + row0 + r0] = a0[v];
-          if (r1 < nrt_rows) D[(int64_t)c * ldi + row0 + r1] = a1[v];
-        }
-        if (MODE == 2) {
-          // |x| of a non-negative double orders like its bit pattern
-          const double x0 = (c < nb && r0 < nrt_rows) ? fabs(a0[v]) : 0.0;
-          const double x1 = (c < nb && r1 < nrt_rows) ? fabs(a1[v]) : 0.0;
-          const double xa0 = row0 + r0 >= t.rw ? x0 : 0.0, xa1 = row0 + r1 >= t.rw ? x1 : 0.0;
-          mx_step = fmax(mx_step, fmax(x0, x1));
-          mx_anc = fmax(mx_anc, fmax(xa0, xa1));
         }
       }
     }
   }
+  if (t.nrt == 0) __syncthreads();  // keep the barrier count uniform
   if (MODE == 2 && t.nrt > 0) {
     atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mx_step));
     atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mx_anc));
@@ -423,6 +387,73 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
       atomicMax(smax + t.s_step, s_max[0]);
       if (s_max[1]) atomicMax(smax + t.s_anc, s_max[1]);
     }
+  }
+}
+
+// Inverse of every diagonal tile of the factor, for the solves: inv(L_kk)
+// of the <=64x64 tile goes, strict lower part transposed, into the tile's
+// unused strict upper triangle (inv(L)(i,j), i > j, at row j of column i).
+// One workgroup per tile: the 16x16 diagonal blocks are inverted by
+// substitution (one wavefront each), then the 2 x 2 block formula
+// [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1] joins them in two levels.
+__global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict__ tiles,
+                                                      double* __restrict__ L) {
+  const DiagTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = t.nb, ldi = t.ld;
+  double* D = L + t.diag;
+  __shared__ double T[64 * TP];
+  __shared__ double I[64 * TP];
+  {
+    const int row = lane, cg = wave;
+    const int dr = min(row, nb - 1);
+    double dv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dv[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + dr];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int j = cg + 4 * i;
+      T[row * TP + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  const int nbb = (nb + 15) >> 4;
+  if (wave < nbb) inv16(T, I, 16 * wave, lane);
+  __syncthreads();
+  // level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
+  {
+    const int i1 = wave == 0 ? 1 : 3;
+    if ((wave == 0 && nbb >= 2) || (wave == 1 && nbb >= 4)) {
+      const v4d s = mma16(&T[16 * i1 * TP + 16 * (i1 - 1)], TP, 1,
+                          &I[16 * (i1 - 1) * TP + 16 * (i1 - 1)], TP, 1, lane);
+      const v4d u = mma16r(&I[16 * i1 * TP + 16 * i1], TP, 1, s, lane);
+      st16(&I[16 * i1 * TP + 16 * (i1 - 1)], u, lane, -1.0);
+    }
+  }
+  __syncthreads();
+  // level 2 (nbb >= 3): for i in [2, nbb), j in {0, 1}: S(i,j) = L(i,0)
+  // inv(0,j) + L(i,1) inv(1,j), kept in T's unused block (j, i), then
+  // inv(i,j) = -sum_{2 <= l <= i} inv(i,l) S(l,j)
+  const int i2 = 2 + (wave >> 1), j2 = wave & 1;
+  const bool p2 = nbb >= 3 && i2 < nbb;
+  if (p2) {
+    v4d s = mma16(&T[16 * i2 * TP + 16], TP, 1, &I[16 * TP + 16 * j2], TP, 1, lane);
+    if (j2 == 0) s += mma16(&T[16 * i2 * TP], TP, 1, &I[0], TP, 1, lane);
+    st16(&T[16 * j2 * TP + 16 * i2], s, lane, 1.0);
+  }
+  __syncthreads();
+  if (p2) {
+    v4d u = {0, 0, 0, 0};
+    for (int l = 2; l <= i2; ++l)
+      u += mma16(&I[16 * i2 * TP + 16 * l], TP, 1, &T[16 * j2 * TP + 16 * l], TP, 1, lane);
+    st16(&I[16 * i2 * TP + 16 * j2], u, lane, -1.0);
+  }
+  __syncthreads();
+  const int i = lane;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int j = wave + 4 * q;
+    if (i < j && j < nb) D[(int64_t)j * ldi + i] = I[j * TP + i];
   }
 }
 
@@ -1180,6 +1211,10 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
   else
     hipLaunchKernelGGL(k_panel<2>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
                        counters, thr, amax, ufix, smax, nfixed);
+}
+void launch_tile_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_tile_inverse, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, hipStream_t st) {

@@ -393,6 +393,11 @@ int build_plan(Symbolic& s, std::string& err) {
       if (lu.count) p.launches.push_back(lu);
     }
   }
+  // diagonal tiles of every 64-column step, inverted after the factorization
+  for (int64_t J = 0; J < S; ++J)
+    for (int64_t c0 = 0; c0 < W(J); c0 += NB)
+      p.dtiles.push_back(DiagTile{p.off[J] + c0 * M(J) + c0, (int32_t)M(J),
+                                  (int32_t)std::min<int64_t>(NB, W(J) - c0)});
   // solves: forward by level and 64-column step (row tiles of 256 below the
   // chunk), backward by level from the root: first every column chunk against
   // the ancestor rows (segments of 512 rows), then the steps from the last

@@ -70,6 +70,14 @@ struct PanelTile {
 };
 static_assert(sizeof(PanelTile) == 56, "PanelTile layout");
 
+// A diagonal tile of the factor (see k_tile_inverse).
+struct DiagTile {
+  int64_t diag;  // offset of its top-left element
+  int32_t ld;
+  int32_t nb;
+};
+static_assert(sizeof(DiagTile) == 16, "DiagTile layout");
+
 // Work item of the supernodal solves, one workgroup each (see k_fwd_step,
 // k_bwd_below, k_bwd_step). Columns and rows are relative to the supernode.
 struct SolveTile {
@@ -121,6 +129,7 @@ struct Plan {
   std::vector<UpdSeg> segs;
   int32_t n_scale_slots = 0;     // per column block of every supernode, plus one per supernode
   std::vector<int64_t> diag_src; // input entry of the diagonal of every factored column
+  std::vector<DiagTile> dtiles;       // every 64-column step's diagonal tile
   std::vector<SolveTile> stiles;      // solve work items, launch by launch
   std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
   std::vector<Launch> launches;

@@ -529,7 +529,8 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax, st);
+      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
+                    l.shortk != 0, st);
     else
       launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, h->thr,
                    h->amax, u, h->smax, nfixed, st);
@@ -862,7 +863,7 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
       }
     }
     if (!any) break;
-    Launch m{bk, bl, bs, 0, 0, 0};
+    Launch m{bk, bl, bs, 1, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
@@ -870,6 +871,7 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
       if (cur[i] >= p.launches.size()) continue;
       const Launch& l = p.launches[cur[i]];
       if (l.level != bl || l.step != bs || l.kind != bk) continue;
+      m.shortk &= l.shortk;
       if (bk != LAUNCH_UPDATE) {
         int32_t g_hi = 0;
         for (int64_t t = 0; t < l.count; ++t) {
@@ -933,7 +935,8 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   launch_scatter_batch(b->d_vals, b->d_nnz_ptr, count, b->nnz_ptr[count], b->d_amap, L, st);
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
-      launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr, st);
+      launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
+                    l.shortk != 0, st);
     else
       launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, nullptr, nullptr,
                    0.0, nullptr, nullptr, st);

@@ -25,7 +25,7 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   int precision, const double* thr, const unsigned long long* amax, double ufix,
                   unsigned long long* smax, unsigned int* nfixed, hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, hipStream_t st);
+                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st);
 void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
                    unsigned long long* amax, hipStream_t st);

@@ -660,6 +660,94 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
 
+// The same update for launches whose tiles all hold a single contribution
+// with k <= 64 and a single owner (the trailing updates of a step): every
+// load of K is issued up front, so the tile waits for memory once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_short(const UpdTile* __restrict__ tiles,
+                                                      const UpdSeg* __restrict__ segs,
+                                                      double* __restrict__ L) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const UpdTile t = tiles[blockIdx.x];
+  const UpdSeg g = segs[t.seg0];
+  __shared__ T sX[2][KC][64];
+  __shared__ T sY[2][KC][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int lr = tid & 63, lk = tid >> 6;
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
+  const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+  const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
+  double xr[16], yr[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t kk = min(lk + 4 * q, g.k - 1);
+    xr[q] = L[xo + kk * g.lds];
+    yr[q] = L[yo + kk * g.lds];
+  }
+  double cv[2][2][4];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+        const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
+        cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+      }
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  const int nch = (g.k + KC - 1) / KC;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c < nch) {
+      const int buf = c & 1;
+#pragma unroll
+      for (int u = 0; u < KC / 4; ++u) {
+        const int q = 4 * c + u;
+        const bool kin = lk + 4 * q < g.k;
+        sX[buf][lk + 4 * u][lr] = (T)((kin && xin) ? xr[q] : 0.0);
+        sY[buf][lk + 4 * u][lr] = (T)((kin && yin) ? yr[q] : 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const T a0 = sY[buf][kk][wc + (lane & 15)];
+        const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const T b0 = sX[buf][kk][wr + (lane & 15)];
+        const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
+        if (row < t.m && col < t.n && (!diag || row >= col))
+          C[(int64_t)col * ldc + row] = cv[bj][bi][v] - (double)acc[bj][bi][v];
+      }
+}
+
+template __global__ void k_update_short<double>(const UpdTile*, const UpdSeg*, double*);
+template __global__ void k_update_short<float>(const UpdTile*, const UpdSeg*, double*);
+
 // 16-bit operand form of the update. Every contribution's X and Y are scaled
 // by the power of two s = 2^e of its source panel (e chosen so that the
 // panel's largest |entry| times s lies in [2^13, 2^14)), rounded to FP16 or
@@ -1217,10 +1305,15 @@ void launch_tile_inverse(const DiagTile* tiles, int64_t count, double* L, hipStr
   hipLaunchKernelGGL(k_tile_inverse, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, hipStream_t st) {
+                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st) {
   if (count <= 0) return;
   const dim3 g((unsigned)count), b(256);
-  if (precision == 1)
+  if (shortk && precision <= 1) {
+    if (precision == 1)
+      hipLaunchKernelGGL(k_update_short<float>, g, b, 0, st, tiles, segs, L);
+    else
+      hipLaunchKernelGGL(k_update_short<double>, g, b, 0, st, tiles, segs, L);
+  } else if (precision == 1)
     hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L);
   else if (precision == 2)
     hipLaunchKernelGGL(k_update16<2>, g, b, 0, st, tiles, segs, L, smax);

@@ -390,6 +390,14 @@ int build_plan(Symbolic& s, std::string& err) {
         std::copy(sorted.begin(), sorted.end(), p.updates.begin() + lu.start);
       }
       lu.count = (int64_t)p.updates.size() - lu.start;
+      lu.shortk = 1;
+      for (int64_t i = lu.start; i < lu.start + lu.count; ++i) {
+        const UpdTile& t = p.updates[i];
+        if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || p.segs[t.seg0].k > 64) {
+          lu.shortk = 0;
+          break;
+        }
+      }
       if (lu.count) p.launches.push_back(lu);
     }
   }

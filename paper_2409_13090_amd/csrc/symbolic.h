@@ -114,7 +114,7 @@ struct Launch {
   int32_t kind;   // LAUNCH_*
   int32_t level;
   int32_t step;   // column block index inside the level
-  int32_t pad;
+  int32_t shortk; // update launch whose tiles all have one contribution, k <= 64, one owner
   int64_t start;  // first tile
   int64_t count;  // number of tiles
 };

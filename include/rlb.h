@@ -231,6 +231,26 @@ rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int6
                            void* stream);
 void rlb_batch_free(rlb_batch b);
 
+/* Level schedule of a batch: which levels of the matrices share a launch.
+ * LEAVES aligns every matrix's leaves (level 0 of all matrices together),
+ * ROOTS aligns the roots, CENTERED shifts each matrix by half the difference.
+ * Every schedule gives the same factors; they differ in launch count and
+ * balance. rlb_batch_create starts with LEAVES. Synchronizes the device and
+ * drops the captured graph. Errors: RLB_ERR_ARG, RLB_ERR_HIP, RLB_ERR_ALLOC. */
+#define RLB_BATCH_SCHED_LEAVES 0
+#define RLB_BATCH_SCHED_ROOTS 1
+#define RLB_BATCH_SCHED_CENTERED 2
+rlb_status rlb_batch_set_schedule(rlb_batch b, int32_t schedule);
+
+/* Autotune the level schedule: factor the batch (same arguments as
+ * rlb_batch_factor) once untimed and `reps` times timed with HIP events under
+ * each schedule, keep the fastest. *chosen (may be NULL) receives it and ms
+ * (may be NULL, 3 entries) the mean milliseconds of each. The workspace holds
+ * a valid factorization afterwards. Errors: as rlb_batch_factor. */
+rlb_status rlb_batch_autotune(rlb_batch b, const double* const* values, void* workspace,
+                              size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen,
+                              double* ms);
+
 /* Record the factor's launch sequence in a HIP graph on first use and replay
  * it on later rlb_factor / rlb_batch_factor calls with the same buffers. */
 rlb_status rlb_set_graph_mode(rlb_numeric num, int32_t on);

@@ -256,7 +256,8 @@ struct rlb_batch_s {
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
   std::vector<UpdSeg> segs;
-  std::vector<DiagTile> dtiles;
+  std::vector<DiagTile> dtiles;  // by width class, as in a plan
+  int64_t dt_ptr[4] = {0, 0, 0, 0};
   DiagTile* d_dtiles = nullptr;
   PanelTile* d_panels = nullptr;
   UpdTile* d_updates = nullptr;
@@ -268,6 +269,8 @@ struct rlb_batch_s {
   int* counters = nullptr;
   int ncounters = 0;
   std::vector<DevPlan> per;  // solve data of every matrix
+  std::vector<int64_t> segbase;  // first contribution of every matrix
+  int32_t schedule = -1;         // RLB_BATCH_SCHED_*
   SolveScratch sc;
   double* L = nullptr;
   bool factored = false;
@@ -530,13 +533,16 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE)
       launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
-                    l.shortk != 0, st);
+                    l.variant != 0, st);
     else
-      launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, h->thr,
-                   h->amax, u, h->smax, nfixed, st);
+      launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, l.variant,
+                   h->thr, h->amax, u, h->smax, nfixed, st);
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
-  launch_tile_inverse(h->d.dtiles, (int64_t)p.dtiles.size(), L, st);
+  const int cls_nbb[3] = {1, 2, 4};
+  for (int ci = 0; ci < 3; ++ci)
+    launch_tile_inverse(h->d.dtiles + p.dt_ptr[ci], p.dt_ptr[ci + 1] - p.dt_ptr[ci], cls_nbb[ci],
+                        L, st);
 }
 
 rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size_t ws_bytes,
@@ -811,6 +817,101 @@ rlb_status rlb_last_profile(rlb_numeric h, double* update_ms, double* panel_ms, 
 // ---------------------------------------------------------------------------
 // batched form
 
+// Merged launch lists of a batch: for each (shifted level, step, kind) the
+// tiles of every matrix, in matrix order. The level of matrix i is shifted
+// by 0 (leaves aligned), by (max levels - its levels) (roots aligned) or by
+// half of that (centered); each matrix keeps its own launch order, and
+// matrices are independent, so every schedule computes the same factors.
+static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
+  const int32_t count = (int32_t)b->syms.size();
+  const auto& syms = b->syms;
+  int32_t maxlev = 0;
+  for (int32_t i = 0; i < count; ++i) maxlev = std::max(maxlev, syms[i]->s.plan.nlevels);
+  std::vector<int32_t> shift(count, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    int32_t gap = maxlev - syms[i]->s.plan.nlevels;
+    shift[i] = schedule == RLB_BATCH_SCHED_ROOTS ? gap
+               : schedule == RLB_BATCH_SCHED_CENTERED ? gap / 2 : 0;
+  }
+  const std::vector<int64_t>& segbase = b->segbase;
+  b->launches.clear();
+  b->panels.clear();
+  b->updates.clear();
+  b->ncounters = 0;
+  // merge: for each (level, step, kind) the tiles of every matrix, in matrix order
+  std::vector<size_t> cur(count, 0);
+  for (;;) {
+    // the smallest (level, step, kind) among the matrices' next launches
+    bool any = false;
+    int32_t bl = 0, bs = 0, bk = 0, bv = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      const auto& L = syms[i]->s.plan.launches;
+      if (cur[i] >= L.size()) continue;
+      const Launch& l = L[cur[i]];
+      const int32_t lv = l.level + shift[i];
+      const int32_t vv = l.kind == LAUNCH_PANEL ? l.variant : 0;
+      if (!any || std::make_tuple(lv, l.step, l.kind, vv) < std::make_tuple(bl, bs, bk, bv)) {
+        bl = lv;
+        bs = l.step;
+        bk = l.kind;
+        bv = vv;
+        any = true;
+      }
+    }
+    if (!any) break;
+    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0};
+    int32_t gbase = 0;  // group counters are numbered across the merged matrices
+    m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
+    for (int32_t i = 0; i < count; ++i) {
+      const Plan& p = syms[i]->s.plan;
+      if (cur[i] >= p.launches.size()) continue;
+      const Launch& l = p.launches[cur[i]];
+      if (l.level + shift[i] != bl || l.step != bs || l.kind != bk) continue;
+      if (bk == LAUNCH_PANEL && l.variant != bv) continue;
+      if (bk == LAUNCH_UPDATE) m.variant &= l.variant;
+      if (bk != LAUNCH_UPDATE) {
+        int32_t g_hi = 0;
+        for (int64_t t = 0; t < l.count; ++t) {
+          PanelTile pt = p.panels[l.start + t];
+          pt.diag += b->base[i];
+          pt.slot = i;
+          g_hi = std::max(g_hi, pt.grp + 1);
+          pt.grp += gbase;
+          b->panels.push_back(pt);
+        }
+        gbase += g_hi;
+      } else {
+        for (int64_t t = 0; t < l.count; ++t) {
+          UpdTile ut = p.updates[l.start + t];
+          ut.c += b->base[i];
+          ut.seg0 += (int32_t)segbase[i];
+          b->updates.push_back(ut);
+        }
+      }
+      cur[i]++;
+    }
+    m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
+              m.start;
+    b->launches.push_back(m);
+    b->ncounters = std::max(b->ncounters, (int)gbase);
+  }
+  dfree(b->d_panels);
+  dfree(b->d_updates);
+  dfree(b->counters);
+  rlb_status st;
+  if ((st = upload(&b->d_panels, b->panels))) return st;
+  if ((st = upload(&b->d_updates, b->updates))) return st;
+  b->ncounters = std::max(1, b->ncounters);
+  HIP_OK(hipMalloc((void**)&b->counters, sizeof(int) * b->ncounters));
+  HIP_OK(hipMemset(b->counters, 0, sizeof(int) * b->ncounters));
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  b->schedule = schedule;
+  return RLB_OK;
+}
+
 rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t precision,
                             rlb_batch* out, int64_t* ws_bytes) {
   if (count < 1 || !syms || !out) return fail(RLB_ERR_ARG, "bad argument");
@@ -845,81 +946,32 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     }
   }
   if (b->segs.size() > (size_t)INT32_MAX) return fail(RLB_ERR_ARG, "batch too large");
-  // merge: for each (level, step, kind) the tiles of every matrix, in matrix order
-  std::vector<size_t> cur(count, 0);
-  for (;;) {
-    // the smallest (level, step, kind) among the matrices' next launches
-    bool any = false;
-    int32_t bl = 0, bs = 0, bk = 0;
-    for (int32_t i = 0; i < count; ++i) {
-      const auto& L = syms[i]->s.plan.launches;
-      if (cur[i] >= L.size()) continue;
-      const Launch& l = L[cur[i]];
-      if (!any || std::make_tuple(l.level, l.step, l.kind) < std::make_tuple(bl, bs, bk)) {
-        bl = l.level;
-        bs = l.step;
-        bk = l.kind;
-        any = true;
-      }
-    }
-    if (!any) break;
-    Launch m{bk, bl, bs, 1, 0, 0};
-    int32_t gbase = 0;  // group counters are numbered across the merged matrices
-    m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
-    for (int32_t i = 0; i < count; ++i) {
-      const Plan& p = syms[i]->s.plan;
-      if (cur[i] >= p.launches.size()) continue;
-      const Launch& l = p.launches[cur[i]];
-      if (l.level != bl || l.step != bs || l.kind != bk) continue;
-      m.shortk &= l.shortk;
-      if (bk != LAUNCH_UPDATE) {
-        int32_t g_hi = 0;
-        for (int64_t t = 0; t < l.count; ++t) {
-          PanelTile pt = p.panels[l.start + t];
-          pt.diag += b->base[i];
-          pt.slot = i;
-          g_hi = std::max(g_hi, pt.grp + 1);
-          pt.grp += gbase;
-          b->panels.push_back(pt);
-        }
-        gbase += g_hi;
-      } else {
-        for (int64_t t = 0; t < l.count; ++t) {
-          UpdTile ut = p.updates[l.start + t];
-          ut.c += b->base[i];
-          ut.seg0 += (int32_t)segbase[i];
-          b->updates.push_back(ut);
-        }
-      }
-      cur[i]++;
-    }
-    m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
-              m.start;
-    b->launches.push_back(m);
-    b->ncounters = std::max(b->ncounters, (int)gbase);
-  }
+  b->segbase = segbase;
+  rlb_status st;
+  if ((st = batch_schedule(b.get(), RLB_BATCH_SCHED_LEAVES))) return st;
   (void)maxlev;
   std::vector<int64_t> amap;
   amap.reserve(b->nnz_ptr[count]);
   for (int32_t i = 0; i < count; ++i)
     for (int64_t a : syms[i]->s.plan.amap) amap.push_back(a + b->base[i]);
-  rlb_status st;
-  if ((st = upload(&b->d_panels, b->panels))) return st;
-  if ((st = upload(&b->d_updates, b->updates))) return st;
   if ((st = upload(&b->d_segs, b->segs))) return st;
-  for (int32_t i = 0; i < count; ++i)
-    for (DiagTile d : syms[i]->s.plan.dtiles) {
-      d.diag += b->base[i];
-      b->dtiles.push_back(d);
+  for (int ci = 0; ci < 3; ++ci) {
+    b->dt_ptr[ci] = (int64_t)b->dtiles.size();
+    for (int32_t i = 0; i < count; ++i) {
+      const Plan& p = syms[i]->s.plan;
+      for (int64_t q = p.dt_ptr[ci]; q < p.dt_ptr[ci + 1]; ++q) {
+        DiagTile d = p.dtiles[q];
+        d.diag += b->base[i];
+        b->dtiles.push_back(d);
+      }
     }
+  }
+  b->dt_ptr[3] = (int64_t)b->dtiles.size();
   if ((st = upload(&b->d_dtiles, b->dtiles))) return st;
   if ((st = upload(&b->d_amap, amap))) return st;
   if ((st = upload(&b->d_nnz_ptr, b->nnz_ptr))) return st;
   HIP_OK(hipMalloc((void**)&b->d_vals, sizeof(double*) * count));
   HIP_OK(hipMalloc((void**)&b->status, sizeof(int) * count));
-  b->ncounters = std::max(1, b->ncounters);
-  HIP_OK(hipMalloc((void**)&b->counters, sizeof(int) * b->ncounters));
-  HIP_OK(hipMemset(b->counters, 0, sizeof(int) * b->ncounters));
   b->per.resize(count);
   for (int32_t i = 0; i < count; ++i)
     if ((st = upload_solve(syms[i]->s, b->base[i], b->per[i]))) return st;
@@ -936,12 +988,15 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
-                    l.shortk != 0, st);
+                    l.variant != 0, st);
     else
-      launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, nullptr, nullptr,
-                   0.0, nullptr, nullptr, st);
+      launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, l.variant,
+                   nullptr, nullptr, 0.0, nullptr, nullptr, st);
   }
-  launch_tile_inverse(b->d_dtiles, (int64_t)b->dtiles.size(), L, st);
+  const int cls_nbb[3] = {1, 2, 4};
+  for (int ci = 0; ci < 3; ++ci)
+    launch_tile_inverse(b->d_dtiles + b->dt_ptr[ci], b->dt_ptr[ci + 1] - b->dt_ptr[ci],
+                        cls_nbb[ci], L, st);
 }
 
 rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* workspace,
@@ -1018,6 +1073,54 @@ rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int6
   if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
   if (nrhs == 0 || s.n == 0) return RLB_OK;
   return solve_into(s, b->per[i], b->sc, b->L, nrhs, B, ldb, B, ldb, (hipStream_t)stream);
+}
+
+rlb_status rlb_batch_set_schedule(rlb_batch b, int32_t schedule) {
+  if (!b || schedule < RLB_BATCH_SCHED_LEAVES || schedule > RLB_BATCH_SCHED_CENTERED)
+    return fail(RLB_ERR_ARG, "bad schedule");
+  if (schedule == b->schedule) return RLB_OK;
+  HIP_OK(hipDeviceSynchronize());
+  b->factored = false;
+  return batch_schedule(b, schedule);
+}
+
+rlb_status rlb_batch_autotune(rlb_batch b, const double* const* values, void* workspace,
+                              size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen,
+                              double* ms) {
+  if (!b || !values || !workspace || reps < 1) return fail(RLB_ERR_ARG, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  double best = 0;
+  int32_t best_s = RLB_BATCH_SCHED_LEAVES;
+  rlb_status r = RLB_OK;
+  for (int32_t sch = RLB_BATCH_SCHED_LEAVES; sch <= RLB_BATCH_SCHED_CENTERED && !r; ++sch) {
+    if ((r = rlb_batch_set_schedule(b, sch))) break;
+    // one untimed factorization (graph capture when enabled), then reps timed
+    if ((r = rlb_batch_factor(b, values, workspace, ws_bytes, stream))) break;
+    float total = 0;
+    for (int32_t k = 0; k < reps && !r; ++k) {
+      (void)hipEventRecord(e0, st);
+      r = rlb_batch_factor(b, values, workspace, ws_bytes, stream);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) r = fail(RLB_ERR_HIP, "event");
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      total += t;
+    }
+    const double avg = total / reps;
+    if (ms) ms[sch] = avg;
+    if (sch == RLB_BATCH_SCHED_LEAVES || avg < best) {
+      best = avg;
+      best_s = sch;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r) return r;
+  if (chosen) *chosen = best_s;
+  return rlb_batch_set_schedule(b, best_s);
 }
 
 rlb_status rlb_batch_set_graph_mode(rlb_batch b, int32_t on) {

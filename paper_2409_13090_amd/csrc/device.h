@@ -22,11 +22,12 @@ void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, doub
 void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
                           int64_t total, const int64_t* amap, double* L, hipStream_t st);
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  int precision, const double* thr, const unsigned long long* amax, double ufix,
-                  unsigned long long* smax, unsigned int* nfixed, hipStream_t st);
+                  int precision, int nbb, const double* thr, const unsigned long long* amax,
+                  double ufix, unsigned long long* smax, unsigned int* nfixed, hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, bool shortk, hipStream_t st);
-void launch_tile_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st);
+void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
+                         hipStream_t st);
 void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
                    unsigned long long* amax, hipStream_t st);
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,

@@ -96,8 +96,6 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-constexpr int TP = 65;  // LDS row pitch of a 64x64 tile (doubles)
-constexpr int AP = 65;  // LDS pitch of the staged row tile: sA[k * AP + r] = A(r, k)
 
 __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -131,62 +129,62 @@ __device__ __forceinline__ v4d mma16r(const double* A, int ar, int ac, const v4d
   return c0 + c1;
 }
 
-// element v of lane l of a 16x16 FP64 MFMA result is D(4v + l/16, l%16)
-__device__ __forceinline__ void st16(double* D, const v4d& acc, int lane, double scale) {
+// element v of lane l of a 16x16 FP64 MFMA result is D(4v + l/16, l%16); row pitch tp
+__device__ __forceinline__ void st16(double* D, int tp, const v4d& acc, int lane, double scale) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) D[(4 * v + (lane >> 4)) * TP + (lane & 15)] = scale * acc[v];
+  for (int v = 0; v < 4; ++v) D[(4 * v + (lane >> 4)) * tp + (lane & 15)] = scale * acc[v];
 }
 
-// T(q, p) -= L(q, b) * L(p, b)^T for 16x16 blocks of the tile
-__device__ __forceinline__ void syrk16(double* T, int q, int p, int b, int lane) {
-  const v4d acc = mma16(&T[16 * q * TP + 16 * b], TP, 1, &T[16 * p * TP + 16 * b], 1, TP, lane);
+// T(q, p) -= L(q, b) * L(p, b)^T for 16x16 blocks of a tile with row pitch tp
+__device__ __forceinline__ void syrk16(double* T, int tp, int q, int p, int b, int lane) {
+  const v4d acc = mma16(&T[16 * q * tp + 16 * b], tp, 1, &T[16 * p * tp + 16 * b], 1, tp, lane);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    T[(16 * q + 4 * v + (lane >> 4)) * TP + 16 * p + (lane & 15)] -= acc[v];
+    T[(16 * q + 4 * v + (lane >> 4)) * tp + 16 * p + (lane & 15)] -= acc[v];
 }
 
-// inverse of the 16x16 lower-triangular block at (o, o) of T into I; lane r
-// (< 16) forms column r by forward substitution, reading row i of L with
-// same-address LDS loads
-__device__ __forceinline__ void inv16(const double* T, double* I, int o, int lane) {
+// inverse of the 16x16 lower-triangular block at (o, o) of T (row pitch tp)
+// into the block at (o, o) of I (same pitch); lane r (< 16) forms column r by
+// forward substitution, reading row i of L with same-address LDS loads
+__device__ __forceinline__ void inv16(const double* T, double* I, int tp, int o, int lane) {
   const int r = lane & 15;
-  const double rr = 1.0 / T[(o + r) * TP + o + r];
-  const double* Lo = T + o * TP + o;
+  const double rr = 1.0 / T[(o + r) * tp + o + r];
+  const double* Lo = T + o * tp + o;
   double yv[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     double q0 = (i == r) ? 1.0 : 0.0, q1 = 0.0;
 #pragma unroll
     for (int k = 0; k + 1 < i; k += 2) {
-      q0 = fma(-Lo[i * TP + k], yv[k], q0);
-      q1 = fma(-Lo[i * TP + k + 1], yv[k + 1], q1);
+      q0 = fma(-Lo[i * tp + k], yv[k], q0);
+      q1 = fma(-Lo[i * tp + k + 1], yv[k + 1], q1);
     }
-    if (i & 1) q0 = fma(-Lo[i * TP + i - 1], yv[i - 1], q0);
+    if (i & 1) q0 = fma(-Lo[i * tp + i - 1], yv[i - 1], q0);
     yv[i] = (q0 + q1) * lane_bcast(rr, i);
   }
   if (lane < 16) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) I[(o + i) * TP + o + r] = yv[i];
+    for (int i = 0; i < 16; ++i) I[(o + i) * tp + o + r] = yv[i];
   }
 }
 
-// right-looking factorization of the 64 x 16 column block at column o of T,
-// one wavefront, lane = row; Lc (16 x 64) receives the scaled columns for
-// the broadcasts. A non-positive pivot is not patched on the way (its NaN or
+// right-looking factorization of the tr x 16 column block at column o of T
+// (row pitch tp), one wavefront, lane = row (lanes >= tr idle); Lc (16 x 64)
+// receives the scaled columns for the broadcasts. FIX (reduced-precision
+// update forms): a pivot at or below thr (this lane's column threshold, u
+// times the column's diagonal entry of A) is replaced by rep and counted in
+// *nfix. Otherwise a non-positive pivot is not patched on the way (its NaN or
 // Inf only reaches later columns of this supernode and its ancestors, whose
 // column indices are larger); afterwards each pivot lane checks its own raw
 // pivot and the smallest failing column (1-based, factored order) is
 // returned, or INT_MAX.
-//
-// FIX (reduced-precision update forms): a pivot at or below thr (this lane's
-// column threshold, u times the column's diagonal entry of A) is replaced by
-// rep, and the replacements are counted in *nfix.
 template <bool FIX>
-__device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int col0, int lane,
-                                       double thr, double rep, int* nfix) {
+__device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, int o, int nb,
+                                       int col0, int lane, double thr, double rep, int* nfix) {
+  const int lr = min(lane, tr - 1);
   double v[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = T[lane * TP + o + j];
+  for (int j = 0; j < 16; ++j) v[j] = T[lr * tp + o + j];
   double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
   double dn = lane_bcast(v[0], o);  // the next pivot, before any patching
 #pragma unroll
@@ -215,54 +213,63 @@ __device__ __forceinline__ int panel16(double* T, double* Lc, int o, int nb, int
     }
   }
   const double sq = sqrt(dg);
+  if (lane < tr) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    T[lane * TP + o + j] = lane > o + j ? v[j] : (lane == o + j ? sq : 0.0);
+    for (int j = 0; j < 16; ++j)
+      T[lane * tp + o + j] = lane > o + j ? v[j] : (lane == o + j ? sq : 0.0);
+  }
   const unsigned long long fails =
       __ballot(lane >= o && lane < o + 16 && lane < nb && !(dg > 0.0));
   return fails ? col0 + __ffsll((long long)fails) : 0x7fffffff;
 }
 
+constexpr int AP = 65;  // LDS pitch of the staged row tile: sA[k * AP + r] = A(r, k)
+
 // MODE 0: FP64 form. MODE 1: reduced-precision updates (pivot patching).
 // MODE 2: 16-bit updates (pivot patching, and the largest |entry| of the row
-// tile, overall and in the rows below the diagonal block, into the scale
+// tiles, overall and in the rows below the diagonal block, into the scale
 // slots of the column block and of the supernode).
-template <int MODE>
-__global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ tiles,
+// NBB: 16-column blocks of the widest tile of the launch (1, 2 or 4); the
+// tile and its LDS images are 16*NBB wide.
+template <int MODE, int NBB>
+__global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_panel(const PanelTile* __restrict__ tiles,
                                                double* __restrict__ L, int* __restrict__ status,
                                                int* __restrict__ counters,
                                                const double* __restrict__ thr,
                                                const unsigned long long* __restrict__ amax,
                                                double ufix, unsigned long long* __restrict__ smax,
                                                unsigned int* __restrict__ nfixed) {
+  constexpr int TR = 16 * NBB;  // tile rows and columns
+  constexpr int TPn = TR + 1;   // LDS row pitch of the tile images
   const PanelTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = t.nb, ldi = t.ld;
   const int nr = min(64, t.nrows - t.row0);  // rows of the first row tile (may be <= 0)
   double* D = L + t.diag;
-  __shared__ double T[64 * TP];   // the tile, row-major: T[i*TP + j]
-  __shared__ double I[64 * TP];   // inv(L), row-major
-  __shared__ double sA[64 * AP];  // the row tile, k-major
+  __shared__ double T[TR * TPn];  // the tile, row-major: T[i*TPn + j]
+  __shared__ double I[TR * TPn];  // inverses of its 16x16 diagonal blocks
+  __shared__ double sA[TR * AP];  // the row tile, k-major
   __shared__ double Lc[16 * 64];  // finished columns of the current 16-column block
   __shared__ int s_last;
   __shared__ unsigned long long s_max[2];
-  // stage: thread (row, cg) loads columns cg, cg+4, ..., all 32 loads in flight;
+  // stage: thread (row, cg) loads columns cg, cg+4, ..., all loads in flight;
   // addresses are clamped so every load is in bounds
   {
     const int row = lane, cg = wave;
     const int dr = min(row, nb - 1);
     const int arow = min(t.row0 + max(0, min(row, nr - 1)), t.nrows - 1);
-    double dv[16], av[16];
+    double dv[4 * NBB], av[4 * NBB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 4 * NBB; ++i) {
       const int j = min(cg + 4 * i, nb - 1);
       dv[i] = D[(int64_t)j * ldi + dr];
       av[i] = D[(int64_t)j * ldi + arow];
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 4 * NBB; ++i) {
       const int j = cg + 4 * i;
-      T[row * TP + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+      if (row < TR)
+        T[row * TPn + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
       sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
     }
   }
@@ -286,35 +293,36 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
   }
   for (int r = 0; r < nbb; ++r) {
     if (wave == 0) {
-      bad = min(bad, panel16<(MODE >= 1)>(T, Lc, 16 * r, nb, t.col, lane, cthr, crep, &nfix));
+      bad = min(bad, panel16<(MODE >= 1)>(T, TPn, TR, Lc, 16 * r, nb, t.col, lane, cthr, crep,
+                                          &nfix));
     } else if (r >= 1) {
       if (wave == 3) {
-        inv16(T, I, 16 * (r - 1), lane);
+        inv16(T, I, TPn, 16 * (r - 1), lane);
       } else {
         // block r-1's updates of column blocks p >= r+1
         int idx = 0;
         for (int p = r + 1; p < nbb; ++p)
           for (int q = p; q < nbb; ++q, ++idx)
-            if ((idx & 1) == wave - 1) syrk16(T, q, p, r - 1, lane);
+            if ((idx & 1) == wave - 1) syrk16(T, TPn, q, p, r - 1, lane);
       }
     }
     __syncthreads();
     // column block r+1 from block r
-    if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, r + 1 + wave, r + 1, r, lane);
+    if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, TPn, r + 1 + wave, r + 1, r, lane);
     __syncthreads();
   }
   // the last base inverse (wave 3) alongside the first column blocks of the
   // row tiles' solves
-  if (wave == 3) inv16(T, I, 16 * (nbb - 1), lane);
+  if (wave == 3) inv16(T, I, TPn, 16 * (nbb - 1), lane);
   // the last reader writes the factored tile (lower triangle)
   if (s_last) {
     if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
     if (MODE >= 1 && wave == 0 && lane == 0 && nfix) atomicAdd(nfixed + t.slot, (unsigned)nfix);
     const int i = lane;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 4 * NBB; ++q) {
       const int j = wave + 4 * q;
-      if (i < nb && j < nb && i >= j) D[(int64_t)j * ldi + i] = T[i * TP + j];
+      if (i < nb && j < nb && i >= j) D[(int64_t)j * ldi + i] = T[i * TPn + j];
     }
   }
   // X = A * L^-T for each of this member's row tiles (the first was staged
@@ -332,19 +340,19 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
       __syncthreads();  // the previous tile's reads of sA are done
       const int row = lane, cg = wave;
       const int arow = row0 + min(row, nrt_rows - 1);
-      double av[16];
+      double av[4 * NBB];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) av[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + arow];
+      for (int i = 0; i < 4 * NBB; ++i) av[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + arow];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < 4 * NBB; ++i) {
         const int j = cg + 4 * i;
         sA[j * AP + row] = (row < nrt_rows && j < nb) ? av[i] : 0.0;
       }
       __syncthreads();
     }
-    v4d X[4];
+    v4d X[NBB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NBB; ++b) {
       if (b == nbb - 1 && rt == 0) __syncthreads();  // inv(L_bb) of the last block is ready
       X[b] = v4d{0, 0, 0, 0};
       if (b < nbb) {
@@ -356,11 +364,12 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
         for (int c = 0; c < b; ++c)
 #pragma unroll
           for (int kq = 0; kq < 4; ++kq)
-            r = mfma64(-T[(16 * b + (lane & 15)) * TP + 16 * c + 4 * kq + (lane >> 4)], X[c][kq], r);
+            r = mfma64(-T[(16 * b + (lane & 15)) * TPn + 16 * c + 4 * kq + (lane >> 4)], X[c][kq],
+                       r);
         v4d x = {0, 0, 0, 0};
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq)
-          x = mfma64(I[(16 * b + (lane & 15)) * TP + 16 * b + 4 * kq + (lane >> 4)], r[kq], x);
+          x = mfma64(I[(16 * b + (lane & 15)) * TPn + 16 * b + 4 * kq + (lane >> 4)], r[kq], x);
         X[b] = x;
         const int rr = 16 * rb + (lane & 15);
 #pragma unroll
@@ -378,7 +387,6 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
       }
     }
   }
-  if (t.nrt == 0) __syncthreads();  // keep the barrier count uniform
   if (MODE == 2 && t.nrt > 0) {
     atomicMax(&s_max[0], (unsigned long long)__double_as_longlong(mx_step));
     atomicMax(&s_max[1], (unsigned long long)__double_as_longlong(mx_anc));
@@ -396,64 +404,73 @@ __global__ __launch_bounds__(256) void k_panel(const PanelTile* __restrict__ til
 // One workgroup per tile: the 16x16 diagonal blocks are inverted by
 // substitution (one wavefront each), then the 2 x 2 block formula
 // [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1] joins them in two levels.
+// NBB as in k_panel.
+template <int NBB>
 __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict__ tiles,
                                                       double* __restrict__ L) {
+  constexpr int TR = 16 * NBB, TPn = TR + 1;
   const DiagTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = t.nb, ldi = t.ld;
   double* D = L + t.diag;
-  __shared__ double T[64 * TP];
-  __shared__ double I[64 * TP];
+  __shared__ double T[TR * TPn];
+  __shared__ double I[TR * TPn];
   {
     const int row = lane, cg = wave;
     const int dr = min(row, nb - 1);
-    double dv[16];
+    double dv[4 * NBB];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dv[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + dr];
+    for (int i = 0; i < 4 * NBB; ++i) dv[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + dr];
+    if (row < TR) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int j = cg + 4 * i;
-      T[row * TP + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+      for (int i = 0; i < 4 * NBB; ++i) {
+        const int j = cg + 4 * i;
+        T[row * TPn + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+      }
     }
   }
   __syncthreads();
   const int nbb = (nb + 15) >> 4;
-  if (wave < nbb) inv16(T, I, 16 * wave, lane);
+  if (wave < nbb) inv16(T, I, TPn, 16 * wave, lane);
   __syncthreads();
-  // level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
-  {
+  if (NBB >= 2) {
+    // level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
     const int i1 = wave == 0 ? 1 : 3;
     if ((wave == 0 && nbb >= 2) || (wave == 1 && nbb >= 4)) {
-      const v4d s = mma16(&T[16 * i1 * TP + 16 * (i1 - 1)], TP, 1,
-                          &I[16 * (i1 - 1) * TP + 16 * (i1 - 1)], TP, 1, lane);
-      const v4d u = mma16r(&I[16 * i1 * TP + 16 * i1], TP, 1, s, lane);
-      st16(&I[16 * i1 * TP + 16 * (i1 - 1)], u, lane, -1.0);
+      const v4d s = mma16(&T[16 * i1 * TPn + 16 * (i1 - 1)], TPn, 1,
+                          &I[16 * (i1 - 1) * TPn + 16 * (i1 - 1)], TPn, 1, lane);
+      const v4d u = mma16r(&I[16 * i1 * TPn + 16 * i1], TPn, 1, s, lane);
+      st16(&I[16 * i1 * TPn + 16 * (i1 - 1)], TPn, u, lane, -1.0);
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // level 2 (nbb >= 3): for i in [2, nbb), j in {0, 1}: S(i,j) = L(i,0)
-  // inv(0,j) + L(i,1) inv(1,j), kept in T's unused block (j, i), then
-  // inv(i,j) = -sum_{2 <= l <= i} inv(i,l) S(l,j)
-  const int i2 = 2 + (wave >> 1), j2 = wave & 1;
-  const bool p2 = nbb >= 3 && i2 < nbb;
-  if (p2) {
-    v4d s = mma16(&T[16 * i2 * TP + 16], TP, 1, &I[16 * TP + 16 * j2], TP, 1, lane);
-    if (j2 == 0) s += mma16(&T[16 * i2 * TP], TP, 1, &I[0], TP, 1, lane);
-    st16(&T[16 * j2 * TP + 16 * i2], s, lane, 1.0);
+  if (NBB >= 4) {
+    // level 2 (nbb >= 3): for i in [2, nbb), j in {0, 1}: S(i,j) = L(i,0)
+    // inv(0,j) + L(i,1) inv(1,j), kept in T's unused block (j, i), then
+    // inv(i,j) = -sum_{2 <= l <= i} inv(i,l) S(l,j)
+    const int i2 = 2 + (wave >> 1), j2 = wave & 1;
+    const bool p2 = nbb >= 3 && i2 < nbb;
+    if (p2) {
+      v4d s = mma16(&T[16 * i2 * TPn + 16], TPn, 1, &I[16 * TPn + 16 * j2], TPn, 1, lane);
+      if (j2 == 0) s += mma16(&T[16 * i2 * TPn], TPn, 1, &I[0], TPn, 1, lane);
+      st16(&T[16 * j2 * TPn + 16 * i2], TPn, s, lane, 1.0);
+    }
+    __syncthreads();
+    if (p2) {
+      v4d u = {0, 0, 0, 0};
+      for (int l = 2; l <= i2; ++l)
+        u += mma16(&I[16 * i2 * TPn + 16 * l], TPn, 1, &T[16 * j2 * TPn + 16 * l], TPn, 1, lane);
+      st16(&I[16 * i2 * TPn + 16 * j2], TPn, u, lane, -1.0);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (p2) {
-    v4d u = {0, 0, 0, 0};
-    for (int l = 2; l <= i2; ++l)
-      u += mma16(&I[16 * i2 * TP + 16 * l], TP, 1, &T[16 * j2 * TP + 16 * l], TP, 1, lane);
-    st16(&I[16 * i2 * TP + 16 * j2], u, lane, -1.0);
-  }
-  __syncthreads();
   const int i = lane;
+  if (i < TR) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int j = wave + 4 * q;
-    if (i < j && j < nb) D[(int64_t)j * ldi + i] = I[j * TP + i];
+    for (int q = 0; q < 4 * NBB; ++q) {
+      const int j = wave + 4 * q;
+      if (i < j && j < nb) D[(int64_t)j * ldi + i] = I[j * TPn + i];
+    }
   }
 }
 
@@ -1286,23 +1303,46 @@ void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int
   hipLaunchKernelGGL(k_scatter_batch, dim3(grid_for(total, 256, INT32_MAX)), dim3(256), 0, st,
                      vals, nnz_ptr, count, total, amap, L);
 }
-void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  int precision, const double* thr, const unsigned long long* amax, double ufix,
-                  unsigned long long* smax, unsigned int* nfixed, hipStream_t st) {
-  if (count <= 0) return;
-  if (precision == 0)
-    hipLaunchKernelGGL(k_panel<0>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
-                       counters, thr, amax, ufix, smax, nfixed);
-  else if (precision == 1)
-    hipLaunchKernelGGL(k_panel<1>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
-                       counters, thr, amax, ufix, smax, nfixed);
+template <int NBB>
+static void launch_panel_n(const PanelTile* tiles, int64_t count, double* L, int* status,
+                           int* counters, int mode, const double* thr,
+                           const unsigned long long* amax, double ufix, unsigned long long* smax,
+                           unsigned int* nfixed, hipStream_t st) {
+  const dim3 g((unsigned)count), b(256);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_panel<0, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
+                       smax, nfixed);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_panel<1, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
+                       smax, nfixed);
   else
-    hipLaunchKernelGGL(k_panel<2>, dim3((unsigned)count), dim3(256), 0, st, tiles, L, status,
-                       counters, thr, amax, ufix, smax, nfixed);
+    hipLaunchKernelGGL((k_panel<2, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
+                       smax, nfixed);
 }
-void launch_tile_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st) {
+void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
+                  int precision, int nbb, const double* thr, const unsigned long long* amax,
+                  double ufix, unsigned long long* smax, unsigned int* nfixed, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_tile_inverse, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
+  if (nbb <= 1)
+    launch_panel_n<1>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
+                      st);
+  else if (nbb == 2)
+    launch_panel_n<2>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
+                      st);
+  else
+    launch_panel_n<4>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
+                      st);
+}
+void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
+                         hipStream_t st) {
+  if (count <= 0) return;
+  const dim3 g((unsigned)count), b(256);
+  if (nbb <= 1)
+    hipLaunchKernelGGL(k_tile_inverse<1>, g, b, 0, st, tiles, L);
+  else if (nbb == 2)
+    hipLaunchKernelGGL(k_tile_inverse<2>, g, b, 0, st, tiles, L);
+  else
+    hipLaunchKernelGGL(k_tile_inverse<4>, g, b, 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, bool shortk, hipStream_t st) {

@@ -33,6 +33,12 @@ constexpr int TN = 64;   // update tile columns
 constexpr int FLAG_DIAG = 1;
 constexpr int FLAG_ATOMIC = 2;
 constexpr int KCH = 16;        // K chunk of the update kernel
+// panel launch cost model by width class (1, 2, 4 blocks of 16 columns):
+// microseconds per workgroup, resident workgroups on the device, and the
+// fixed cost of a launch (measured orders of magnitude on MI355X)
+constexpr double PANEL_US[3] = {6.0, 10.0, 16.0};
+constexpr int64_t PANEL_SLOTS[3] = {3 * 256, 2 * 256, 256};
+constexpr double LAUNCH_US = 4.0;
 constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a tile is split
 
 // One rectangle of the ancestor update: target rows [r0, r0+mr) and columns
@@ -201,8 +207,6 @@ int build_plan(Symbolic& s, std::string& err) {
       // none); in launches with more than panel_spread row tiles a
       // workgroup takes several consecutive row tiles, so that the redundant
       // factorization of the diagonal tile is not repeated needlessly
-      Launch lp{LAUNCH_PANEL, h, (int32_t)k, 0, (int64_t)p.panels.size(), 0};
-      int32_t ngroups = 0;
       int64_t ntiles = 0;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
@@ -212,6 +216,9 @@ int build_plan(Symbolic& s, std::string& err) {
       }
       const int64_t spread = std::max(1, s.opt.panel_spread);
       const int64_t per = std::max<int64_t>(1, (ntiles + spread - 1) / spread);
+      // one launch per width class of the diagonal tiles (1, 2 or 4 blocks of 16)
+      std::vector<PanelTile> cls[3];
+      int32_t ngroups[3] = {0, 0, 0};
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         if (k * NB >= w) continue;
@@ -221,6 +228,7 @@ int build_plan(Symbolic& s, std::string& err) {
         // counts nb..1) plus TRSM of the rows below (nb^2 per row)
         for (int64_t t = 0; t < nb; ++t) p.flops_panel += (double)(nb - t) * (double)(nb - t);
         p.flops_panel += (double)below * (double)nb * (double)nb;
+        const int ci = nb <= 16 ? 0 : (nb <= 32 ? 1 : 2);
         int64_t nt = (below + 63) / 64;  // row tiles
         int64_t nwg = std::max<int64_t>(1, (nt + per - 1) / per);
         PanelTile pt;
@@ -230,7 +238,7 @@ int build_plan(Symbolic& s, std::string& err) {
         pt.nrows = (int32_t)nrows;
         pt.col = (int32_t)(s.sn_ptr[J] + c0);
         pt.slot = 0;
-        pt.grp = ngroups++;
+        pt.grp = ngroups[ci]++;
         pt.gcnt = (int32_t)nwg;
         pt.s_step = sbase[J] + (int32_t)k;
         pt.s_anc = anc_slot(J);
@@ -238,12 +246,38 @@ int build_plan(Symbolic& s, std::string& err) {
         for (int64_t g = 0; g < nwg; ++g) {
           pt.row0 = (int32_t)(nb + 64 * per * g);
           pt.nrt = (int32_t)std::min<int64_t>(per, std::max<int64_t>(0, nt - per * g));
-          p.panels.push_back(pt);
+          cls[ci].push_back(pt);
         }
       }
-      lp.count = (int64_t)p.panels.size() - lp.start;
-      if (lp.count) p.launches.push_back(lp);
-      p.max_groups = std::max(p.max_groups, ngroups);
+      // a narrow class gets a launch of its own unless running its tiles in
+      // the next wider class's launch is estimated cheaper: workgroup rounds
+      // (workgroups over resident slots) times a per-workgroup time, plus a
+      // fixed cost per launch
+      auto rounds = [](int64_t wgs, int64_t slots) { return (wgs + slots - 1) / slots; };
+      for (int ci = 0; ci < 2; ++ci)
+        if (!cls[ci].empty()) {
+          const int64_t nn = (int64_t)cls[ci].size(), nw = (int64_t)cls[ci + 1].size();
+          const double tw = PANEL_US[ci + 1], tn = PANEL_US[ci];
+          const int64_t sw = PANEL_SLOTS[ci + 1], sn = PANEL_SLOTS[ci];
+          const double sep = (nw ? rounds(nw, sw) * tw + LAUNCH_US : 0.0) + rounds(nn, sn) * tn +
+                             LAUNCH_US;
+          const double fold = rounds(nn + nw, sw) * tw + LAUNCH_US;
+          if (fold > sep) continue;
+          for (PanelTile& t : cls[ci]) t.grp += ngroups[ci + 1];
+          cls[ci + 1].insert(cls[ci + 1].end(), cls[ci].begin(), cls[ci].end());
+          ngroups[ci + 1] += ngroups[ci];
+          ngroups[ci] = 0;
+          cls[ci].clear();
+        }
+      const int32_t cls_nbb[3] = {1, 2, 4};
+      for (int ci = 0; ci < 3; ++ci) {
+        if (cls[ci].empty()) continue;
+        Launch lp{LAUNCH_PANEL, h, (int32_t)k, cls_nbb[ci], (int64_t)p.panels.size(),
+                  (int64_t)cls[ci].size()};
+        p.panels.insert(p.panels.end(), cls[ci].begin(), cls[ci].end());
+        p.launches.push_back(lp);
+        p.max_groups = std::max(p.max_groups, ngroups[ci]);
+      }
       // UPDATE: trailing updates of step k, ancestor updates of finished
       // supernodes; one target tile per workgroup with all its contributions
       Launch lu{LAUNCH_UPDATE, h, (int32_t)k, 0, (int64_t)p.updates.size(), 0};
@@ -390,22 +424,29 @@ int build_plan(Symbolic& s, std::string& err) {
         std::copy(sorted.begin(), sorted.end(), p.updates.begin() + lu.start);
       }
       lu.count = (int64_t)p.updates.size() - lu.start;
-      lu.shortk = 1;
+      lu.variant = 1;
       for (int64_t i = lu.start; i < lu.start + lu.count; ++i) {
         const UpdTile& t = p.updates[i];
         if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || p.segs[t.seg0].k > 64) {
-          lu.shortk = 0;
+          lu.variant = 0;
           break;
         }
       }
       if (lu.count) p.launches.push_back(lu);
     }
   }
-  // diagonal tiles of every 64-column step, inverted after the factorization
-  for (int64_t J = 0; J < S; ++J)
-    for (int64_t c0 = 0; c0 < W(J); c0 += NB)
-      p.dtiles.push_back(DiagTile{p.off[J] + c0 * M(J) + c0, (int32_t)M(J),
-                                  (int32_t)std::min<int64_t>(NB, W(J) - c0)});
+  // diagonal tiles of every 64-column step, inverted after the factorization,
+  // grouped by width class
+  for (int ci = 0; ci < 3; ++ci) {
+    p.dt_ptr[ci] = (int64_t)p.dtiles.size();
+    for (int64_t J = 0; J < S; ++J)
+      for (int64_t c0 = 0; c0 < W(J); c0 += NB) {
+        int64_t nb = std::min<int64_t>(NB, W(J) - c0);
+        if ((nb <= 16 ? 0 : (nb <= 32 ? 1 : 2)) != ci) continue;
+        p.dtiles.push_back(DiagTile{p.off[J] + c0 * M(J) + c0, (int32_t)M(J), (int32_t)nb});
+      }
+  }
+  p.dt_ptr[3] = (int64_t)p.dtiles.size();
   // solves: forward by level and 64-column step (row tiles of 256 below the
   // chunk), backward by level from the root: first every column chunk against
   // the ancestor rows (segments of 512 rows), then the steps from the last

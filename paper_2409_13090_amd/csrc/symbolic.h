@@ -114,7 +114,8 @@ struct Launch {
   int32_t kind;   // LAUNCH_*
   int32_t level;
   int32_t step;   // column block index inside the level
-  int32_t shortk; // update launch whose tiles all have one contribution, k <= 64, one owner
+  int32_t variant; // update: 1 when every tile has one contribution, k <= 64, one owner;
+                   // panel: 16-column blocks of its widest tile (1, 2 or 4)
   int64_t start;  // first tile
   int64_t count;  // number of tiles
 };
@@ -129,7 +130,8 @@ struct Plan {
   std::vector<UpdSeg> segs;
   int32_t n_scale_slots = 0;     // per column block of every supernode, plus one per supernode
   std::vector<int64_t> diag_src; // input entry of the diagonal of every factored column
-  std::vector<DiagTile> dtiles;       // every 64-column step's diagonal tile
+  std::vector<DiagTile> dtiles;       // every 64-column step's diagonal tile, by width class
+  int64_t dt_ptr[4] = {0, 0, 0, 0};   // classes of 1, 2 and 4 16-column blocks
   std::vector<SolveTile> stiles;      // solve work items, launch by launch
   std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
   std::vector<Launch> launches;

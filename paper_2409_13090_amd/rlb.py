@@ -70,6 +70,7 @@ EXPORTED = [
     "rlb_batch_create", "rlb_batch_factor", "rlb_batch_status", "rlb_batch_solve",
     "rlb_batch_free", "rlb_set_graph_mode", "rlb_batch_set_graph_mode", "rlb_set_profiling",
     "rlb_last_profile", "rlb_status_string", "rlb_last_error", "rlb_factor_pivots_patched",
+    "rlb_batch_set_schedule", "rlb_batch_autotune",
 ]
 
 _lib = None
@@ -108,6 +109,8 @@ def lib():
         "rlb_set_profiling": [_vp, i32],
         "rlb_last_profile": [_vp, _vp, _vp, _vp, _vp],
         "rlb_factor_pivots_patched": [_vp, ctypes.POINTER(i64)],
+        "rlb_batch_set_schedule": [_vp, i32],
+        "rlb_batch_autotune": [_vp, _vp, _vp, ctypes.c_size_t, _vp, i32, ctypes.POINTER(i32), _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -344,6 +347,30 @@ class Batch:
         if check:
             return self.status()
         return None
+
+    SCHEDULES = ("leaves", "roots", "centered")
+
+    def set_schedule(self, name):
+        _check(lib().rlb_batch_set_schedule(self.h, self.SCHEDULES.index(name)))
+
+    def autotune(self, values_list, workspace=None, stream=None, reps=2):
+        """Time the level schedules on the device and keep the fastest;
+        returns (chosen name, {name: ms})."""
+        import torch
+        if workspace is None:
+            if self.workspace is None:
+                self.workspace = torch.empty(max(1, self.ws_bytes // 8), dtype=torch.float64,
+                                             device=values_list[0].device)
+            workspace = self.workspace
+        self.workspace = workspace
+        self._vals = list(values_list)
+        arr = (_vp * len(self._vals))(*[_ptr(v) for v in self._vals])
+        chosen = ctypes.c_int32()
+        ms = np.zeros(3)
+        _check(lib().rlb_batch_autotune(self.h, ctypes.cast(arr, _vp), _ptr(workspace),
+                                        workspace.numel() * 8, _stream(stream), int(reps),
+                                        ctypes.byref(chosen), ms.ctypes.data))
+        return self.SCHEDULES[chosen.value], dict(zip(self.SCHEDULES, ms.tolist()))
 
     def status(self):
         out = np.zeros(len(self.syms), np.int64)

@@ -175,6 +175,35 @@ def test_batched_matches_unbatched_and_oracle():
             compare_factor(num.export(), f, A.n)
 
 
+def test_batch_schedules_agree_and_autotune_picks_one():
+    torch = _torch()
+    mats = [W.batch_member(i) for i in range(10)]
+    syms = [rlb.Symbolic.from_matrix(A) for A in mats]
+    b = rlb.Batch(syms)
+    vals = [torch.from_numpy(A.values).cuda() for A in mats]
+    outs = {}
+    for name in rlb.Batch.SCHEDULES:
+        b.set_schedule(name)
+        assert np.all(b.factor(vals) == 0)
+        xs = []
+        for i, A in enumerate(mats):
+            B = torch.from_numpy(A.rhs[:, 0].copy()).cuda()
+            X = B.clone()
+            b.solve(i, X)
+            num = rlb.Numeric(syms[i])
+            num.values = vals[i]
+            assert num.backward_error(B, X)[0] <= 1e-14, (name, i)
+            xs.append(X.cpu().numpy())
+        outs[name] = xs
+    # the same factors up to the order of floating-point additions
+    for name in rlb.Batch.SCHEDULES[1:]:
+        for a, c in zip(outs["leaves"], outs[name]):
+            assert np.linalg.norm(a - c) <= 1e-9 * np.linalg.norm(a), name
+    chosen, ms = b.autotune(vals, reps=1)
+    assert chosen in rlb.Batch.SCHEDULES and all(v > 0 for v in ms.values())
+    assert np.all(b.status() == 0)
+
+
 def test_fp32_updates_with_refinement_reach_1e14():
     torch = _torch()
     A = W.small_grid("27pt", (14, 14, 14), seed=30, lo=0.1, hi=1.0, shift=1e-4, nrhs=4)

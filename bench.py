@@ -107,6 +107,8 @@ def main():
                     help="only copy 256 MiB device to device (calibrates the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=100,
+                    help="refinement steps allowed to the reduced-precision form")
     ap.add_argument("--mixed", choices=["fp32", "bf16", "fp16"], default=None,
                     help="update operands of the refined form (default: fp32, bf16 for elast3_40)")
     ap.add_argument("--no-graph", action="store_true",
@@ -261,7 +263,7 @@ def main():
             if info32 != 0:
                 break
             X32 = torch.zeros_like(B).T.contiguous().T
-            r = num32.refine(B, X32, tol=1e-14, max_iter=50)
+            r = num32.refine(B, X32, tol=1e-14, max_iter=args.max_iter)
             torch.cuda.synchronize()
             tts.append(time.perf_counter() - t0)
             ms32.append(e0.elapsed_time(e1))

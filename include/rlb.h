@@ -189,7 +189,8 @@ typedef struct rlb_refine_report {
  * correction fails to halve (max over columns of ||d||_2) at two steps, the
  * iteration continues as conjugate gradients in FP64 preconditioned by the
  * computed factor (M = L L^T), per column, from the current iterate (residual
- * by recurrence; the stopping test always uses the true residual B - A X).
+ * by recurrence; the stopping test always uses the true residual B - A X, and
+ * CG restarts from it when the backward error has not halved in 8 steps).
  *   values : (device) the same FP64 values that were factored (for A X)
  *   B, X   : (device) n x nrhs column-major, ORIGINAL order, ld = ld; nrhs <= 16
  * Returns RLB_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not met. */

@@ -697,7 +697,8 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
     launch_perm_out(h->d.perm, sc.x, n, sc.d, n, n, nr, st);
   };
   double be[SOLVE_MAXRHS], rz[SOLVE_MAXRHS] = {0}, dd[SOLVE_MAXRHS], prev_dn = -1.0;
-  int strikes = 0, it = 0;
+  int strikes = 0, it = 0, since_best = 0;
+  double best_pcg = INFINITY;
   bool pcg = false;
   ColCoef one, zero;
   for (int k = 0; k < SOLVE_MAXRHS; ++k) {
@@ -713,6 +714,14 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
     if (worst <= tol || it >= max_iter) {
       r.converged = worst <= tol;
       break;
+    }
+    if (pcg) {
+      if (worst <= 0.5 * best_pcg) {
+        best_pcg = worst;
+        since_best = 0;
+      } else {
+        ++since_best;
+      }
     }
     if (!pcg) {
       solve_r(sc.r);  // sc.d = M^-1 (B - A X)
@@ -733,6 +742,15 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
       pcg = true;
       r.pcg_from = it;
       launch_axpby_cols(sc.rr, n, sc.r, n, n, nr, one, zero, st);
+      if ((e = dots(sc.rr, sc.d, rz))) return e;
+      launch_axpby_cols(sc.p, n, sc.d, n, n, nr, one, zero, st);
+    } else if (since_best >= 8) {
+      // restart from the true residual when the backward error has not halved
+      // in 8 steps (the recurrence residual drifts from B - A X)
+      since_best = 0;
+      best_pcg = worst;
+      launch_axpby_cols(sc.rr, n, sc.r, n, n, nr, one, zero, st);
+      solve_r(sc.rr);
       if ((e = dots(sc.rr, sc.d, rz))) return e;
       launch_axpby_cols(sc.p, n, sc.d, n, n, nr, one, zero, st);
     } else {

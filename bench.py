@@ -45,7 +45,7 @@ PEAK_16BIT_TFLOPS = 2516.6  # dense BF16/FP16 MFMA
 # only for the kernel source they were taken on (first 16 hex digits of the
 # SHA-256 of kernels.hip), otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "lap3d7_48": {"kernels_sha256": "43afa5523fc50ef5", "bytes_per_launch": 59769509,
+    "lap3d7_48": {"kernels_sha256": "446ef79ea7a8d088", "bytes_per_launch": 76525799,
                   "summary": "profiles/k_update_lap3d7_48_hbm_traffic.md"},
 }
 
@@ -202,7 +202,8 @@ def main():
     # dominant kernel: the SYRK/GEMM update tiles (FP64 MFMA)
     upd_s = statistics.mean(upd_ms) / 1e3
     ach = info["flops_upd_alg"] / upd_s / 1e12
-    roof = {"kernel": "k_update<double> (SYRK/GEMM into target, MFMA f64 16x16x4)",
+    roof = {"kernel": "update launches: k_update<double> / k_update_short<double> (SYRK/GEMM "
+                      "summed into 64x64 target tiles, MFMA f64 16x16x4)",
             "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(args.workload, args.side),

@@ -457,10 +457,10 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
                        t.nrt};
       tmp.insert(tmp.end(), v, v + 11);
     }
-  } else if (w == "launches") {  // kind, level, step, start, count per launch
+  } else if (w == "launches") {  // kind, level, step, start, count, variant, pre, ustart, ucount
     for (const Launch& l : s.plan.launches) {
-      int64_t v[5] = {l.kind, l.level, l.step, l.start, l.count};
-      tmp.insert(tmp.end(), v, v + 5);
+      int64_t v[9] = {l.kind, l.level, l.step, l.start, l.count, l.variant, l.pre, l.ustart, l.ucount};
+      tmp.insert(tmp.end(), v, v + 9);
     }
   }
   else return fail(RLB_ERR_ARG, "unknown array " + w);
@@ -531,12 +531,18 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   size_t ei = 0;
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
-    if (l.kind == LAUNCH_UPDATE)
+    if (l.kind == LAUNCH_UPDATE) {
       launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
                     l.variant != 0, st);
-    else
+    } else {
       launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, l.variant,
-                   h->thr, h->amax, u, h->smax, nfixed, st);
+                   l.pre != 0, h->thr, h->amax, u, h->smax, nfixed, h->d.updates + l.ustart,
+                   h->d.segs, l.ucount, st);
+      // the 16-bit forms run the fused update tiles as a launch of their own
+      if (pmode == 2 && l.ucount)
+        launch_update(h->d.updates + l.ustart, h->d.segs, l.ucount, L, h->precision, h->smax,
+                      false, st);
+    }
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
   const int cls_nbb[3] = {1, 2, 4};
@@ -861,31 +867,35 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
   for (;;) {
     // the smallest (level, step, kind) among the matrices' next launches
     bool any = false;
-    int32_t bl = 0, bs = 0, bk = 0, bv = 0;
+    int32_t bl = 0, bs = 0, bk = 0, bv = 0, bp = 0;
     for (int32_t i = 0; i < count; ++i) {
       const auto& L = syms[i]->s.plan.launches;
       if (cur[i] >= L.size()) continue;
       const Launch& l = L[cur[i]];
       const int32_t lv = l.level + shift[i];
       const int32_t vv = l.kind == LAUNCH_PANEL ? l.variant : 0;
-      if (!any || std::make_tuple(lv, l.step, l.kind, vv) < std::make_tuple(bl, bs, bk, bv)) {
+      const int32_t pp = l.kind == LAUNCH_PANEL ? l.pre : 0;
+      if (!any ||
+          std::make_tuple(lv, l.step, l.kind, vv, pp) < std::make_tuple(bl, bs, bk, bv, bp)) {
         bl = lv;
         bs = l.step;
         bk = l.kind;
         bv = vv;
+        bp = pp;
         any = true;
       }
     }
     if (!any) break;
-    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0};
+    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0, bp, 0, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
+    m.ustart = (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
       const Plan& p = syms[i]->s.plan;
       if (cur[i] >= p.launches.size()) continue;
       const Launch& l = p.launches[cur[i]];
       if (l.level + shift[i] != bl || l.step != bs || l.kind != bk) continue;
-      if (bk == LAUNCH_PANEL && l.variant != bv) continue;
+      if (bk == LAUNCH_PANEL && (l.variant != bv || l.pre != bp)) continue;
       if (bk == LAUNCH_UPDATE) m.variant &= l.variant;
       if (bk != LAUNCH_UPDATE) {
         int32_t g_hi = 0;
@@ -898,6 +908,14 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
           b->panels.push_back(pt);
         }
         gbase += g_hi;
+        // the fused update tiles of the previous step ride along
+        for (int64_t t = 0; t < l.ucount; ++t) {
+          UpdTile ut = p.updates[l.ustart + t];
+          ut.c += b->base[i];
+          ut.seg0 += (int32_t)segbase[i];
+          b->updates.push_back(ut);
+        }
+        m.ucount += l.ucount;
       } else {
         for (int64_t t = 0; t < l.count; ++t) {
           UpdTile ut = p.updates[l.start + t];
@@ -1007,9 +1025,18 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
                     l.variant != 0, st);
-    else
+    else {
+      // the batch factors with the FP64 panel kernel; its fused update tiles
+      // run inside it in the FP64 form and as a short launch of their own in
+      // the FP32 form
+      const bool inside = b->precision == RLB_PREC_FP64;
       launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, l.variant,
-                   nullptr, nullptr, 0.0, nullptr, nullptr, st);
+                   l.pre != 0, nullptr, nullptr, 0.0, nullptr, nullptr,
+                   b->d_updates + l.ustart, b->d_segs, inside ? l.ucount : 0, st);
+      if (!inside && l.ucount)
+        launch_update(b->d_updates + l.ustart, b->d_segs, l.ucount, L, b->precision, nullptr,
+                      true, st);
+    }
   }
   const int cls_nbb[3] = {1, 2, 4};
   for (int ci = 0; ci < 3; ++ci)

@@ -21,9 +21,16 @@ void launch_scatter_a(const double* vals, const int64_t* amap, int64_t nnz, doub
                       hipStream_t st);
 void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int32_t count,
                           int64_t total, const int64_t* amap, double* L, hipStream_t st);
+// cdiv of the tiles of one panel launch; pre: apply the previous block's
+// trailing update of each column block first; the ucount tiles of utiles (the
+// rest of that trailing update, short single-contribution tiles) run as extra
+// workgroups of the same launch in the FP64 and FP32 forms (precision 0, 1);
+// with precision 2 the caller launches them separately
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  int precision, int nbb, const double* thr, const unsigned long long* amax,
-                  double ufix, unsigned long long* smax, unsigned int* nfixed, hipStream_t st);
+                  int precision, int nbb, bool pre, const double* thr,
+                  const unsigned long long* amax, double ufix, unsigned long long* smax,
+                  unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
+                  int64_t ucount, hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, bool shortk, hipStream_t st);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,

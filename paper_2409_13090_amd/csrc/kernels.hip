@@ -144,9 +144,10 @@ __device__ __forceinline__ void syrk16(double* T, int tp, int q, int p, int b, i
 }
 
 // inverse of the 16x16 lower-triangular block at (o, o) of T (row pitch tp)
-// into the block at (o, o) of I (same pitch); lane r (< 16) forms column r by
+// into the 16x16 block Io (row pitch ip); lane r (< 16) forms column r by
 // forward substitution, reading row i of L with same-address LDS loads
-__device__ __forceinline__ void inv16(const double* T, double* I, int tp, int o, int lane) {
+__device__ __forceinline__ void inv16(const double* T, int tp, int o, double* Io, int ip,
+                                      int lane) {
   const int r = lane & 15;
   const double rr = 1.0 / T[(o + r) * tp + o + r];
   const double* Lo = T + o * tp + o;
@@ -164,8 +165,118 @@ __device__ __forceinline__ void inv16(const double* T, double* I, int tp, int o,
   }
   if (lane < 16) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) I[(o + i) * tp + o + r] = yv[i];
+    for (int i = 0; i < 16; ++i) Io[i * ip + r] = yv[i];
   }
+}
+
+// MFMA 16x16x4 operand layout (lane l): A[l%16][l/16] and B[l/16][l%16]. The
+// accumulator layout differs by type: for FP64 element v of lane l is
+// D[4*v + l/16][l%16]; for FP32 it is D[4*(l/16) + v][l%16]. The kernel computes
+// D = Y * X^T, so D's column index is the target row: for fixed v, 16 lanes
+// cover 16 consecutive rows of one target column, which keeps the
+// read-modify-write of column-major storage coalesced.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int KC = 16;  // K chunk staged per LDS buffer
+
+
+// One target tile of a launch whose tiles all hold a single contribution
+// with k <= 64 and a single owner (the trailing updates of a step): every
+// load of K is issued up front, so the tile waits for memory once. sX and sY
+// are LDS stages of 2 x KC x 64 elements each.
+template <typename T>
+__device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g,
+                                               double* __restrict__ L, T (*sX)[KC][64],
+                                               T (*sY)[KC][64]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int lr = tid & 63, lk = tid >> 6;
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
+  const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+  const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
+  double xr[16], yr[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t kk = min(lk + 4 * q, g.k - 1);
+    xr[q] = L[xo + kk * g.lds];
+    yr[q] = L[yo + kk * g.lds];
+  }
+  double cv[2][2][4];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+        const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
+        cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+      }
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  const int nch = (g.k + KC - 1) / KC;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c < nch) {
+      const int buf = c & 1;
+#pragma unroll
+      for (int u = 0; u < KC / 4; ++u) {
+        const int q = 4 * c + u;
+        const bool kin = lk + 4 * q < g.k;
+        sX[buf][lk + 4 * u][lr] = (T)((kin && xin) ? xr[q] : 0.0);
+        sY[buf][lk + 4 * u][lr] = (T)((kin && yin) ? yr[q] : 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const T a0 = sY[buf][kk][wc + (lane & 15)];
+        const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const T b0 = sX[buf][kk][wr + (lane & 15)];
+        const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
+        if (row < t.m && col < t.n && (!diag || row >= col))
+          C[(int64_t)col * ldc + row] = cv[bj][bi][v] - (double)acc[bj][bi][v];
+      }
 }
 
 // right-looking factorization of the tr x 16 column block at column o of T
@@ -225,33 +336,120 @@ __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, in
 
 constexpr int AP = 65;  // LDS pitch of the staged row tile: sA[k * AP + r] = A(r, k)
 
+constexpr int IP = 17;  // LDS row pitch of the 16x16 inverse blocks
+
+// T(q, p) -= Y_q Y_p^T over the 64 columns of the previous column block, Y
+// staged k-major in sY (pitch yp): the tile's share of that block's trailing
+// update (two accumulation chains over the halves of k)
+__device__ __forceinline__ void pre_syrk16(double* T, int tp, const double* sY, int yp, int q,
+                                           int p, int lane) {
+  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+  const int kl = lane >> 4, il = lane & 15;
+#pragma unroll
+  for (int kq = 0; kq < 16; kq += 2) {
+    const int k0 = 4 * kq + kl, k1 = k0 + 4;
+    c0 = mfma64(sY[k0 * yp + 16 * q + il], sY[k0 * yp + 16 * p + il], c0);
+    c1 = mfma64(sY[k1 * yp + 16 * q + il], sY[k1 * yp + 16 * p + il], c1);
+  }
+  const v4d acc = c0 + c1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) T[(16 * q + 4 * v + kl) * tp + 16 * p + il] -= acc[v];
+}
+
+// rows 16a.. and columns 16b.. of a k-major row tile sA (pitch AP) minus
+// X_a Y_b^T over the previous column block, X staged k-major in sX (pitch AP):
+// the MFMA forms (Y_b X_a^T), whose result layout is sA's k-major layout
+__device__ __forceinline__ void pre_gemm16(double* sA, const double* sX, const double* sY, int yp,
+                                           int a, int b, int lane) {
+  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+  const int kl = lane >> 4, il = lane & 15;
+#pragma unroll
+  for (int kq = 0; kq < 16; kq += 2) {
+    const int k0 = 4 * kq + kl, k1 = k0 + 4;
+    c0 = mfma64(sY[k0 * yp + 16 * b + il], sX[k0 * AP + 16 * a + il], c0);
+    c1 = mfma64(sY[k1 * yp + 16 * b + il], sX[k1 * AP + 16 * a + il], c1);
+  }
+  const v4d acc = c0 + c1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sA[(16 * b + 4 * v + kl) * AP + 16 * a + il] -= acc[v];
+}
+
+template <int MODE>
+struct PanelUpd {
+  typedef double type;  // FP64 form
+};
+template <>
+struct PanelUpd<1> {
+  typedef float type;  // FP32 update operands
+};
+
+// resident workgroups per compute unit the register budget is sized for
+// (the FP64 form's fused update tiles need more registers than 3 per unit allow)
+constexpr int panel_occupancy(int mode, int nbb, bool pre) {
+  return pre ? (nbb == 1 && mode != 0 ? 2 : 1) : (nbb == 1 ? (mode == 0 ? 2 : 3) : (nbb == 2 ? 2 : 1));
+}
+
 // MODE 0: FP64 form. MODE 1: reduced-precision updates (pivot patching).
 // MODE 2: 16-bit updates (pivot patching, and the largest |entry| of the row
 // tiles, overall and in the rows below the diagonal block, into the scale
 // slots of the column block and of the supernode).
 // NBB: 16-column blocks of the widest tile of the launch (1, 2 or 4); the
 // tile and its LDS images are 16*NBB wide.
-template <int MODE, int NBB>
-__global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_panel(const PanelTile* __restrict__ tiles,
-                                               double* __restrict__ L, int* __restrict__ status,
-                                               int* __restrict__ counters,
-                                               const double* __restrict__ thr,
-                                               const unsigned long long* __restrict__ amax,
-                                               double ufix, unsigned long long* __restrict__ smax,
-                                               unsigned int* __restrict__ nfixed) {
+// PRE: the column block's own share of the trailing update of the previous
+// (64-column) block of its supernode is applied here, before the
+// factorization, in FP64 on MFMA: T -= Y Y^T on the diagonal tile and
+// A -= X Y^T on each row tile, Y and X being the previous block's entries in
+// the rows of the diagonal tile and of the row tile (they sit 64 columns to
+// the left). Column block 0 of T is updated by all waves before the first
+// pivot round, the other column blocks and the row tile by waves 1-3 while
+// wave 0 factors.
+// Workgroups blockIdx.x >= npanel (MODE 0 and 1) each run one tile of utiles:
+// the rest of that previous block's trailing update (single-contribution
+// tiles, k <= 64) in the update precision of the form; those tiles lie right
+// of this column block, so the two kinds of work touch disjoint entries.
+template <int MODE, int NBB, bool PRE>
+__global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
+    const PanelTile* __restrict__ tiles, double* __restrict__ L, int* __restrict__ status,
+    int* __restrict__ counters, const double* __restrict__ thr,
+    const unsigned long long* __restrict__ amax, double ufix, unsigned long long* __restrict__ smax,
+    unsigned int* __restrict__ nfixed, const UpdTile* __restrict__ utiles,
+    const UpdSeg* __restrict__ usegs, int npanel) {
   constexpr int TR = 16 * NBB;  // tile rows and columns
   constexpr int TPn = TR + 1;   // LDS row pitch of the tile images
+  constexpr int YP = TR + 1;    // pitch of sY
+  // LDS carve (doubles): the tile T (row-major), the inverses of its 16x16
+  // diagonal blocks, the row tile (k-major), the finished columns of the
+  // current 16-column block, and for PRE the previous block's rows Y and X
+  constexpr int O_I = TR * TPn;
+  constexpr int O_A = O_I + NBB * 16 * IP;
+  constexpr int O_LC = O_A + TR * AP;
+  constexpr int O_Y = O_LC + 16 * 64;
+  constexpr int O_X = O_Y + (PRE ? 64 * YP : 0);
+  constexpr int N_PANEL = O_X + (PRE ? 64 * AP : 0);
+  constexpr int N_UPD = MODE == 2 ? 0 : 4 * KC * 64 * (int)sizeof(typename PanelUpd<MODE>::type) / 8;
+  constexpr int N_LDS = N_PANEL > N_UPD ? N_PANEL : N_UPD;
+  __shared__ double smem[N_LDS];
+  __shared__ int s_last;
+  __shared__ unsigned long long s_max[2];
+  if (MODE != 2 && (int)blockIdx.x >= npanel) {
+    typedef typename PanelUpd<MODE>::type UT;
+    UT* su = reinterpret_cast<UT*>(smem);
+    const UpdTile ut = utiles[blockIdx.x - npanel];
+    upd_short_tile<UT>(ut, usegs[ut.seg0], L, reinterpret_cast<UT(*)[KC][64]>(su),
+                       reinterpret_cast<UT(*)[KC][64]>(su + 2 * KC * 64));
+    return;
+  }
+  double* const T = smem;
+  double* const Ib = smem + O_I;
+  double* const sA = smem + O_A;
+  double* const Lc = smem + O_LC;
+  double* const sY = smem + O_Y;
+  double* const sX = smem + O_X;
   const PanelTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = t.nb, ldi = t.ld;
   const int nr = min(64, t.nrows - t.row0);  // rows of the first row tile (may be <= 0)
   double* D = L + t.diag;
-  __shared__ double T[TR * TPn];  // the tile, row-major: T[i*TPn + j]
-  __shared__ double I[TR * TPn];  // inverses of its 16x16 diagonal blocks
-  __shared__ double sA[TR * AP];  // the row tile, k-major
-  __shared__ double Lc[16 * 64];  // finished columns of the current 16-column block
-  __shared__ int s_last;
-  __shared__ unsigned long long s_max[2];
   // stage: thread (row, cg) loads columns cg, cg+4, ..., all loads in flight;
   // addresses are clamped so every load is in bounds
   {
@@ -259,11 +457,20 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
     const int dr = min(row, nb - 1);
     const int arow = min(t.row0 + max(0, min(row, nr - 1)), t.nrows - 1);
     double dv[4 * NBB], av[4 * NBB];
+    double yv[PRE ? 16 : 1], xv[PRE ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < 4 * NBB; ++i) {
       const int j = min(cg + 4 * i, nb - 1);
       dv[i] = D[(int64_t)j * ldi + dr];
       av[i] = D[(int64_t)j * ldi + arow];
+    }
+    if (PRE) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t kk = cg + 4 * i - 64;
+        yv[i] = D[kk * ldi + dr];
+        xv[i] = D[kk * ldi + arow];
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4 * NBB; ++i) {
@@ -272,9 +479,18 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
         T[row * TPn + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
       sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
     }
+    if (PRE) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int kk = cg + 4 * i;
+        if (row < TR) sY[kk * YP + row] = row < nb ? yv[i] : 0.0;
+        sX[kk * AP + row] = row < nr ? xv[i] : 0.0;
+      }
+    }
   }
   __syncthreads();
-  if (tid == 0) {
+  // group counter on a wave that does not start the pivot chain
+  if (tid == 192) {
     const int old = atomicAdd(&counters[t.grp], 1);
     const int last = (old == t.gcnt - 1);
     if (last) atomicExch(&counters[t.grp], 0);
@@ -291,19 +507,45 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
     crep = ufix * am;
     if (tid < 2) s_max[tid] = 0ull;
   }
+  if (PRE) {
+    if (wave < nbb) pre_syrk16(T, TPn, sY, YP, wave, 0, lane);
+    __syncthreads();
+  }
+  // row-tile jobs of the previous block's update: job j = (column block j/4,
+  // row block j%4), wave w (1..3) takes j = w-1, w+2, ... a few per round
+  const int njobs = (PRE && t.nrt > 0) ? 4 * nbb : 0;
+  int jdone = 0;
   for (int r = 0; r < nbb; ++r) {
     if (wave == 0) {
       bad = min(bad, panel16<(MODE >= 1)>(T, TPn, TR, Lc, 16 * r, nb, t.col, lane, cthr, crep,
                                           &nfix));
-    } else if (r >= 1) {
-      if (wave == 3) {
-        inv16(T, I, TPn, 16 * (r - 1), lane);
-      } else {
-        // block r-1's updates of column blocks p >= r+1
-        int idx = 0;
-        for (int p = r + 1; p < nbb; ++p)
-          for (int q = p; q < nbb; ++q, ++idx)
-            if ((idx & 1) == wave - 1) syrk16(T, TPn, q, p, r - 1, lane);
+    } else {
+      if (r >= 1) {
+        if (wave == 3) {
+          inv16(T, TPn, 16 * (r - 1), Ib + (r - 1) * 16 * IP, IP, lane);
+        } else {
+          // block r-1's updates of column blocks p >= r+1
+          int idx = 0;
+          for (int p = r + 1; p < nbb; ++p)
+            for (int q = p; q < nbb; ++q, ++idx)
+              if ((idx & 1) == wave - 1) syrk16(T, TPn, q, p, r - 1, lane);
+        }
+      }
+      if (PRE) {
+        if (r == 0) {
+          // the previous block's update of column blocks 1.. of the tile
+          int idx = 0;
+          for (int p = 1; p < nbb; ++p)
+            for (int q = p; q < nbb; ++q, ++idx)
+              if (idx % 3 == wave - 1) pre_syrk16(T, TPn, sY, YP, q, p, lane);
+        }
+        const int quota = r == nbb - 1 ? njobs : (r == 0 ? 2 : (wave == 3 ? r : 3));
+        for (int c = 0; c < quota; ++c) {
+          const int j = wave - 1 + 3 * jdone;
+          if (j >= njobs) break;
+          if (16 * (j & 3) < nr) pre_gemm16(sA, sX, sY, YP, j & 3, j >> 2, lane);
+          ++jdone;
+        }
       }
     }
     __syncthreads();
@@ -313,7 +555,7 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
   }
   // the last base inverse (wave 3) alongside the first column blocks of the
   // row tiles' solves
-  if (wave == 3) inv16(T, I, TPn, 16 * (nbb - 1), lane);
+  if (wave == 3) inv16(T, TPn, 16 * (nbb - 1), Ib + (nbb - 1) * 16 * IP, IP, lane);
   // the last reader writes the factored tile (lower triangle)
   if (s_last) {
     if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
@@ -340,15 +582,28 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
       __syncthreads();  // the previous tile's reads of sA are done
       const int row = lane, cg = wave;
       const int arow = row0 + min(row, nrt_rows - 1);
-      double av[4 * NBB];
+      double av[4 * NBB], xv[PRE ? 16 : 1];
 #pragma unroll
       for (int i = 0; i < 4 * NBB; ++i) av[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + arow];
+      if (PRE) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xv[i] = D[(int64_t)(cg + 4 * i - 64) * ldi + arow];
+      }
 #pragma unroll
       for (int i = 0; i < 4 * NBB; ++i) {
         const int j = cg + 4 * i;
         sA[j * AP + row] = (row < nrt_rows && j < nb) ? av[i] : 0.0;
       }
+      if (PRE) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sX[(cg + 4 * i) * AP + row] = row < nrt_rows ? xv[i] : 0.0;
+      }
       __syncthreads();
+      if (PRE) {
+        for (int j = wave; j < 4 * nbb; j += 4)
+          if (16 * (j & 3) < nrt_rows) pre_gemm16(sA, sX, sY, YP, j & 3, j >> 2, lane);
+        __syncthreads();
+      }
     }
     v4d X[NBB];
 #pragma unroll
@@ -369,7 +624,7 @@ __global__ __launch_bounds__(256, NBB == 1 ? 3 : (NBB == 2 ? 2 : 1)) void k_pane
         v4d x = {0, 0, 0, 0};
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq)
-          x = mfma64(I[(16 * b + (lane & 15)) * TPn + 16 * b + 4 * kq + (lane >> 4)], r[kq], x);
+          x = mfma64(Ib[(16 * b + (lane & 15)) * IP + 4 * kq + (lane >> 4)], r[kq], x);
         X[b] = x;
         const int rr = 16 * rb + (lane & 15);
 #pragma unroll
@@ -431,7 +686,7 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict
   }
   __syncthreads();
   const int nbb = (nb + 15) >> 4;
-  if (wave < nbb) inv16(T, I, TPn, 16 * wave, lane);
+  if (wave < nbb) inv16(T, TPn, 16 * wave, &I[16 * wave * TPn + 16 * wave], TPn, lane);
   __syncthreads();
   if (NBB >= 2) {
     // level 1: blocks (1,0) and (3,2) = -inv(i,i) * (L(i,j) * inv(j,j))
@@ -483,33 +738,6 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict
 // the start and written once at the end; the parts of a split tile are added
 // with atomics.
 //
-// MFMA 16x16x4 operand layout (lane l): A[l%16][l/16] and B[l/16][l%16]. The
-// accumulator layout differs by type: for FP64 element v of lane l is
-// D[4*v + l/16][l%16]; for FP32 it is D[4*(l/16) + v][l%16]. The kernel computes
-// D = Y * X^T, so D's column index is the target row: for fixed v, 16 lanes
-// cover 16 consecutive rows of one target column, which keeps the
-// read-modify-write of column-major storage coalesced.
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef v4d acc_t;
-  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * v + (lane >> 4); }
-};
-template <>
-struct Mfma<float> {
-  typedef v4f acc_t;
-  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-
-constexpr int KC = 16;  // K chunk staged per LDS buffer
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles,
                                                 const UpdSeg* __restrict__ segs,
@@ -677,89 +905,15 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
 
-// The same update for launches whose tiles all hold a single contribution
-// with k <= 64 and a single owner (the trailing updates of a step): every
-// load of K is issued up front, so the tile waits for memory once.
+// The trailing updates of a step as a launch of their own.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_short(const UpdTile* __restrict__ tiles,
                                                       const UpdSeg* __restrict__ segs,
                                                       double* __restrict__ L) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  const UpdTile t = tiles[blockIdx.x];
-  const UpdSeg g = segs[t.seg0];
   __shared__ T sX[2][KC][64];
   __shared__ T sY[2][KC][64];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
-  const int lr = tid & 63, lk = tid >> 6;
-  double* __restrict__ C = L + t.c;
-  const int64_t ldc = t.ldc;
-  const bool diag = t.flags & 1;
-  const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
-  const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
-  const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
-  double xr[16], yr[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int64_t kk = min(lk + 4 * q, g.k - 1);
-    xr[q] = L[xo + kk * g.lds];
-    yr[q] = L[yo + kk * g.lds];
-  }
-  double cv[2][2][4];
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
-        const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
-        cv[bj][bi][v] = C[(int64_t)col * ldc + row];
-      }
-  acc_t acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  const int nch = (g.k + KC - 1) / KC;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (c < nch) {
-      const int buf = c & 1;
-#pragma unroll
-      for (int u = 0; u < KC / 4; ++u) {
-        const int q = 4 * c + u;
-        const bool kin = lk + 4 * q < g.k;
-        sX[buf][lk + 4 * u][lr] = (T)((kin && xin) ? xr[q] : 0.0);
-        sY[buf][lk + 4 * u][lr] = (T)((kin && yin) ? yr[q] : 0.0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kq = 0; kq < KC / 4; ++kq) {
-        const int kk = kq * 4 + (lane >> 4);
-        const T a0 = sY[buf][kk][wc + (lane & 15)];
-        const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
-        const T b0 = sX[buf][kk][wr + (lane & 15)];
-        const T b1 = sX[buf][kk][wr + 16 + (lane & 15)];
-        acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
-      }
-    }
-  }
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + (lane & 15);
-        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
-        if (row < t.m && col < t.n && (!diag || row >= col))
-          C[(int64_t)col * ldc + row] = cv[bj][bi][v] - (double)acc[bj][bi][v];
-      }
+  const UpdTile t = tiles[blockIdx.x];
+  upd_short_tile<T>(t, segs[t.seg0], L, sX, sY);
 }
 
 template __global__ void k_update_short<double>(const UpdTile*, const UpdSeg*, double*);
@@ -1303,35 +1457,45 @@ void launch_scatter_batch(const double* const* vals, const int64_t* nnz_ptr, int
   hipLaunchKernelGGL(k_scatter_batch, dim3(grid_for(total, 256, INT32_MAX)), dim3(256), 0, st,
                      vals, nnz_ptr, count, total, amap, L);
 }
-template <int NBB>
+template <int NBB, bool PRE>
 static void launch_panel_n(const PanelTile* tiles, int64_t count, double* L, int* status,
                            int* counters, int mode, const double* thr,
                            const unsigned long long* amax, double ufix, unsigned long long* smax,
-                           unsigned int* nfixed, hipStream_t st) {
-  const dim3 g((unsigned)count), b(256);
+                           unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
+                           int64_t ucount, hipStream_t st) {
+  const int np = (int)count;
+  const dim3 b(256);
   if (mode == 0)
-    hipLaunchKernelGGL((k_panel<0, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
-                       smax, nfixed);
+    hipLaunchKernelGGL((k_panel<0, NBB, PRE>), dim3((unsigned)(count + ucount)), b, 0, st, tiles,
+                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_panel<1, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
-                       smax, nfixed);
+    hipLaunchKernelGGL((k_panel<1, NBB, PRE>), dim3((unsigned)(count + ucount)), b, 0, st, tiles,
+                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
   else
-    hipLaunchKernelGGL((k_panel<2, NBB>), g, b, 0, st, tiles, L, status, counters, thr, amax, ufix,
-                       smax, nfixed);
+    hipLaunchKernelGGL((k_panel<2, NBB, PRE>), dim3((unsigned)count), b, 0, st, tiles, L, status,
+                       counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
 }
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
-                  int precision, int nbb, const double* thr, const unsigned long long* amax,
-                  double ufix, unsigned long long* smax, unsigned int* nfixed, hipStream_t st) {
+                  int precision, int nbb, bool pre, const double* thr,
+                  const unsigned long long* amax, double ufix, unsigned long long* smax,
+                  unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
+                  int64_t ucount, hipStream_t st) {
   if (count <= 0) return;
-  if (nbb <= 1)
-    launch_panel_n<1>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
-                      st);
-  else if (nbb == 2)
-    launch_panel_n<2>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
-                      st);
-  else
-    launch_panel_n<4>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed,
-                      st);
+  if (precision == 2) ucount = 0;
+#define RLB_PANEL_N(N, P)                                                                       \
+  launch_panel_n<N, P>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed, \
+                       utiles, usegs, ucount, st)
+  if (nbb <= 1) {
+    if (pre) RLB_PANEL_N(1, true);
+    else RLB_PANEL_N(1, false);
+  } else if (nbb == 2) {
+    if (pre) RLB_PANEL_N(2, true);
+    else RLB_PANEL_N(2, false);
+  } else {
+    if (pre) RLB_PANEL_N(4, true);
+    else RLB_PANEL_N(4, false);
+  }
+#undef RLB_PANEL_N
 }
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st) {

@@ -40,6 +40,22 @@ constexpr double PANEL_US[3] = {6.0, 10.0, 16.0};
 constexpr int64_t PANEL_SLOTS[3] = {3 * 256, 2 * 256, 256};
 constexpr double LAUNCH_US = 4.0;
 constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a tile is split
+// fusion of a step's trailing update into the next panel launch: compute
+// units of the device, and short update tiles one unit runs while the panel
+// workgroups factor (one resident workgroup per unit in a fused launch)
+constexpr int64_t DEVICE_CUS = 256;
+constexpr int64_t FUSE_TILES_PER_CU = 4;
+
+// the update work of one step before it is placed: target tiles with their
+// contributions; `next` marks the trailing tiles of the column block right
+// after the step's block, which the next panel launch can apply itself
+struct PendingUpdate {
+  bool valid = false;
+  int32_t level = 0, step = 0;
+  std::vector<UpdTile> tiles;               // seg0 relative to `segs`
+  std::vector<UpdSeg> segs;
+  std::vector<char> next;
+};
 
 // One rectangle of the ancestor update: target rows [r0, r0+mr) and columns
 // [c0, c0+nc) of Lnz(P); source rows [sx, ..) and [sy, ..) of Lnz(J).
@@ -197,10 +213,46 @@ int build_plan(Symbolic& s, std::string& err) {
 
   // launches
   p.flops_tiles = 0;
+  // places a step's update work: every tile (or every tile not marked next)
+  // goes to p.updates, heaviest workgroups first; into a launch of its own,
+  // or as the fused part of panel launch `fused_into`
+  auto commit = [&](const PendingUpdate& u, bool skip_next, int64_t fused_into) {
+    const int64_t start = (int64_t)p.updates.size();
+    std::vector<std::pair<int64_t, size_t>> order;
+    for (size_t i = 0; i < u.tiles.size(); ++i) {
+      if (skip_next && u.next[i]) continue;
+      int64_t ch = 0;
+      for (int32_t e = 0; e < u.tiles[i].nseg; ++e)
+        ch += (u.segs[u.tiles[i].seg0 + e].k + KCH - 1) / KCH;
+      order.push_back({-ch, i});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int64_t, size_t>& x, const std::pair<int64_t, size_t>& y) {
+                       return x.first < y.first;
+                     });
+    bool shortk = true;
+    for (auto& o : order) {
+      UpdTile t = u.tiles[o.second];
+      const int32_t s0 = t.seg0;
+      t.seg0 = (int32_t)p.segs.size();
+      for (int32_t e = 0; e < t.nseg; ++e) p.segs.push_back(u.segs[s0 + e]);
+      if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || u.segs[s0].k > 64) shortk = false;
+      p.updates.push_back(t);
+    }
+    const int64_t count = (int64_t)p.updates.size() - start;
+    if (fused_into >= 0) {
+      p.launches[fused_into].ustart = start;
+      p.launches[fused_into].ucount = count;
+    } else if (count) {
+      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, count, 0, 0, 0, 0};
+      p.launches.push_back(lu);
+    }
+  };
   for (int32_t h = 0; h < p.nlevels; ++h) {
     int64_t steps = 0;
     for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
       steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
+    PendingUpdate pend;
     for (int64_t k = 0; k < steps; ++k) {
       // PANEL: one group per supernode with a column block k, one workgroup
       // per 64 rows below the diagonal tile (a single one when there are
@@ -269,18 +321,54 @@ int build_plan(Symbolic& s, std::string& err) {
           ngroups[ci] = 0;
           cls[ci].clear();
         }
+      // the previous step's update: its trailing tiles of this column block
+      // go into this step's panel workgroups (pre-update) and the rest runs
+      // as extra workgroups of this step's widest panel launch, when the rest
+      // is all short single-contribution tiles few enough to run beside the
+      // panel workgroups; otherwise it keeps a launch of its own, before
+      // this step's panels
+      bool fuse = false;
+      if (pend.valid) {
+        int64_t rest = 0, npw = 0;
+        bool short_rest = true;
+        for (size_t i = 0; i < pend.tiles.size(); ++i) {
+          if (pend.next[i]) continue;
+          ++rest;
+          const UpdTile& t = pend.tiles[i];
+          if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || pend.segs[t.seg0].k > 64)
+            short_rest = false;
+        }
+        for (int ci = 0; ci < 3; ++ci) npw += (int64_t)cls[ci].size();
+        fuse = short_rest && rest <= FUSE_TILES_PER_CU * std::max<int64_t>(0, DEVICE_CUS - npw);
+        if (!fuse) commit(pend, false, -1);
+      }
       const int32_t cls_nbb[3] = {1, 2, 4};
+      int64_t widest = -1;
       for (int ci = 0; ci < 3; ++ci) {
         if (cls[ci].empty()) continue;
         Launch lp{LAUNCH_PANEL, h, (int32_t)k, cls_nbb[ci], (int64_t)p.panels.size(),
-                  (int64_t)cls[ci].size()};
+                  (int64_t)cls[ci].size(), fuse ? 1 : 0, 0, 0, 0};
         p.panels.insert(p.panels.end(), cls[ci].begin(), cls[ci].end());
+        widest = (int64_t)p.launches.size();
         p.launches.push_back(lp);
         p.max_groups = std::max(p.max_groups, ngroups[ci]);
       }
-      // UPDATE: trailing updates of step k, ancestor updates of finished
-      // supernodes; one target tile per workgroup with all its contributions
-      Launch lu{LAUNCH_UPDATE, h, (int32_t)k, 0, (int64_t)p.updates.size(), 0};
+      if (fuse) commit(pend, true, widest);
+      // UPDATE work of step k: trailing updates of its block, and the
+      // ancestor updates of supernodes whose last block it is; one target
+      // tile per workgroup with all its contributions
+      pend = PendingUpdate();
+      pend.valid = true;
+      pend.level = h;
+      pend.step = (int32_t)k;
+      auto add_tile = [&](UpdTile t, const std::vector<UpdSeg>& gs, size_t g0, size_t g1,
+                          bool next) {
+        t.seg0 = (int32_t)pend.segs.size();
+        t.nseg = (int32_t)(g1 - g0);
+        pend.segs.insert(pend.segs.end(), gs.begin() + g0, gs.begin() + g1);
+        pend.tiles.push_back(t);
+        pend.next.push_back(next ? 1 : 0);
+      };
       std::vector<int64_t> finished;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
@@ -298,8 +386,6 @@ int build_plan(Symbolic& s, std::string& err) {
               t.m = (int32_t)tm;
               t.n = (int32_t)tn;
               t.flags = diag ? FLAG_DIAG : 0;
-              t.seg0 = (int32_t)p.segs.size();
-              t.nseg = 1;
               UpdSeg g;
               g.x = p.off[J] + c0 * m + ti0;
               g.y = p.off[J] + c0 * m + tj0;
@@ -311,8 +397,7 @@ int build_plan(Symbolic& s, std::string& err) {
               g.cb = (int32_t)tn;
               g.src = (int32_t)J;
               g.sslot = sbase[J] + (int32_t)k;
-              p.updates.push_back(t);
-              p.segs.push_back(g);
+              add_tile(t, std::vector<UpdSeg>{g}, 0, 1, tj0 == c1);
               p.flops_tiles += seg_exec_flops(0, tm, 0, tn, nb);
               p.flops_upd_alg += 2.0 * (double)nb * seg_entries(0, tm, 0, tn, diag);
             }
@@ -371,15 +456,11 @@ int build_plan(Symbolic& s, std::string& err) {
         int64_t chunks = 0;
         for (const UpdSeg& g : kv.second) chunks += (g.k + KCH - 1) / KCH;
         if (chunks <= WG_CHUNKS) {
-          t.seg0 = (int32_t)p.segs.size();
-          t.nseg = (int32_t)kv.second.size();
-          p.segs.insert(p.segs.end(), kv.second.begin(), kv.second.end());
-          p.updates.push_back(t);
+          add_tile(t, kv.second, 0, kv.second.size(), false);
           continue;
         }
         t.flags |= FLAG_ATOMIC;
-        t.seg0 = (int32_t)p.segs.size();
-        t.nseg = 0;
+        std::vector<UpdSeg> part;
         int64_t used = 0;
         for (const UpdSeg& g : kv.second) {
           for (int64_t k0 = 0; k0 < g.k;) {
@@ -388,52 +469,24 @@ int build_plan(Symbolic& s, std::string& err) {
             piece.x += k0 * g.lds;
             piece.y += k0 * g.lds;
             piece.k = (int32_t)take;
-            p.segs.push_back(piece);
-            t.nseg++;
+            part.push_back(piece);
             used += (take + KCH - 1) / KCH;
             k0 += take;
             if (used >= WG_CHUNKS) {
-              p.updates.push_back(t);
+              add_tile(t, part, 0, part.size(), false);
               p.n_split_tiles++;
-              t.seg0 = (int32_t)p.segs.size();
-              t.nseg = 0;
+              part.clear();
               used = 0;
             }
           }
         }
-        if (t.nseg) {
-          p.updates.push_back(t);
+        if (!part.empty()) {
+          add_tile(t, part, 0, part.size(), false);
           p.n_split_tiles++;
         }
       }
-      // the heaviest workgroups first
-      {
-        std::vector<std::pair<int64_t, size_t>> order;
-        for (size_t i = (size_t)lu.start; i < p.updates.size(); ++i) {
-          int64_t ch = 0;
-          for (int32_t e = 0; e < p.updates[i].nseg; ++e)
-            ch += (p.segs[p.updates[i].seg0 + e].k + KCH - 1) / KCH;
-          order.push_back({-ch, i});
-        }
-        std::stable_sort(order.begin(), order.end(),
-                         [](const std::pair<int64_t, size_t>& a, const std::pair<int64_t, size_t>& b) {
-                           return a.first < b.first;
-                         });
-        std::vector<UpdTile> sorted;
-        for (auto& o : order) sorted.push_back(p.updates[o.second]);
-        std::copy(sorted.begin(), sorted.end(), p.updates.begin() + lu.start);
-      }
-      lu.count = (int64_t)p.updates.size() - lu.start;
-      lu.variant = 1;
-      for (int64_t i = lu.start; i < lu.start + lu.count; ++i) {
-        const UpdTile& t = p.updates[i];
-        if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || p.segs[t.seg0].k > 64) {
-          lu.variant = 0;
-          break;
-        }
-      }
-      if (lu.count) p.launches.push_back(lu);
     }
+    if (pend.valid) commit(pend, false, -1);
   }
   // diagonal tiles of every 64-column step, inverted after the factorization,
   // grouped by width class

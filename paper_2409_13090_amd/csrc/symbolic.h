@@ -118,6 +118,10 @@ struct Launch {
                    // panel: 16-column blocks of its widest tile (1, 2 or 4)
   int64_t start;  // first tile
   int64_t count;  // number of tiles
+  int32_t pre;    // panel: its tiles first apply the previous block's trailing update
+  int32_t pad;
+  int64_t ustart; // panel: update tiles of the previous step run in the same launch
+  int64_t ucount; //   (single-contribution tiles, k <= 64)
 };
 
 struct Plan {

@@ -5,9 +5,10 @@ factor (Algorithm 1) and solve A x = b to backward error ~1e-16.
 
 This pins the host lowering of Alg. 5 (storage offsets, ancestor rectangles
 cut by the target tile grid, relind-based target positions, level and step
-order, single-owner / split ownership of target tiles) independently of the
-GPU. Each kernel's dense block arithmetic is replaced by numpy here, so only
-the indexing and the ordering are under test."""
+order, single-owner / split ownership of target tiles, the previous block's
+update applied inside a panel launch and the update tiles that run beside its
+workgroups) independently of the GPU. Each kernel's dense block arithmetic is
+replaced by numpy here, so only the indexing and the ordering are under test."""
 import numpy as np
 import pytest
 
@@ -24,15 +25,52 @@ def replay_factor(A, **kw):
     U = s.array("update_tiles").reshape(-1, 7)
     G = s.array("update_segs").reshape(-1, 9)
     P = s.array("panel_tiles").reshape(-1, 11)
-    for kind, lev, step, st, cnt in s.array("launches").reshape(-1, 5):
+
+    def updates(tiles):
+        """Every target tile sums its contributions, then subtracts them once;
+        returns the entries read (sources) and written (targets)."""
+        owner, reads = {}, set()
+        for c, ldc, m, n, flags, seg0, nseg in tiles:
+            acc = np.zeros((m, n))
+            for x, y, lds, k, ra, rb, ca, cb, src in G[seg0:seg0 + nseg]:
+                assert 0 <= ra < rb <= m and 0 <= ca < cb <= n and k > 0
+                assert x + (k - 1) * lds + (rb - ra) - 1 < size
+                assert y + (k - 1) * lds + (cb - ca) - 1 < size
+                X = np.array([Lb[x + q * lds: x + q * lds + (rb - ra)] for q in range(k)]).T
+                Y = np.array([Lb[y + q * lds: y + q * lds + (cb - ca)] for q in range(k)]).T
+                acc[ra:rb, ca:cb] += X @ Y.T
+                for q in range(k):
+                    reads.update(range(x + q * lds, x + q * lds + rb - ra))
+                    reads.update(range(y + q * lds, y + q * lds + cb - ca))
+            for j in range(n):
+                for r in range(m):
+                    prev = owner.get(c + j * ldc + r)
+                    # one owner per entry, except the parts of a split tile
+                    assert prev is None or (prev and (flags & 2)), "two owners"
+                    owner[c + j * ldc + r] = bool(flags & 2)
+                col = acc[:, j].copy()
+                if flags & 1:
+                    col[:j] = 0.0
+                Lb[c + j * ldc: c + j * ldc + m] -= col
+        return reads, set(owner)
+
+    for kind, lev, step, st, cnt, variant, pre, ust, ucnt in s.array("launches").reshape(-1, 9):
         if kind == 0:
             groups = {}
             for t in P[st:st + cnt]:
                 groups.setdefault(int(t[7]), []).append(t)
+            touched = set()
             for mem in groups.values():
                 assert len(mem) == mem[0][8], "group size"
                 diag, ld, nb, nrows = (int(v) for v in mem[0][:4])
+                assert nb <= 16 * variant
                 D = np.array([Lb[diag + j * ld: diag + j * ld + nb] for j in range(nb)]).T
+                if pre:
+                    # the previous 64-column block's update of this column block
+                    assert step >= 1 and diag - 64 * ld >= 0
+                    Y = np.array([Lb[diag + (q - 64) * ld: diag + (q - 64) * ld + nb]
+                                  for q in range(64)]).T
+                    D = D - Y @ Y.T
                 Lt = np.linalg.cholesky(np.tril(D) + np.tril(D, -1).T)
                 covered = 0
                 for t in mem:
@@ -42,6 +80,10 @@ def replay_factor(A, **kw):
                         assert nb <= row0 < nrows and diag + (nb - 1) * ld + r1 - 1 < size
                         Arow = np.array([Lb[diag + j * ld + row0: diag + j * ld + r1]
                                          for j in range(nb)]).T
+                        if pre:
+                            X = np.array([Lb[diag + (q - 64) * ld + row0: diag + (q - 64) * ld + r1]
+                                          for q in range(64)]).T
+                            Arow = Arow - X @ Y.T
                         Xr = np.linalg.solve(Lt, Arow.T).T
                         for j in range(nb):
                             Lb[diag + j * ld + row0: diag + j * ld + r1] = Xr[:, j]
@@ -49,27 +91,19 @@ def replay_factor(A, **kw):
                 assert covered == nrows - nb, "row tiles cover the panel once"
                 for j in range(nb):
                     Lb[diag + j * ld + j: diag + j * ld + nb] = Lt[j:, j]
+                for j in range(nb):
+                    touched.update(range(diag + j * ld, diag + j * ld + nrows))
+            if ucnt:
+                # the previous step's remaining update tiles run in the same
+                # launch: they may neither write nor read the column blocks
+                # the panel workgroups write
+                assert pre
+                reads, writes = updates(U[ust:ust + ucnt])
+                assert not (reads & touched) and not (writes & touched), "fused overlap"
+                assert all(int(U[i][6]) == 1 and G[int(U[i][5])][3] <= 64
+                           for i in range(ust, ust + ucnt))
         else:
-            owner = {}
-            for c, ldc, m, n, flags, seg0, nseg in U[st:st + cnt]:
-                acc = np.zeros((m, n))
-                for x, y, lds, k, ra, rb, ca, cb, src in G[seg0:seg0 + nseg]:
-                    assert 0 <= ra < rb <= m and 0 <= ca < cb <= n and k > 0
-                    assert x + (k - 1) * lds + (rb - ra) - 1 < size
-                    assert y + (k - 1) * lds + (cb - ca) - 1 < size
-                    X = np.array([Lb[x + q * lds: x + q * lds + (rb - ra)] for q in range(k)]).T
-                    Y = np.array([Lb[y + q * lds: y + q * lds + (cb - ca)] for q in range(k)]).T
-                    acc[ra:rb, ca:cb] += X @ Y.T
-                for j in range(n):
-                    for r in range(m):
-                        prev = owner.get(c + j * ldc + r)
-                        # one owner per entry, except the parts of a split tile
-                        assert prev is None or (prev and (flags & 2)), "two owners"
-                        owner[c + j * ldc + r] = bool(flags & 2)
-                    col = acc[:, j].copy()
-                    if flags & 1:
-                        col[:j] = 0.0
-                    Lb[c + j * ldc: c + j * ldc + m] -= col
+            updates(U[st:st + cnt])
     for diag, ld, nb in s.array("diag_tiles").reshape(-1, 3):
         Lt = np.array([[Lb[diag + j * ld + i] if i >= j else 0.0 for j in range(nb)]
                        for i in range(nb)])

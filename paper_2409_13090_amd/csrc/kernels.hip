@@ -338,40 +338,103 @@ constexpr int AP = 65;  // LDS pitch of the staged row tile: sA[k * AP + r] = A(
 
 constexpr int IP = 17;  // LDS row pitch of the 16x16 inverse blocks
 
-// T(q, p) -= Y_q Y_p^T over the 64 columns of the previous column block, Y
-// staged k-major in sY (pitch yp): the tile's share of that block's trailing
-// update (two accumulation chains over the halves of k)
-__device__ __forceinline__ void pre_syrk16(double* T, int tp, const double* sY, int yp, int q,
-                                           int p, int lane) {
-  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+constexpr int YP = 66;  // LDS row pitch of the previous block's rows Y and X (row-major)
+
+// The previous block's update of the tile and the row tile, K = 64: an FP64
+// MFMA 16x16x4 sums over k in any order as long as both operands use the same
+// one, so step kq takes k = 16 g + kq in lane group g = l/16; a lane's
+// operands of a product are then consecutive doubles of one row of Y (or X),
+// read as 16-byte LDS loads. The loads of the next two steps are issued
+// before the products of the current two (a wave cannot issue past an MFMA
+// that waits for the matrix pipe), and sched_barrier keeps that order.
+__device__ __forceinline__ v4d pre_mma64(const double* Ra, const double* Rb, int lane) {
   const int kl = lane >> 4, il = lane & 15;
+  const double* pa = Ra + il * YP + 16 * kl;
+  const double* pb = Rb + il * YP + 16 * kl;
+  double2 a = *reinterpret_cast<const double2*>(pa), b = *reinterpret_cast<const double2*>(pb);
+  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
 #pragma unroll
   for (int kq = 0; kq < 16; kq += 2) {
-    const int k0 = 4 * kq + kl, k1 = k0 + 4;
-    c0 = mfma64(sY[k0 * yp + 16 * q + il], sY[k0 * yp + 16 * p + il], c0);
-    c1 = mfma64(sY[k1 * yp + 16 * q + il], sY[k1 * yp + 16 * p + il], c1);
+    double2 na = a, nb = b;
+    if (kq + 2 < 16) {
+      na = *reinterpret_cast<const double2*>(pa + kq + 2);
+      nb = *reinterpret_cast<const double2*>(pb + kq + 2);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    c0 = mfma64(a.x, b.x, c0);
+    c1 = mfma64(a.y, b.y, c1);
+    __builtin_amdgcn_sched_barrier(0);
+    a = na;
+    b = nb;
   }
-  const v4d acc = c0 + c1;
+  return c0 + c1;
+}
+
+// T(q, p) -= Y_q Y_p^T (sY row-major, pitch YP)
+__device__ __forceinline__ void pre_syrk16(double* T, int tp, const double* sY, int q, int p,
+                                           int lane) {
+  const v4d acc = pre_mma64(sY + 16 * q * YP, sY + 16 * p * YP, lane);
+  const int kl = lane >> 4, il = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) T[(16 * q + 4 * v + kl) * tp + 16 * p + il] -= acc[v];
 }
 
-// rows 16a.. and columns 16b.. of a k-major row tile sA (pitch AP) minus
-// X_a Y_b^T over the previous column block, X staged k-major in sX (pitch AP):
-// the MFMA forms (Y_b X_a^T), whose result layout is sA's k-major layout
-__device__ __forceinline__ void pre_gemm16(double* sA, const double* sX, const double* sY, int yp,
-                                           int a, int b, int lane) {
-  v4d c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+// row blocks a0, a0+1 and column blocks b0, b0+1 (b0 only without TWO) of
+// the k-major row tile sA (pitch AP) minus X_a Y_b^T (sX, sY row-major, pitch
+// YP): each product is formed as Y_b X_a^T, whose MFMA result layout is sA's
+// k-major layout; every operand loaded serves two of the products
+template <bool TWO>
+__device__ __forceinline__ void pre_gemm2x2(double* sA, const double* sX, const double* sY,
+                                            int a0, int b0, int lane) {
   const int kl = lane >> 4, il = lane & 15;
+  const double* y0 = sY + (16 * b0 + il) * YP + 16 * kl;
+  const double* y1 = y0 + 16 * YP;
+  const double* x0 = sX + (16 * a0 + il) * YP + 16 * kl;
+  const double* x1 = x0 + 16 * YP;
+  v4d c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;  // c[b][a]
+  double2 ya = *reinterpret_cast<const double2*>(y0);
+  double2 yb = TWO ? *reinterpret_cast<const double2*>(y1) : ya;
+  double2 xa = *reinterpret_cast<const double2*>(x0);
+  double2 xb = *reinterpret_cast<const double2*>(x1);
 #pragma unroll
   for (int kq = 0; kq < 16; kq += 2) {
-    const int k0 = 4 * kq + kl, k1 = k0 + 4;
-    c0 = mfma64(sY[k0 * yp + 16 * b + il], sX[k0 * AP + 16 * a + il], c0);
-    c1 = mfma64(sY[k1 * yp + 16 * b + il], sX[k1 * AP + 16 * a + il], c1);
+    double2 nya = ya, nyb = yb, nxa = xa, nxb = xb;
+    if (kq + 2 < 16) {
+      nya = *reinterpret_cast<const double2*>(y0 + kq + 2);
+      if (TWO) nyb = *reinterpret_cast<const double2*>(y1 + kq + 2);
+      nxa = *reinterpret_cast<const double2*>(x0 + kq + 2);
+      nxb = *reinterpret_cast<const double2*>(x1 + kq + 2);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    c00 = mfma64(ya.x, xa.x, c00);
+    c01 = mfma64(ya.x, xb.x, c01);
+    if (TWO) {
+      c10 = mfma64(yb.x, xa.x, c10);
+      c11 = mfma64(yb.x, xb.x, c11);
+    }
+    c00 = mfma64(ya.y, xa.y, c00);
+    c01 = mfma64(ya.y, xb.y, c01);
+    if (TWO) {
+      c10 = mfma64(yb.y, xa.y, c10);
+      c11 = mfma64(yb.y, xb.y, c11);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    ya = nya;
+    yb = nyb;
+    xa = nxa;
+    xb = nxb;
   }
-  const v4d acc = c0 + c1;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) sA[(16 * b + 4 * v + kl) * AP + 16 * a + il] -= acc[v];
+  for (int v = 0; v < 4; ++v) {
+    double* r0 = sA + (16 * b0 + 4 * v + kl) * AP + 16 * a0 + il;
+    r0[0] -= c00[v];
+    r0[16] -= c01[v];
+    if (TWO) {
+      double* r1 = r0 + 16 * AP;
+      r1[0] -= c10[v];
+      r1[16] -= c11[v];
+    }
+  }
 }
 
 template <int MODE>
@@ -416,7 +479,6 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
     const UpdSeg* __restrict__ usegs, int npanel) {
   constexpr int TR = 16 * NBB;  // tile rows and columns
   constexpr int TPn = TR + 1;   // LDS row pitch of the tile images
-  constexpr int YP = TR + 1;    // pitch of sY
   // LDS carve (doubles): the tile T (row-major), the inverses of its 16x16
   // diagonal blocks, the row tile (k-major), the finished columns of the
   // current 16-column block, and for PRE the previous block's rows Y and X
@@ -424,8 +486,8 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
   constexpr int O_A = O_I + NBB * 16 * IP;
   constexpr int O_LC = O_A + TR * AP;
   constexpr int O_Y = O_LC + 16 * 64;
-  constexpr int O_X = O_Y + (PRE ? 64 * YP : 0);
-  constexpr int N_PANEL = O_X + (PRE ? 64 * AP : 0);
+  constexpr int O_X = O_Y + (PRE ? TR * YP : 0);
+  constexpr int N_PANEL = O_X + (PRE ? 64 * YP : 0);
   constexpr int N_UPD = MODE == 2 ? 0 : 4 * KC * 64 * (int)sizeof(typename PanelUpd<MODE>::type) / 8;
   constexpr int N_LDS = N_PANEL > N_UPD ? N_PANEL : N_UPD;
   __shared__ double smem[N_LDS];
@@ -451,51 +513,37 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
   const int nr = min(64, t.nrows - t.row0);  // rows of the first row tile (may be <= 0)
   double* D = L + t.diag;
   // stage: thread (row, cg) loads columns cg, cg+4, ..., all loads in flight;
-  // addresses are clamped so every load is in bounds
+  // addresses are clamped so every load is in bounds. With PRE the row tile
+  // and its X rows are staged later, during the first pivot round.
+  const int arow0 = min(t.row0 + max(0, min(lane, nr - 1)), t.nrows - 1);
   {
     const int row = lane, cg = wave;
     const int dr = min(row, nb - 1);
-    const int arow = min(t.row0 + max(0, min(row, nr - 1)), t.nrows - 1);
-    double dv[4 * NBB], av[4 * NBB];
-    double yv[PRE ? 16 : 1], xv[PRE ? 16 : 1];
+    double dv[4 * NBB], av[PRE ? 1 : 4 * NBB];
+    double yv[PRE ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < 4 * NBB; ++i) {
       const int j = min(cg + 4 * i, nb - 1);
       dv[i] = D[(int64_t)j * ldi + dr];
-      av[i] = D[(int64_t)j * ldi + arow];
+      if (!PRE) av[i] = D[(int64_t)j * ldi + arow0];
     }
     if (PRE) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t kk = cg + 4 * i - 64;
-        yv[i] = D[kk * ldi + dr];
-        xv[i] = D[kk * ldi + arow];
-      }
+      for (int i = 0; i < 16; ++i) yv[i] = D[(int64_t)(cg + 4 * i - 64) * ldi + dr];
     }
 #pragma unroll
     for (int i = 0; i < 4 * NBB; ++i) {
       const int j = cg + 4 * i;
       if (row < TR)
         T[row * TPn + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
-      sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
+      if (!PRE) sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
     }
-    if (PRE) {
+    if (PRE && row < TR) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int kk = cg + 4 * i;
-        if (row < TR) sY[kk * YP + row] = row < nb ? yv[i] : 0.0;
-        sX[kk * AP + row] = row < nr ? xv[i] : 0.0;
-      }
+      for (int i = 0; i < 16; ++i) sY[row * YP + cg + 4 * i] = row < nb ? yv[i] : 0.0;
     }
   }
   __syncthreads();
-  // group counter on a wave that does not start the pivot chain
-  if (tid == 192) {
-    const int old = atomicAdd(&counters[t.grp], 1);
-    const int last = (old == t.gcnt - 1);
-    if (last) atomicExch(&counters[t.grp], 0);
-    s_last = last;
-  }
   const int nbb = (nb + 15) >> 4;
   int bad = 0x7fffffff;
   int nfix = 0;
@@ -508,13 +556,34 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
     if (tid < 2) s_max[tid] = 0ull;
   }
   if (PRE) {
-    if (wave < nbb) pre_syrk16(T, TPn, sY, YP, wave, 0, lane);
+    // the previous block's update of column block 0 of the tile (one 16x16
+    // block per wave) while the first row tile and its X rows arrive
+    const int row = lane, cg = wave;
+    double av[4 * NBB], xv[16];
+    if (t.nrt > 0) {
+#pragma unroll
+      for (int i = 0; i < 4 * NBB; ++i) av[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + arow0];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv[i] = D[(int64_t)(cg + 4 * i - 64) * ldi + arow0];
+    }
+    if (wave < nbb) pre_syrk16(T, TPn, sY, wave, 0, lane);
+    if (t.nrt > 0) {
+#pragma unroll
+      for (int i = 0; i < 4 * NBB; ++i) {
+        const int j = cg + 4 * i;
+        sA[j * AP + row] = (row < nr && j < nb) ? av[i] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sX[row * YP + cg + 4 * i] = row < nr ? xv[i] : 0.0;
+    }
     __syncthreads();
   }
-  // row-tile jobs of the previous block's update: job j = (column block j/4,
-  // row block j%4), wave w (1..3) takes j = w-1, w+2, ... a few per round
-  const int njobs = (PRE && t.nrt > 0) ? 4 * nbb : 0;
-  int jdone = 0;
+  // row-tile work of the previous block's update: 2x2 groups of 16x16 blocks,
+  // g = (row blocks 2(g&1).., column blocks 2(g>>1)..); waves 1 and 2 take one
+  // each per pivot round from the second round on, the rest after the rounds
+  // (a 16-column tile image holds one column block)
+  const int ngrp = (PRE && t.nrt > 0) ? 2 * ((nbb + 1) >> 1) : 0;
+  auto grp = [&](int g) { pre_gemm2x2<(NBB > 1)>(sA, sX, sY, 2 * (g & 1), 2 * (g >> 1), lane); };
   for (int r = 0; r < nbb; ++r) {
     if (wave == 0) {
       bad = min(bad, panel16<(MODE >= 1)>(T, TPn, TR, Lc, 16 * r, nb, t.col, lane, cthr, crep,
@@ -531,26 +600,36 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
               if ((idx & 1) == wave - 1) syrk16(T, TPn, q, p, r - 1, lane);
         }
       }
-      if (PRE) {
-        if (r == 0) {
+      if (r == 0) {
+        // group counter, on a wave that does not carry the pivot chain
+        int old = 0;
+        if (tid == 192) old = atomicAdd(&counters[t.grp], 1);
+        if (PRE) {
           // the previous block's update of column blocks 1.. of the tile
           int idx = 0;
           for (int p = 1; p < nbb; ++p)
             for (int q = p; q < nbb; ++q, ++idx)
-              if (idx % 3 == wave - 1) pre_syrk16(T, TPn, sY, YP, q, p, lane);
+              if (idx % 3 == wave - 1) pre_syrk16(T, TPn, sY, q, p, lane);
         }
-        const int quota = r == nbb - 1 ? njobs : (r == 0 ? 2 : (wave == 3 ? r : 3));
-        for (int c = 0; c < quota; ++c) {
-          const int j = wave - 1 + 3 * jdone;
-          if (j >= njobs) break;
-          if (16 * (j & 3) < nr) pre_gemm16(sA, sX, sY, YP, j & 3, j >> 2, lane);
-          ++jdone;
+        if (tid == 192) {
+          const int last = (old == t.gcnt - 1);
+          if (last) atomicExch(&counters[t.grp], 0);
+          s_last = last;
         }
+      } else if (PRE && wave <= 2) {
+        const int g = 2 * (r - 1) + wave - 1;
+        if (g < ngrp) grp(g);
       }
     }
     __syncthreads();
     // column block r+1 from block r
     if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, TPn, r + 1 + wave, r + 1, r, lane);
+    __syncthreads();
+  }
+  if (PRE && 2 * (nbb - 1) < ngrp) {
+    // groups the rounds had no room for (single-round tiles)
+    if (wave == 1 || wave == 2)
+      for (int g = 2 * (nbb - 1) + wave - 1; g < ngrp; g += 2) grp(g);
     __syncthreads();
   }
   // the last base inverse (wave 3) alongside the first column blocks of the
@@ -596,12 +675,11 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
       }
       if (PRE) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sX[(cg + 4 * i) * AP + row] = row < nrt_rows ? xv[i] : 0.0;
+        for (int i = 0; i < 16; ++i) sX[row * YP + cg + 4 * i] = row < nrt_rows ? xv[i] : 0.0;
       }
       __syncthreads();
       if (PRE) {
-        for (int j = wave; j < 4 * nbb; j += 4)
-          if (16 * (j & 3) < nrt_rows) pre_gemm16(sA, sX, sY, YP, j & 3, j >> 2, lane);
+        for (int g = wave; g < ngrp; g += 4) grp(g);
         __syncthreads();
       }
     }

@@ -457,10 +457,12 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
                        t.nrt};
       tmp.insert(tmp.end(), v, v + 11);
     }
-  } else if (w == "launches") {  // kind, level, step, start, count, variant, pre, ustart, ucount
+  } else if (w == "launches") {
+    // kind, level, step, start, count, variant, pre, ustart, ucount, ncount
     for (const Launch& l : s.plan.launches) {
-      int64_t v[9] = {l.kind, l.level, l.step, l.start, l.count, l.variant, l.pre, l.ustart, l.ucount};
-      tmp.insert(tmp.end(), v, v + 9);
+      int64_t v[10] = {l.kind,  l.level, l.step,   l.start,  l.count,
+                       l.variant, l.pre, l.ustart, l.ucount, l.ncount};
+      tmp.insert(tmp.end(), v, v + 10);
     }
   }
   else return fail(RLB_ERR_ARG, "unknown array " + w);
@@ -858,6 +860,31 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
                : schedule == RLB_BATCH_SCHED_CENTERED ? gap / 2 : 0;
   }
   const std::vector<int64_t>& segbase = b->segbase;
+  // every matrix's launches in the unfused form: a panel launch that applies
+  // the previous block's update itself (and runs the rest of that step's
+  // update beside its workgroups) becomes that step's update launch followed
+  // by a plain panel launch -- one merged launch then holds the work of many
+  // matrices, more than one fused launch runs beside its panels
+  std::vector<std::vector<Launch>> lists(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const std::vector<Launch>& L = syms[i]->s.plan.launches;
+    for (size_t j = 0; j < L.size(); ++j) {
+      Launch l = L[j];
+      if (l.kind == LAUNCH_PANEL && l.pre) {
+        const bool first = j == 0 || L[j - 1].kind != LAUNCH_PANEL || L[j - 1].level != l.level ||
+                           L[j - 1].step != l.step;
+        for (size_t q = j; first && q < L.size() && L[q].kind == LAUNCH_PANEL &&
+                           L[q].level == l.level && L[q].step == l.step;
+             ++q)
+          if (L[q].ucount + L[q].ncount > 0)
+            lists[i].push_back(Launch{LAUNCH_UPDATE, l.level, l.step - 1, 1, L[q].ustart,
+                                      L[q].ucount + L[q].ncount, 0, 0, 0, 0, 0});
+        l.pre = 0;
+        l.ustart = l.ucount = l.ncount = 0;
+      }
+      lists[i].push_back(l);
+    }
+  }
   b->launches.clear();
   b->panels.clear();
   b->updates.clear();
@@ -869,7 +896,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
     bool any = false;
     int32_t bl = 0, bs = 0, bk = 0, bv = 0, bp = 0;
     for (int32_t i = 0; i < count; ++i) {
-      const auto& L = syms[i]->s.plan.launches;
+      const auto& L = lists[i];
       if (cur[i] >= L.size()) continue;
       const Launch& l = L[cur[i]];
       const int32_t lv = l.level + shift[i];
@@ -886,14 +913,14 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       }
     }
     if (!any) break;
-    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0, bp, 0, 0, 0};
+    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0, bp, 0, 0, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
     m.ustart = (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
       const Plan& p = syms[i]->s.plan;
-      if (cur[i] >= p.launches.size()) continue;
-      const Launch& l = p.launches[cur[i]];
+      if (cur[i] >= lists[i].size()) continue;
+      const Launch& l = lists[i][cur[i]];
       if (l.level + shift[i] != bl || l.step != bs || l.kind != bk) continue;
       if (bk == LAUNCH_PANEL && (l.variant != bv || l.pre != bp)) continue;
       if (bk == LAUNCH_UPDATE) m.variant &= l.variant;

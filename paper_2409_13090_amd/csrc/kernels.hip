@@ -447,9 +447,8 @@ struct PanelUpd<1> {
 };
 
 // resident workgroups per compute unit the register budget is sized for
-// (the FP64 form's fused update tiles need more registers than 3 per unit allow)
-constexpr int panel_occupancy(int mode, int nbb, bool pre) {
-  return pre ? (nbb == 1 && mode != 0 ? 2 : 1) : (nbb == 1 ? (mode == 0 ? 2 : 3) : (nbb == 2 ? 2 : 1));
+constexpr int panel_occupancy(int nbb, bool pre) {
+  return pre ? (nbb == 1 ? 2 : 1) : (nbb == 1 ? 3 : (nbb == 2 ? 2 : 1));
 }
 
 // MODE 0: FP64 form. MODE 1: reduced-precision updates (pivot patching).
@@ -466,12 +465,12 @@ constexpr int panel_occupancy(int mode, int nbb, bool pre) {
 // the left). Column block 0 of T is updated by all waves before the first
 // pivot round, the other column blocks and the row tile by waves 1-3 while
 // wave 0 factors.
-// Workgroups blockIdx.x >= npanel (MODE 0 and 1) each run one tile of utiles:
+// Workgroups blockIdx.x >= npanel (MODE 0 and 1, NBB 4) each run one tile of utiles:
 // the rest of that previous block's trailing update (single-contribution
 // tiles, k <= 64) in the update precision of the form; those tiles lie right
 // of this column block, so the two kinds of work touch disjoint entries.
 template <int MODE, int NBB, bool PRE>
-__global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
+__global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     const PanelTile* __restrict__ tiles, double* __restrict__ L, int* __restrict__ status,
     int* __restrict__ counters, const double* __restrict__ thr,
     const unsigned long long* __restrict__ amax, double ufix, unsigned long long* __restrict__ smax,
@@ -488,12 +487,13 @@ __global__ __launch_bounds__(256, panel_occupancy(MODE, NBB, PRE)) void k_panel(
   constexpr int O_Y = O_LC + 16 * 64;
   constexpr int O_X = O_Y + (PRE ? TR * YP : 0);
   constexpr int N_PANEL = O_X + (PRE ? 64 * YP : 0);
-  constexpr int N_UPD = MODE == 2 ? 0 : 4 * KC * 64 * (int)sizeof(typename PanelUpd<MODE>::type) / 8;
+  constexpr bool UROLE = MODE != 2 && NBB == 4;  // launches that carry update tiles
+  constexpr int N_UPD = UROLE ? 4 * KC * 64 * (int)sizeof(typename PanelUpd<MODE>::type) / 8 : 0;
   constexpr int N_LDS = N_PANEL > N_UPD ? N_PANEL : N_UPD;
   __shared__ double smem[N_LDS];
   __shared__ int s_last;
   __shared__ unsigned long long s_max[2];
-  if (MODE != 2 && (int)blockIdx.x >= npanel) {
+  if (UROLE && (int)blockIdx.x >= npanel) {
     typedef typename PanelUpd<MODE>::type UT;
     UT* su = reinterpret_cast<UT*>(smem);
     const UpdTile ut = utiles[blockIdx.x - npanel];
@@ -1559,7 +1559,7 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
                   int64_t ucount, hipStream_t st) {
   if (count <= 0) return;
-  if (precision == 2) ucount = 0;
+  if (precision == 2 || nbb < 4) ucount = 0;  // (the plan fuses into 64-column launches only)
 #define RLB_PANEL_N(N, P)                                                                       \
   launch_panel_n<N, P>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed, \
                        utiles, usegs, ucount, st)

@@ -213,38 +213,45 @@ int build_plan(Symbolic& s, std::string& err) {
 
   // launches
   p.flops_tiles = 0;
-  // places a step's update work: every tile (or every tile not marked next)
-  // goes to p.updates, heaviest workgroups first; into a launch of its own,
-  // or as the fused part of panel launch `fused_into`
-  auto commit = [&](const PendingUpdate& u, bool skip_next, int64_t fused_into) {
+  // places a step's update work in p.updates, heaviest workgroups first: into
+  // a launch of its own, or as the fused part of panel launch `fused_into`
+  // (the tiles not marked next, followed by the next ones, which that
+  // launch's panels apply themselves and which stay listed for the unfused
+  // form)
+  auto commit = [&](const PendingUpdate& u, int64_t fused_into) {
     const int64_t start = (int64_t)p.updates.size();
-    std::vector<std::pair<int64_t, size_t>> order;
-    for (size_t i = 0; i < u.tiles.size(); ++i) {
-      if (skip_next && u.next[i]) continue;
-      int64_t ch = 0;
-      for (int32_t e = 0; e < u.tiles[i].nseg; ++e)
-        ch += (u.segs[u.tiles[i].seg0 + e].k + KCH - 1) / KCH;
-      order.push_back({-ch, i});
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<int64_t, size_t>& x, const std::pair<int64_t, size_t>& y) {
-                       return x.first < y.first;
-                     });
     bool shortk = true;
-    for (auto& o : order) {
-      UpdTile t = u.tiles[o.second];
-      const int32_t s0 = t.seg0;
-      t.seg0 = (int32_t)p.segs.size();
-      for (int32_t e = 0; e < t.nseg; ++e) p.segs.push_back(u.segs[s0 + e]);
-      if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || u.segs[s0].k > 64) shortk = false;
-      p.updates.push_back(t);
+    int64_t counts[2] = {0, 0};
+    for (int part = 0; part < 2; ++part) {
+      if (part == 1 && fused_into < 0) break;
+      std::vector<std::pair<int64_t, size_t>> order;
+      for (size_t i = 0; i < u.tiles.size(); ++i) {
+        if (fused_into >= 0 && (u.next[i] != 0) != (part == 1)) continue;
+        int64_t ch = 0;
+        for (int32_t e = 0; e < u.tiles[i].nseg; ++e)
+          ch += (u.segs[u.tiles[i].seg0 + e].k + KCH - 1) / KCH;
+        order.push_back({-ch, i});
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [](const std::pair<int64_t, size_t>& x, const std::pair<int64_t, size_t>& y) {
+                         return x.first < y.first;
+                       });
+      for (auto& o : order) {
+        UpdTile t = u.tiles[o.second];
+        const int32_t s0 = t.seg0;
+        t.seg0 = (int32_t)p.segs.size();
+        for (int32_t e = 0; e < t.nseg; ++e) p.segs.push_back(u.segs[s0 + e]);
+        if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || u.segs[s0].k > 64) shortk = false;
+        p.updates.push_back(t);
+      }
+      counts[part] = (int64_t)order.size();
     }
-    const int64_t count = (int64_t)p.updates.size() - start;
     if (fused_into >= 0) {
       p.launches[fused_into].ustart = start;
-      p.launches[fused_into].ucount = count;
-    } else if (count) {
-      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, count, 0, 0, 0, 0};
+      p.launches[fused_into].ucount = counts[0];
+      p.launches[fused_into].ncount = counts[1];
+    } else if (counts[0]) {
+      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, counts[0], 0, 0, 0, 0, 0};
       p.launches.push_back(lu);
     }
   };
@@ -323,9 +330,9 @@ int build_plan(Symbolic& s, std::string& err) {
         }
       // the previous step's update: its trailing tiles of this column block
       // go into this step's panel workgroups (pre-update) and the rest runs
-      // as extra workgroups of this step's widest panel launch, when the rest
-      // is all short single-contribution tiles few enough to run beside the
-      // panel workgroups; otherwise it keeps a launch of its own, before
+      // as extra workgroups of this step's 64-column panel launch, when the
+      // rest is all short single-contribution tiles few enough to run beside
+      // the panel workgroups; otherwise it keeps a launch of its own, before
       // this step's panels
       bool fuse = false;
       if (pend.valid) {
@@ -339,21 +346,23 @@ int build_plan(Symbolic& s, std::string& err) {
             short_rest = false;
         }
         for (int ci = 0; ci < 3; ++ci) npw += (int64_t)cls[ci].size();
-        fuse = short_rest && rest <= FUSE_TILES_PER_CU * std::max<int64_t>(0, DEVICE_CUS - npw);
-        if (!fuse) commit(pend, false, -1);
+        // (the update tiles ride on the 64-column class launch)
+        fuse = short_rest && !cls[2].empty() &&
+               rest <= FUSE_TILES_PER_CU * std::max<int64_t>(0, DEVICE_CUS - npw);
+        if (!fuse) commit(pend, -1);
       }
       const int32_t cls_nbb[3] = {1, 2, 4};
       int64_t widest = -1;
       for (int ci = 0; ci < 3; ++ci) {
         if (cls[ci].empty()) continue;
         Launch lp{LAUNCH_PANEL, h, (int32_t)k, cls_nbb[ci], (int64_t)p.panels.size(),
-                  (int64_t)cls[ci].size(), fuse ? 1 : 0, 0, 0, 0};
+                  (int64_t)cls[ci].size(), fuse ? 1 : 0, 0, 0, 0, 0};
         p.panels.insert(p.panels.end(), cls[ci].begin(), cls[ci].end());
         widest = (int64_t)p.launches.size();
         p.launches.push_back(lp);
         p.max_groups = std::max(p.max_groups, ngroups[ci]);
       }
-      if (fuse) commit(pend, true, widest);
+      if (fuse) commit(pend, widest);
       // UPDATE work of step k: trailing updates of its block, and the
       // ancestor updates of supernodes whose last block it is; one target
       // tile per workgroup with all its contributions
@@ -486,7 +495,7 @@ int build_plan(Symbolic& s, std::string& err) {
         }
       }
     }
-    if (pend.valid) commit(pend, false, -1);
+    if (pend.valid) commit(pend, -1);
   }
   // diagonal tiles of every 64-column step, inverted after the factorization,
   // grouped by width class

@@ -121,7 +121,8 @@ struct Launch {
   int32_t pre;    // panel: its tiles first apply the previous block's trailing update
   int32_t pad;
   int64_t ustart; // panel: update tiles of the previous step run in the same launch
-  int64_t ucount; //   (single-contribution tiles, k <= 64)
+  int64_t ucount; //   (single-contribution tiles, k <= 64); the ncount tiles after
+  int64_t ncount; //   them are the ones pre applies (kept for the unfused form)
 };
 
 struct Plan {

@@ -17,7 +17,28 @@ from paper_2409_13090_amd import rlb
 from paper_2409_13090_amd import workloads as W
 
 
-def replay_factor(A, **kw):
+def unfused(launches):
+    """The launch list with every fused panel step expanded into the previous
+    step's update launch (the tiles beside the panels and the ones the panels
+    apply themselves) followed by plain panel launches, as the batch runs it."""
+    out, done = [], set()
+    for j, l in enumerate(launches):
+        kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt = (int(v) for v in l)
+        if kind == 0 and pre:
+            if (lev, step) not in done:
+                done.add((lev, step))
+                for q in launches[j:]:
+                    if int(q[0]) != 0 or int(q[1]) != lev or int(q[2]) != step:
+                        break
+                    if int(q[8]) + int(q[9]) > 0:
+                        out.append((1, lev, step - 1, int(q[7]), int(q[8]) + int(q[9]), 1, 0, 0, 0, 0))
+            out.append((kind, lev, step, st, cnt, variant, 0, 0, 0, 0))
+        else:
+            out.append((kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt))
+    return out
+
+
+def replay_factor(A, expand=False, **kw):
     s = rlb.Symbolic.from_matrix(A, **kw)
     size = s.info()["factor_bytes"] // 8
     Lb = np.zeros(size)
@@ -54,7 +75,10 @@ def replay_factor(A, **kw):
                 Lb[c + j * ldc: c + j * ldc + m] -= col
         return reads, set(owner)
 
-    for kind, lev, step, st, cnt, variant, pre, ust, ucnt in s.array("launches").reshape(-1, 9):
+    launches = s.array("launches").reshape(-1, 10)
+    if expand:
+        launches = unfused(launches)
+    for kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt in launches:
         if kind == 0:
             groups = {}
             for t in P[st:st + cnt]:
@@ -188,6 +212,9 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     o, f = oracle_factor(A)
     err = compare_factor(export(s, Lb), f, A.n)
     assert err <= 1e-12
+    # the unfused form (the batch's) reaches the same factor
+    s2, Lb2 = replay_factor(A, expand=True, **kw)
+    assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
     B = np.random.default_rng(0).standard_normal((A.n, 3))
     X = replay_solve(s, Lb, B)
     Af = A.to_scipy_full()

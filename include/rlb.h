@@ -93,6 +93,8 @@ typedef struct rlb_info {
   double flops_upd_alg;  /* algorithmic flops of the updates: 2 * inner dimension *
                             entries written, summed over contributions */
   double flops_panel;    /* flops of the panel (POTRF + TRSM) steps */
+  double flops_upd_launch; /* the part of flops_upd_alg run by update launches of their
+                              own (the rest runs inside panel launches) */
 } rlb_info;
 
 typedef struct rlb_symbolic_s* rlb_symbolic;

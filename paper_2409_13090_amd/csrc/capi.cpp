@@ -394,6 +394,7 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* o) {
   o->flops_tiles = s.plan.flops_tiles;
   o->flops_upd_alg = s.plan.flops_upd_alg;
   o->flops_panel = s.plan.flops_panel;
+  o->flops_upd_launch = s.plan.flops_upd_launch;
   return RLB_OK;
 }
 

@@ -55,6 +55,7 @@ struct PendingUpdate {
   std::vector<UpdTile> tiles;               // seg0 relative to `segs`
   std::vector<UpdSeg> segs;
   std::vector<char> next;
+  std::vector<double> alg;                  // algorithmic flops of each tile
 };
 
 // One rectangle of the ancestor update: target rows [r0, r0+mr) and columns
@@ -242,6 +243,7 @@ int build_plan(Symbolic& s, std::string& err) {
         t.seg0 = (int32_t)p.segs.size();
         for (int32_t e = 0; e < t.nseg; ++e) p.segs.push_back(u.segs[s0 + e]);
         if (t.nseg != 1 || (t.flags & FLAG_ATOMIC) || u.segs[s0].k > 64) shortk = false;
+        if (fused_into < 0) p.flops_upd_launch += u.alg[o.second];
         p.updates.push_back(t);
       }
       counts[part] = (int64_t)order.size();
@@ -375,8 +377,13 @@ int build_plan(Symbolic& s, std::string& err) {
         t.seg0 = (int32_t)pend.segs.size();
         t.nseg = (int32_t)(g1 - g0);
         pend.segs.insert(pend.segs.end(), gs.begin() + g0, gs.begin() + g1);
+        double alg = 0;
+        for (size_t i = g0; i < g1; ++i)
+          alg += 2.0 * (double)gs[i].k *
+                 seg_entries(gs[i].ra, gs[i].rb, gs[i].ca, gs[i].cb, (t.flags & FLAG_DIAG) != 0);
         pend.tiles.push_back(t);
         pend.next.push_back(next ? 1 : 0);
+        pend.alg.push_back(alg);
       };
       std::vector<int64_t> finished;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {

@@ -154,6 +154,7 @@ struct Plan {
   double flops_tiles = 0;  // flops the update tiles execute (the 16x16 MFMA blocks they touch)
   double flops_upd_alg = 0;  // algorithmic flops of the update tiles (entries written x 2k)
   double flops_panel = 0;    // flops of the POTRF + TRSM column blocks
+  double flops_upd_launch = 0;  // flops_upd_alg of the tiles run by update launches of their own
 };
 
 struct Symbolic {

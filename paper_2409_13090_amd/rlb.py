@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
                  "n_panel_tiles", "n_update_tiles", "n_merged_tiles", "n_split_tiles",
                  "n_launches")] + [
                 ("flops_tiles", ctypes.c_double), ("flops_upd_alg", ctypes.c_double),
-                ("flops_panel", ctypes.c_double)]
+                ("flops_panel", ctypes.c_double), ("flops_upd_launch", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -215,6 +215,22 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     # the unfused form (the batch's) reaches the same factor
     s2, Lb2 = replay_factor(A, expand=True, **kw)
     assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
+    # algorithmic flops of the tiles of update launches of their own, from the
+    # exported lists (entries written, lower part only on diagonal tiles)
+    U = s.array("update_tiles").reshape(-1, 7)
+    G = s.array("update_segs").reshape(-1, 9)
+    fl = 0.0
+    for l in s.array("launches").reshape(-1, 10):
+        if l[0] != 1:
+            continue
+        for c, ldc, m, n, flags, seg0, nseg in U[l[3]:l[3] + l[4]]:
+            for x, y, lds, k, ra, rb, ca, cb, src in G[seg0:seg0 + nseg]:
+                ent = sum(max(0, rb - max(ra, j)) for j in range(ca, cb)) if flags & 1 \
+                    else (rb - ra) * (cb - ca)
+                fl += 2.0 * k * ent
+    info = s.info()
+    assert fl == pytest.approx(info["flops_upd_launch"], rel=1e-12)
+    assert info["flops_upd_launch"] <= info["flops_upd_alg"] * (1 + 1e-12)
     B = np.random.default_rng(0).standard_normal((A.n, 3))
     X = replay_solve(s, Lb, B)
     Af = A.to_scipy_full()

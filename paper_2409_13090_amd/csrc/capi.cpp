@@ -54,6 +54,7 @@ struct DevPlan {
   UpdTile* updates = nullptr;
   UpdSeg* segs = nullptr;
   DiagTile* dtiles = nullptr;
+  DiagTile* ptiles = nullptr;
   int64_t* amap = nullptr;
   SolveTile* stiles = nullptr;
   int32_t* gl = nullptr;
@@ -66,6 +67,7 @@ struct DevPlan {
     dfree(updates);
     dfree(segs);
     dfree(dtiles);
+    dfree(ptiles);
     dfree(amap);
     dfree(stiles);
     dfree(gl);
@@ -259,6 +261,8 @@ struct rlb_batch_s {
   std::vector<DiagTile> dtiles;  // by width class, as in a plan
   int64_t dt_ptr[4] = {0, 0, 0, 0};
   DiagTile* d_dtiles = nullptr;
+  std::vector<DiagTile> ptiles;
+  DiagTile* d_ptiles = nullptr;
   PanelTile* d_panels = nullptr;
   UpdTile* d_updates = nullptr;
   UpdSeg* d_segs = nullptr;
@@ -286,6 +290,7 @@ struct rlb_batch_s {
     dfree(d_updates);
     dfree(d_segs);
     dfree(d_dtiles);
+    dfree(d_ptiles);
     dfree(d_amap);
     dfree(d_nnz_ptr);
     if (d_vals) (void)hipFree((void*)d_vals);
@@ -499,6 +504,7 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if ((st = upload(&h->d.updates, s.plan.updates))) return st;
   if ((st = upload(&h->d.segs, s.plan.segs))) return st;
   if ((st = upload(&h->d.dtiles, s.plan.dtiles))) return st;
+  if ((st = upload(&h->d.ptiles, s.plan.ptiles))) return st;
   if ((st = upload(&h->d.amap, s.plan.amap))) return st;
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
@@ -552,6 +558,7 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   for (int ci = 0; ci < 3; ++ci)
     launch_tile_inverse(h->d.dtiles + p.dt_ptr[ci], p.dt_ptr[ci + 1] - p.dt_ptr[ci], cls_nbb[ci],
                         L, st);
+  launch_pair_inverse(h->d.ptiles, (int64_t)p.ptiles.size(), L, st);
 }
 
 rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size_t ws_bytes,
@@ -1032,6 +1039,12 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
   }
   b->dt_ptr[3] = (int64_t)b->dtiles.size();
   if ((st = upload(&b->d_dtiles, b->dtiles))) return st;
+  for (int32_t i = 0; i < count; ++i)
+    for (DiagTile d : syms[i]->s.plan.ptiles) {
+      d.diag += b->base[i];
+      b->ptiles.push_back(d);
+    }
+  if ((st = upload(&b->d_ptiles, b->ptiles))) return st;
   if ((st = upload(&b->d_amap, amap))) return st;
   if ((st = upload(&b->d_nnz_ptr, b->nnz_ptr))) return st;
   HIP_OK(hipMalloc((void**)&b->d_vals, sizeof(double*) * count));
@@ -1070,6 +1083,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (int ci = 0; ci < 3; ++ci)
     launch_tile_inverse(b->d_dtiles + b->dt_ptr[ci], b->dt_ptr[ci + 1] - b->dt_ptr[ci],
                         cls_nbb[ci], L, st);
+  launch_pair_inverse(b->d_ptiles, (int64_t)b->ptiles.size(), L, st);
 }
 
 rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* workspace,

@@ -35,6 +35,9 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
                    int precision, const unsigned long long* smax, bool shortk, hipStream_t st);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
+// the off-diagonal inverse blocks of the two-chunk solve steps (after
+// launch_tile_inverse)
+void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st);
 void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
                    unsigned long long* amax, hipStream_t st);
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,

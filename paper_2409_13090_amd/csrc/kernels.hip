@@ -14,6 +14,7 @@
 //    steps, the diagonal chunks as products with the stored inv(L_kk).
 //  * SpMV residual, norms.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include <algorithm>
@@ -1230,9 +1231,117 @@ __device__ __forceinline__ void stage_inv(double* V, const double* Lj, int64_t l
   }
 }
 
-// forward step: x_k = inv(L_kk) y_k (stored into z by the writer), then
-// y(rows r0..r1 of the supernode) -= L(rows, chunk) x_k, one row per thread;
-// own rows plainly, ancestor rows (through glbind) with atomics
+// W[i*VP + j] = inv(L)(c0+64+i, c0+j): the off-diagonal block of the inverse
+// of a two-chunk step's diagonal block, stored transposed in its unused upper
+// block (row c0+j, column c0+64+i), zero outside nbB x 64
+__device__ __forceinline__ void stage_w(double* W, const double* Lj, int64_t ld, int c0, int nbB,
+                                        int tid) {
+  const int row = tid & 63, cg = tid >> 6;
+  const int ii = min(row, nbB - 1);
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = Lj[(int64_t)(c0 + 64 + ii) * ld + c0 + cg + 4 * q];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) W[row * VP + cg + 4 * q] = row < nbB ? v[q] : 0.0;
+}
+
+// After the factorization (and k_tile_inverse), for every two-chunk solve
+// step with a second chunk (64 < nb <= 128): the off-diagonal block of the
+// inverse of its diagonal block, W = -inv(L_BB) L_BA inv(L_AA), into the
+// step's unused upper block (W(i, j) at row c0+j, column c0+64+i). Two LDS
+// blocks: L_BA and inv(L_AA) for the first product, then inv(L_BB) (held in
+// registers until then) and M = L_BA inv(L_AA) for the second.
+__global__ __launch_bounds__(256) void k_pair_inverse(const DiagTile* __restrict__ tiles,
+                                                      double* __restrict__ L) {
+  const DiagTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int64_t ld = t.ld;
+  double* D = L + t.diag;  // (c0, c0)
+  const int nbB = t.nb - 64;
+  __shared__ double V0[64 * VP];  // inv(L_AA), then M
+  __shared__ double B[64 * VP];   // L_BA, then inv(L_BB)
+  const int row = tid & 63, cg = tid >> 6;
+  const int rr = min(row, nbB - 1);
+  double v1[16];  // this thread's entries of inv(L_BB), as stage_inv reads them
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int col = min(cg + 4 * q, nbB - 1);
+    v1[q] = D[(int64_t)(64 + col) * ld + 64 + rr];
+  }
+  stage_inv(V0, D, ld, 0, 64, tid);
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = D[(int64_t)(cg + 4 * q) * ld + 64 + rr];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) B[row * VP + cg + 4 * q] = row < nbB ? v[q] : 0.0;
+  }
+  __syncthreads();
+  // two 64x64 products, each thread a 4x4 block of outputs: M = L_BA
+  // inv(L_AA) (kept in registers until V0 may be overwritten), then W =
+  // -inv(L_BB) M
+  const int ti = tid >> 4, tj = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < 64; ++k) {
+    double bv[4], vv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[r] = B[(4 * ti + r) * VP + k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vv[c] = V0[k * VP + 4 * tj + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] += bv[r] * vv[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      V0[(4 * ti + r) * VP + 4 * tj + c] = acc[r][c];
+      acc[r][c] = 0.0;
+    }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {  // inv(L_BB) as stage_inv lays it out
+    const int col = cg + 4 * q;
+    double e = 0.0;
+    if (row < nbB && col < nbB) e = row < col ? v1[q] : (row == col ? 1.0 / v1[q] : 0.0);
+    B[col * VP + row] = e;
+  }
+  __syncthreads();
+  const int kend = min(4 * ti + 4, nbB);  // inv(L_BB) is 0 above the diagonal
+  for (int k = 0; k < kend; ++k) {
+    double bv[4], vv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[r] = B[(4 * ti + r) * VP + k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vv[c] = V0[k * VP + 4 * tj + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] += bv[r] * vv[c];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (4 * ti + r < nbB)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) D[(int64_t)(64 + 4 * ti + r) * ld + 4 * tj + c] = -acc[r][c];
+}
+
+// forward step over one or two 64-column chunks of a supernode (nb <= 128),
+// split by chunk over the workgroups (flags bit 1: the second chunk). With
+// inv(L_DD) = [V0 0; W V1] (the stored inverses of the chunks' diagonal
+// tiles and the off-diagonal block formed after the factorization), a
+// workgroup of the first chunk forms x_A = V0 y_A, one of the second x_B =
+// W y_A + V1 y_B, redundantly (x stored into z by the half's writer, flags
+// bit 0), then y(rows r0..r1 of the supernode) -= L(rows, its chunk) x_chunk,
+// one row per thread; plainly for own rows of a one-chunk step, else with
+// atomics (the other chunk's workgroups and other supernodes add too)
 __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ gl,
                                                   const double* __restrict__ L,
@@ -1242,18 +1351,25 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
   const int tid = threadIdx.x;
   const double* Lj = L + t.off;
   const int64_t ld = t.ld;
-  __shared__ double V[64 * VP];
-  __shared__ double ys[MAXRHS][64];
+  const int nbA = min(t.nb, 64), nbB = t.nb - nbA;
+  const int half = (t.flags >> 1) & 1;
+  const int cc = t.c0 + 64 * half;          // first column of this workgroup's chunk
+  const int nbc = half ? nbB : nbA;         // its width
+  __shared__ double V0[64 * VP];  // this chunk's inverse
+  __shared__ double W[64 * VP];   // second chunk: the off-diagonal inverse block
+  __shared__ double ys[MAXRHS][128];
   __shared__ double xs[MAXRHS][64];
   // this thread's row of the GEMV: all 64 loads issued before the chunk solve
   const int q = t.r0 + tid;
   const int qq = min(q, t.ld - 1);
+  const int gq = gl[t.gl + min(q, t.r1 - 1)];
   double l[64];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) l[c] = Lj[(int64_t)(t.c0 + min(c, t.nb - 1)) * ld + qq];
-  stage_inv(V, Lj, ld, t.c0, t.nb, tid);
-  for (int e = tid; e < 64 * nrhs; e += 256) {
-    const int i = e & 63, r = e >> 6;
+  for (int c = 0; c < 64; ++c) l[c] = Lj[(int64_t)(cc + min(c, nbc - 1)) * ld + qq];
+  stage_inv(V0, Lj, ld, cc, nbc, tid);
+  if (half) stage_w(W, Lj, ld, t.c0, nbB, tid);
+  for (int e = tid; e < 128 * nrhs; e += 256) {
+    const int i = e & 127, r = e >> 7;
     ys[r][i] = i < t.nb ? y[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
   }
   __syncthreads();
@@ -1262,8 +1378,15 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll 8
     for (int j = 0; j < 64; j += 2) {
-      a0 += V[i * VP + j] * ys[r][j];
-      a1 += V[i * VP + j + 1] * ys[r][j + 1];
+      a0 += V0[i * VP + j] * ys[r][64 * half + j];
+      a1 += V0[i * VP + j + 1] * ys[r][64 * half + j + 1];
+    }
+    if (half) {
+#pragma unroll 8
+      for (int j = 0; j < 64; j += 2) {
+        a0 += W[i * VP + j] * ys[r][j];
+        a1 += W[i * VP + j + 1] * ys[r][j + 1];
+      }
     }
     xs[r][i] = a0 + a1;
   }
@@ -1271,19 +1394,18 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
   if (t.flags & 1)
     for (int e = tid; e < 64 * nrhs; e += 256) {
       const int i = e & 63, r = e >> 6;
-      if (i < t.nb) z[(int64_t)r * ldy + t.f + t.c0 + i] = xs[r][i];
+      if (i < nbc) z[(int64_t)r * ldy + t.f + cc + i] = xs[r][i];
     }
   if (q < t.r1) {
-    const int gq = gl[t.gl + q];
     for (int r = 0; r < nrhs; ++r) {
       double a0 = 0.0, a1 = 0.0;
 #pragma unroll
       for (int c = 0; c < 64; c += 2) {
-        a0 += l[c] * xs[r][c];  // xs is 0 beyond nb
+        a0 += l[c] * xs[r][c];  // xs is 0 beyond the chunk
         a1 += l[c + 1] * xs[r][c + 1];
       }
       const double acc = a0 + a1;
-      if (q < t.w)
+      if (q < t.w && nbB == 0)
         y[(int64_t)r * ldy + gq] -= acc;
       else
         atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
@@ -1352,8 +1474,13 @@ __global__ __launch_bounds__(256) void k_bwd_below(const SolveTile* __restrict__
   }
 }
 
-// backward step: x_k = inv(L_kk)^T z_k (stored into x by the writer), then
-// z(columns r0..r1) -= L(chunk rows, r0..r1)^T x_k for one earlier chunk
+// backward step over one or two 64-column chunks (nb <= 128), split by
+// chunk over the workgroups (flags bit 1: the second chunk): with
+// inv(L_DD)^T = [V0^T W^T; 0 V1^T], a workgroup of the first chunk forms x_A
+// = V0^T z_A + W^T z_B, one of the second x_B = V1^T z_B, redundantly (x
+// stored by the half's writer, flags bit 0), then z(columns r0..r1) -=
+// L(its chunk's rows, r0..r1)^T x_chunk for one earlier 64-column chunk,
+// with atomics when the step has two chunks
 __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ tiles,
                                                   const double* __restrict__ L,
                                                   double* __restrict__ z, double* __restrict__ x,
@@ -1363,21 +1490,27 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
   const double* Lj = L + t.off;
   const int64_t ld = t.ld;
   const bool push = t.r1 > t.r0;
+  const int nbA = min(t.nb, 64), nbB = t.nb - nbA;
+  const int half = (t.flags >> 1) & 1;
+  const int cc = t.c0 + 64 * half;
+  const int nbc = half ? nbB : nbA;
   __shared__ double V[64 * VP];
-  __shared__ double Lb[64][VP];  // Lb[i][c] = L(c0 + i, r0 + c)
-  __shared__ double zs[MAXRHS][64];
+  __shared__ double W[64 * VP];  // first chunk of a two-chunk step: the off-diagonal block
+  __shared__ double Lb[64][VP];  // Lb[i][c] = L(cc + i, r0 + c)
+  __shared__ double zs[MAXRHS][128];
   __shared__ double xs[MAXRHS][64];
   if (push) {
     double v[16];
-    const int ii = min(row, t.nb - 1);
+    const int ii = min(row, nbc - 1);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) v[s] = Lj[(int64_t)(t.r0 + cg + 4 * s) * ld + t.c0 + ii];
+    for (int s = 0; s < 16; ++s) v[s] = Lj[(int64_t)(t.r0 + cg + 4 * s) * ld + cc + ii];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) Lb[row][cg + 4 * s] = row < t.nb ? v[s] : 0.0;
+    for (int s = 0; s < 16; ++s) Lb[row][cg + 4 * s] = row < nbc ? v[s] : 0.0;
   }
-  stage_inv(V, Lj, ld, t.c0, t.nb, tid);
-  for (int e = tid; e < 64 * nrhs; e += 256) {
-    const int i = e & 63, r = e >> 6;
+  stage_inv(V, Lj, ld, cc, nbc, tid);
+  if (!half && nbB > 0) stage_w(W, Lj, ld, t.c0, nbB, tid);
+  for (int e = tid; e < 128 * nrhs; e += 256) {
+    const int i = e & 127, r = e >> 7;
     zs[r][i] = i < t.nb ? z[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
   }
   __syncthreads();
@@ -1386,8 +1519,15 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll 8
     for (int m = 0; m < 64; m += 2) {
-      a0 += V[m * VP + i] * zs[r][m];
-      a1 += V[(m + 1) * VP + i] * zs[r][m + 1];
+      a0 += V[m * VP + i] * zs[r][64 * half + m];
+      a1 += V[(m + 1) * VP + i] * zs[r][64 * half + m + 1];
+    }
+    if (!half && nbB > 0) {
+#pragma unroll 8
+      for (int m = 0; m < 64; m += 2) {
+        a0 += W[m * VP + i] * zs[r][64 + m];
+        a1 += W[(m + 1) * VP + i] * zs[r][64 + m + 1];
+      }
     }
     xs[r][i] = a0 + a1;
   }
@@ -1395,7 +1535,7 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
   if (t.flags & 1)
     for (int e = tid; e < 64 * nrhs; e += 256) {
       const int i = e & 63, r = e >> 6;
-      if (i < t.nb) x[(int64_t)r * ldy + t.f + t.c0 + i] = xs[r][i];
+      if (i < nbc) x[(int64_t)r * ldy + t.f + cc + i] = xs[r][i];
     }
   if (push)
     for (int e = tid; e < 64 * nrhs; e += 256) {
@@ -1406,7 +1546,11 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
         a0 += Lb[i][c] * xs[r][i];
         a1 += Lb[i + 1][c] * xs[r][i + 1];
       }
-      z[(int64_t)r * ldy + t.f + t.r0 + c] -= a0 + a1;
+      double* p = &z[(int64_t)r * ldy + t.f + t.r0 + c];
+      if (nbB > 0)
+        atomicAdd(p, -(a0 + a1));
+      else
+        *p -= a0 + a1;
     }
 }
 
@@ -1620,6 +1764,10 @@ void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u,
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pivthr, dim3(grid_for(n, 256, INT32_MAX)), dim3(256), 0, st, vals, dsrc,
                      n, u, thr, amax);
+}
+void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_pair_inverse, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
 }
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                      double* y, double* z, int nrhs, int64_t ldy, hipStream_t st) {

@@ -516,11 +516,19 @@ int build_plan(Symbolic& s, std::string& err) {
       }
   }
   p.dt_ptr[3] = (int64_t)p.dtiles.size();
-  // solves: forward by level and 64-column step (row tiles of 256 below the
-  // chunk), backward by level from the root: first every column chunk against
-  // the ancestor rows (segments of 512 rows), then the steps from the last
-  // chunk down, each pushing into the earlier chunks of its supernode
+  // diagonal blocks of the two-chunk solve steps that have a second chunk
+  for (int64_t J = 0; J < S; ++J)
+    for (int64_t c0 = 0; c0 < W(J); c0 += 2 * NB) {
+      int64_t nb = std::min<int64_t>(2 * NB, W(J) - c0);
+      if (nb > NB) p.ptiles.push_back(DiagTile{p.off[J] + c0 * M(J) + c0, (int32_t)M(J), (int32_t)nb});
+    }
+  // solves: forward by level and step of two 64-column chunks (row tiles of
+  // 256 below them, for each chunk), backward by level from the root: first
+  // every 64-column chunk against the ancestor rows (segments of 512 rows),
+  // then the steps of two chunks from the last down, each chunk pushing into
+  // the earlier 64-column chunks of its supernode
   {
+    constexpr int64_t SB = 2 * NB;  // columns of a solve step
     auto base_tile = [&](int64_t J) {
       SolveTile t;
       t.off = p.off[J];
@@ -538,23 +546,24 @@ int build_plan(Symbolic& s, std::string& err) {
     for (int32_t h = 0; h < p.nlevels; ++h) {
       int64_t steps = 0;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
-        steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + NB - 1) / NB);
+        steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + SB - 1) / SB);
       for (int64_t k = 0; k < steps; ++k) {
         int64_t start = (int64_t)p.stiles.size();
         for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
           int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
-          if (k * NB >= w) continue;
+          if (k * SB >= w) continue;
           SolveTile t = base_tile(J);
-          t.c0 = (int32_t)(k * NB);
-          t.nb = (int32_t)std::min<int64_t>(NB, w - k * NB);
+          t.c0 = (int32_t)(k * SB);
+          t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
           int64_t lo = t.c0 + t.nb;
           int64_t nt = std::max<int64_t>(1, (m - lo + 255) / 256);
-          for (int64_t i = 0; i < nt; ++i) {
-            t.r0 = (int32_t)std::min<int64_t>(m, lo + 256 * i);
-            t.r1 = (int32_t)std::min<int64_t>(m, lo + 256 * (i + 1));
-            t.flags = i == 0 ? 1 : 0;
-            p.stiles.push_back(t);
-          }
+          for (int32_t half = 0; half < (t.nb > NB ? 2 : 1); ++half)
+            for (int64_t i = 0; i < nt; ++i) {
+              t.r0 = (int32_t)std::min<int64_t>(m, lo + 256 * i);
+              t.r1 = (int32_t)std::min<int64_t>(m, lo + 256 * (i + 1));
+              t.flags = (i == 0 ? 1 : 0) | (half << 1);
+              p.stiles.push_back(t);
+            }
         }
         push_launch(SOLVE_FWD, h, start);
       }
@@ -564,7 +573,7 @@ int build_plan(Symbolic& s, std::string& err) {
       int64_t steps = 0;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
-        steps = std::max<int64_t>(steps, (w + NB - 1) / NB);
+        steps = std::max<int64_t>(steps, (w + SB - 1) / SB);
         for (int64_t c0 = 0; c0 < w && m > w; c0 += NB)
           for (int64_t r = w; r < m; r += 512) {
             SolveTile t = base_tile(J);
@@ -580,16 +589,18 @@ int build_plan(Symbolic& s, std::string& err) {
         start = (int64_t)p.stiles.size();
         for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
           int64_t J = p.lvl_sn[q], w = W(J);
-          if (k * NB >= w) continue;
+          if (k * SB >= w) continue;
           SolveTile t = base_tile(J);
-          t.c0 = (int32_t)(k * NB);
-          t.nb = (int32_t)std::min<int64_t>(NB, w - k * NB);
-          for (int64_t j = 0; j < std::max<int64_t>(k, 1); ++j) {
-            t.r0 = (int32_t)(j * NB);
-            t.r1 = (int32_t)(k == 0 ? 0 : j * NB + NB);  // an empty range: only the solve
-            t.flags = j == 0 ? 1 : 0;
-            p.stiles.push_back(t);
-          }
+          t.c0 = (int32_t)(k * SB);
+          t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
+          const int64_t earlier = k * SB / NB;  // 64-column chunks before the step
+          for (int32_t half = 0; half < (t.nb > NB ? 2 : 1); ++half)
+            for (int64_t j = 0; j < std::max<int64_t>(earlier, 1); ++j) {
+              t.r0 = (int32_t)(j * NB);
+              t.r1 = (int32_t)(earlier == 0 ? 0 : j * NB + NB);  // an empty range: only the solve
+              t.flags = (j == 0 ? 1 : 0) | (half << 1);
+              p.stiles.push_back(t);
+            }
         }
         push_launch(SOLVE_BWD, h, start);
       }

@@ -137,6 +137,7 @@ struct Plan {
   std::vector<int64_t> diag_src; // input entry of the diagonal of every factored column
   std::vector<DiagTile> dtiles;       // every 64-column step's diagonal tile, by width class
   int64_t dt_ptr[4] = {0, 0, 0, 0};   // classes of 1, 2 and 4 16-column blocks
+  std::vector<DiagTile> ptiles;       // diagonal blocks of the two-chunk solve steps (nb > 64)
   std::vector<SolveTile> stiles;      // solve work items, launch by launch
   std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
   std::vector<Launch> launches;

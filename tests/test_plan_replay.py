@@ -159,23 +159,47 @@ def replay_solve(s, Lb, B):
     x = np.full_like(y, np.nan)
 
     def inv_tile(off, ld, c0, nb):
+        assert nb <= 64
         V = np.zeros((nb, nb))
         for i in range(nb):
             V[i, i] = 1.0 / Lb[off + (c0 + i) * ld + c0 + i]
             V[i, :i] = Lb[off + (c0 + i) * ld + c0: off + (c0 + i) * ld + c0 + i]
         return V
 
+    def diag_solve(off, ld, c0, nb, rhs, transposed):
+        """One or two 64-column chunks: the stored inverses of their diagonal
+        tiles and the block between them, as the step kernels use them."""
+        if nb <= 64:
+            V = inv_tile(off, ld, c0, nb)
+            return (V.T if transposed else V) @ rhs
+        nbb = nb - 64
+        VA, VB = inv_tile(off, ld, c0, 64), inv_tile(off, ld, c0 + 64, nbb)
+        LBA = np.array([[Lb[off + (c0 + c) * ld + c0 + 64 + i] for c in range(64)]
+                        for i in range(nbb)])
+        if not transposed:
+            xa = VA @ rhs[:64]
+            xb = VB @ (rhs[64:] - LBA @ xa)
+        else:
+            xb = VB.T @ rhs[64:]
+            xa = VA.T @ (rhs[:64] - LBA.T @ xb)
+        return np.concatenate([xa, xb])
+
     for kind, lev, st, cnt in s.array("solve_launches").reshape(-1, 4):
         for off, ld, f, w, g0, c0, nb, r0, r1, flags, _ in T[st:st + cnt]:
+            assert 1 <= nb <= 128
+            # kernels of the two-chunk steps split the work by chunk (flags bit 1)
+            half = (flags >> 1) & 1
+            assert half == 0 or nb > 64
+            ca, cb = 64 * half, min(nb, 64 * (half + 1))
             if kind == 0:
-                xk = inv_tile(off, ld, c0, nb) @ y[f + c0: f + c0 + nb]
+                xk = diag_solve(off, ld, c0, nb, y[f + c0: f + c0 + nb], False)[ca:cb]
                 if flags & 1:
-                    z[f + c0: f + c0 + nb] = xk
+                    z[f + c0 + ca: f + c0 + cb] = xk
                 for q in range(r0, r1):
-                    lrow = Lb[off + c0 * ld + q: off + (c0 + nb) * ld + q: ld]
+                    lrow = Lb[off + (c0 + ca) * ld + q: off + (c0 + cb) * ld + q: ld]
                     y[gl[g0 + q]] -= lrow @ xk
             elif kind == 1:
-                assert w <= r0 < r1 <= ld
+                assert w <= r0 < r1 <= ld and nb <= 64
                 for q in range(r0, r1):
                     lrow = Lb[off + c0 * ld + q: off + (c0 + nb) * ld + q: ld]
                     assert not np.isnan(x[gl[g0 + q]]).any(), "ancestor solved first"
@@ -183,12 +207,13 @@ def replay_solve(s, Lb, B):
             else:
                 zk = z[f + c0: f + c0 + nb]
                 assert not np.isnan(zk).any(), "forward result present"
-                xk = inv_tile(off, ld, c0, nb).T @ zk
+                xk = diag_solve(off, ld, c0, nb, zk, True)[ca:cb]
                 if flags & 1:
-                    x[f + c0: f + c0 + nb] = xk
+                    x[f + c0 + ca: f + c0 + cb] = xk
+                assert r1 == r0 or (r1 - r0 <= 64 and r1 <= c0), "push into earlier columns"
                 if r1 > r0:
-                    Lblk = np.array([[Lb[off + (r0 + c) * ld + c0 + i] for c in range(r1 - r0)]
-                                     for i in range(nb)])
+                    Lblk = np.array([[Lb[off + (r0 + c) * ld + c0 + ca + i] for c in range(r1 - r0)]
+                                     for i in range(cb - ca)])
                     z[f + r0: f + r1] -= Lblk.T @ xk
     out = np.empty_like(x)
     out[perm] = x

@@ -195,6 +195,29 @@ struct Mfma<float> {
   static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// a contribution record read by every lane alike (from LDS), made scalar so
+// that the loop control and the addresses built from it stay uniform
+__device__ __forceinline__ int32_t uni32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ UpdSeg uniform_seg(const UpdSeg& g) {
+  UpdSeg u;
+  u.x = uni64(g.x);
+  u.y = uni64(g.y);
+  u.lds = uni32(g.lds);
+  u.k = uni32(g.k);
+  u.ra = uni32(g.ra);
+  u.rb = uni32(g.rb);
+  u.ca = uni32(g.ca);
+  u.cb = uni32(g.cb);
+  u.src = uni32(g.src);
+  u.sslot = uni32(g.sslot);
+  return u;
+}
+
 constexpr int KC = 16;  // K chunk staged per LDS buffer
 
 
@@ -887,17 +910,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
       sY[buf][lk + 4 * q][lr] = (T)((kin && yin) ? yr[q] : 0.0);
     }
   };
-  // the tile's contribution records, staged once (the first SEGS_LDS of them)
-  constexpr int SEGS_LDS = 64;
-  __shared__ UpdSeg sg[SEGS_LDS];
-  {
-    const int words = min(t.nseg, SEGS_LDS) * (int)(sizeof(UpdSeg) / 8);
-    const int64_t* src = reinterpret_cast<const int64_t*>(segs + t.seg0);
-    int64_t* dst = reinterpret_cast<int64_t*>(sg);
-    for (int w = tid; w < words; w += 256) dst[w] = src[w];
-  }
-  __syncthreads();
-  auto seg_at = [&](int i) { return i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]; };
+  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
   int e = 0, k0 = 0;
   UpdSeg g = seg_at(0);
   fetch(g, 0);
@@ -1097,7 +1110,7 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
     for (int w = tid; w < words; w += 256) dst[w] = src[w];
   }
   __syncthreads();
-  auto seg_at = [&](int i) { return i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]; };
+  auto seg_at = [&](int i) { return uniform_seg(i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]); };
   double xr[4], yr[4];
   bool xin = false, yin = false;
   int kvalid = 0;
@@ -1611,22 +1624,34 @@ __global__ void k_axpby_cols(double* __restrict__ y, int64_t ldy, const double* 
   y[k * ldy + row] = a.v[k] * x[k * ldx + row] + b.v[k] * y[k * ldy + row];
 }
 
+// largest m over a 256-thread workgroup, to thread 0 (m >= 0 everywhere)
+__device__ __forceinline__ double block_max256(double m) {
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 // out[k] = max(out[k], max_i |v[i + k*ld]|) via the ordering of non-negative
-// doubles as unsigned integers
-__global__ void k_absmax(const double* __restrict__ v, int64_t n, int64_t ld, int nrhs,
-                         unsigned long long* __restrict__ out) {
+// doubles as unsigned integers; one atomic per workgroup
+__global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ v, int64_t n,
+                                                int64_t ld, int nrhs,
+                                                unsigned long long* __restrict__ out) {
   const int k = blockIdx.y;
   double m = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     m = fmax(m, fabs(v[k * ld + i]));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(out + k, (unsigned long long)__double_as_longlong(m));
+  m = block_max256(m);
+  if (threadIdx.x == 0) atomicMax(out + k, (unsigned long long)__double_as_longlong(m));
 }
 
-// infinity norm of A: max over rows of sum |a_ij|
-__global__ void k_anorm(int64_t n, const int64_t* __restrict__ rp, const int64_t* __restrict__ src,
-                        const double* __restrict__ vals, unsigned long long* __restrict__ out) {
+// infinity norm of A: max over rows of sum |a_ij|; one atomic per workgroup
+__global__ __launch_bounds__(256) void k_anorm(int64_t n, const int64_t* __restrict__ rp,
+                                               const int64_t* __restrict__ src,
+                                               const double* __restrict__ vals,
+                                               unsigned long long* __restrict__ out) {
   double m = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -1634,8 +1659,8 @@ __global__ void k_anorm(int64_t n, const int64_t* __restrict__ rp, const int64_t
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += fabs(vals[src[e]]);
     m = fmax(m, s);
   }
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  m = block_max256(m);
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
 }
 
 __global__ void k_axpy(double* __restrict__ x, int64_t ldx, const double* __restrict__ d,
@@ -1812,19 +1837,19 @@ void launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const int6
 void launch_absmax(const double* v, int64_t n, int64_t ld, int nrhs, unsigned long long* out,
                    hipStream_t st) {
   if (n <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, 256, 1024), nrhs), dim3(256), 0, st, v, n, ld,
+  hipLaunchKernelGGL(k_absmax, dim3(grid_for(n, 256, 128), nrhs), dim3(256), 0, st, v, n, ld,
                      nrhs, out);
 }
 void launch_anorm(int64_t n, const int64_t* rp, const int64_t* src, const double* vals,
                   unsigned long long* out, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_anorm, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, n, rp, src, vals,
+  hipLaunchKernelGGL(k_anorm, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, n, rp, src, vals,
                      out);
 }
 void launch_dot_cols(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
                      int nrhs, double* out, hipStream_t st) {
   if (n <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(k_dot_cols, dim3(grid_for(n, 256, 512), nrhs), dim3(256), 0, st, x, ldx, y,
+  hipLaunchKernelGGL(k_dot_cols, dim3(grid_for(n, 256, 128), nrhs), dim3(256), 0, st, x, ldx, y,
                      ldy, n, out);
 }
 void launch_axpby_cols(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,

@@ -348,7 +348,9 @@ __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, in
     }
   }
   const double sq = sqrt(dg);
-  if (lane < tr) {
+  // rows from the diagonal block down; the rows above it lie in the tile's
+  // unused upper part, which may hold other data (the 16x16 inverses)
+  if (lane < tr && lane >= o) {
 #pragma unroll
     for (int j = 0; j < 16; ++j)
       T[lane * tp + o + j] = lane > o + j ? v[j] : (lane == o + j ? sq : 0.0);
@@ -472,7 +474,7 @@ struct PanelUpd<1> {
 
 // resident workgroups per compute unit the register budget is sized for
 constexpr int panel_occupancy(int nbb, bool pre) {
-  return pre ? (nbb == 1 ? 2 : 1) : (nbb == 1 ? 3 : (nbb == 2 ? 2 : 1));
+  return pre ? (nbb == 1 ? 2 : 1) : (nbb == 1 ? 3 : 2);
 }
 
 // MODE 0: FP64 form. MODE 1: reduced-precision updates (pivot patching).
@@ -505,8 +507,12 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
   // LDS carve (doubles): the tile T (row-major), the inverses of its 16x16
   // diagonal blocks, the row tile (k-major), the finished columns of the
   // current 16-column block, and for PRE the previous block's rows Y and X
+  // with four column blocks the 16x16 inverses live in T's unused upper
+  // blocks (0,1), (0,2), (0,3) and (1,3) (pitch TPn), else in a region of
+  // their own (pitch IP)
+  constexpr bool IUP = NBB == 4;
   constexpr int O_I = TR * TPn;
-  constexpr int O_A = O_I + NBB * 16 * IP;
+  constexpr int O_A = O_I + (IUP ? 0 : NBB * 16 * IP);
   constexpr int O_LC = O_A + TR * AP;
   constexpr int O_Y = O_LC + 16 * 64;
   constexpr int O_X = O_Y + (PRE ? TR * YP : 0);
@@ -527,6 +533,11 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
   }
   double* const T = smem;
   double* const Ib = smem + O_I;
+  constexpr int IPB = IUP ? TPn : IP;  // row pitch of the inverse blocks
+  auto inv_blk = [&](int b) -> double* {
+    if (IUP) return T + (b == 3 ? 16 * TPn + 48 : 16 * (b + 1));
+    return Ib + b * 16 * IP;
+  };
   double* const sA = smem + O_A;
   double* const Lc = smem + O_LC;
   double* const sY = smem + O_Y;
@@ -615,7 +626,7 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     } else {
       if (r >= 1) {
         if (wave == 3) {
-          inv16(T, TPn, 16 * (r - 1), Ib + (r - 1) * 16 * IP, IP, lane);
+          inv16(T, TPn, 16 * (r - 1), inv_blk(r - 1), IPB, lane);
         } else {
           // block r-1's updates of column blocks p >= r+1
           int idx = 0;
@@ -658,7 +669,7 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
   }
   // the last base inverse (wave 3) alongside the first column blocks of the
   // row tiles' solves
-  if (wave == 3) inv16(T, TPn, 16 * (nbb - 1), Ib + (nbb - 1) * 16 * IP, IP, lane);
+  if (wave == 3) inv16(T, TPn, 16 * (nbb - 1), inv_blk(nbb - 1), IPB, lane);
   // the last reader writes the factored tile (lower triangle)
   if (s_last) {
     if (wave == 0 && lane == 0 && bad != 0x7fffffff) atomicMin(status + t.slot, bad);
@@ -726,7 +737,7 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
         v4d x = {0, 0, 0, 0};
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq)
-          x = mfma64(Ib[(16 * b + (lane & 15)) * IP + 4 * kq + (lane >> 4)], r[kq], x);
+          x = mfma64(inv_blk(b)[(lane & 15) * IPB + 4 * kq + (lane >> 4)], r[kq], x);
         X[b] = x;
         const int rr = 16 * rb + (lane & 15);
 #pragma unroll

@@ -117,8 +117,8 @@ def main():
                     help="factorizations timed launch by launch for the roofline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the distributed path is a design note, not built)", file=sys.stderr)
+        print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

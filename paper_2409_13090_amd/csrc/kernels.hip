@@ -4,11 +4,11 @@
 // Factor storage: Lnz(J) is m_J x w_J column-major (ld = m_J), one FP64 buffer.
 //  * k_fill / k_scatter_a  -- A-load: zero the factor storage, then place A's
 //    lower-triangle values (Alg. 5 input: Lnz(J) holds A_{*,J} on entry).
-//  * k_panel               -- cdiv of one <=64-wide column block (Alg. 5 line 4):
+//  * k_panel               -- cdiv of one <=64-wide column block (Alg. 5):
 //    POTRF of the diagonal tile in LDS fused with the TRSM of the rows below.
 //  * k_update<T>           -- C -= sum of X * Y^T on a 64x64 tile of factor
 //    storage: the in-supernode trailing update and the SYRK/GEMM updates
-//    written directly into ancestors (Alg. 5 lines 11-16), on MFMA 16x16x4
+//    written directly into ancestors (Alg. 5), on MFMA 16x16x4
 //    (FP64, or FP32 operands with FP32 accumulation in the mixed form).
 //  * k_fwd_step / k_bwd_below / k_bwd_step -- supernodal solves in 64-column
 //    steps, the diagonal chunks as products with the stored inv(L_kk).
@@ -66,7 +66,7 @@ __global__ void k_scatter_a(const double* __restrict__ vals, const int64_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// cdiv of one <=64-column block (Alg. 5 line 4): POTRF of the diagonal tile
+// cdiv of one <=64-column block (Alg. 5): POTRF of the diagonal tile
 // fused with the TRSM of every row below it, in one launch.
 //
 // A group is the set of workgroups that share one diagonal tile: one per 64

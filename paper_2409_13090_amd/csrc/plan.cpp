@@ -9,11 +9,11 @@
 // elimination tree; every level runs, for column block k = 0, 1, ... of its
 // supernodes (blocks of 64 columns):
 //   * a PANEL launch: cdiv of block k -- POTRF of the 64x64 diagonal tile
-//     fused with the TRSM of every row below it (Alg. 5 line 4);
+//     fused with the TRSM of every row below it (Alg. 5);
 //   * an UPDATE launch holding (a) the trailing update of the columns right of
 //     block k inside the same supernode, and (b) for every supernode whose last
 //     column block was k, all of its SYRK/GEMM updates written straight into
-//     the ancestors' factor storage (Alg. 5 lines 7-18).
+//     the ancestors' factor storage (Alg. 5).
 // Siblings of one level may write the same target entries: the update launch
 // gives every 64x64 target tile to one workgroup, which sums the
 // contributions of all supernodes that touch the tile and writes it once.
@@ -44,6 +44,12 @@ constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a t
 // units of the device, and short update tiles one unit runs while the panel
 // workgroups factor (one resident workgroup per unit in a fused launch)
 constexpr int64_t DEVICE_CUS = 256;
+// rows of a backward-solve workgroup against ancestor rows: each 64-row block
+// of them waits on a dependent pair of loads (the row's index, then x), so
+// the blocks a workgroup walks through are kept few
+#ifndef BELOW_ROWS
+#define BELOW_ROWS 64
+#endif
 constexpr int64_t FUSE_TILES_PER_CU = 4;
 
 // the update work of one step before it is placed: target tiles with their
@@ -524,7 +530,7 @@ int build_plan(Symbolic& s, std::string& err) {
     }
   // solves: forward by level and step of two 64-column chunks (row tiles of
   // 256 below them, for each chunk), backward by level from the root: first
-  // every 64-column chunk against the ancestor rows (segments of 512 rows),
+  // every 64-column chunk against the ancestor rows (segments of BELOW_ROWS rows),
   // then the steps of two chunks from the last down, each chunk pushing into
   // the earlier 64-column chunks of its supernode
   {
@@ -575,12 +581,12 @@ int build_plan(Symbolic& s, std::string& err) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         steps = std::max<int64_t>(steps, (w + SB - 1) / SB);
         for (int64_t c0 = 0; c0 < w && m > w; c0 += NB)
-          for (int64_t r = w; r < m; r += 512) {
+          for (int64_t r = w; r < m; r += BELOW_ROWS) {
             SolveTile t = base_tile(J);
             t.c0 = (int32_t)c0;
             t.nb = (int32_t)std::min<int64_t>(NB, w - c0);
             t.r0 = (int32_t)r;
-            t.r1 = (int32_t)std::min<int64_t>(m, r + 512);
+            t.r1 = (int32_t)std::min<int64_t>(m, r + BELOW_ROWS);
             p.stiles.push_back(t);
           }
       }

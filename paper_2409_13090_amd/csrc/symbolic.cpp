@@ -15,7 +15,7 @@
 //   5. partition-refinement reordering inside every supernode (Section 1,
 //      Fig. 2; Section 3.1) so that descendants' rows form fewer blocks;
 //   6. glbind(J), relind(J, p(J)) (Section 2.1.2), blocks and relindB(J, P)
-//      obtained by composition relindB(J,C) o relind(C,P) (Alg. 5 line 10).
+//      obtained by composition relindB(J,C) o relind(C,P) (Alg. 5).
 #include "symbolic.h"
 
 #include <algorithm>
@@ -634,7 +634,7 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx, const Analy
       s.rbp_ptr[J + 1] = (int64_t)s.rbp_anc.size();
       continue;
     }
-    // extract relindB(J, p(J)) from relind(J, p(J)) (Alg. 5 line 5)
+    // extract relindB(J, p(J)) from relind(J, p(J)) (Alg. 5)
     cur.clear();
     tops.clear();
     int64_t q = 0;

@@ -22,6 +22,17 @@ def _torch():
     return torch
 
 
+def cpu_backward_error(A, B, X):
+    """||b - A x||_inf / (||A||_inf ||x||_inf) per column, from A on the host
+    (scipy), independent of the device's residual and norm kernels."""
+    Af = A.to_scipy_full()
+    b = np.asarray(B, dtype=np.float64).reshape(A.n, -1, order="F")
+    x = np.asarray(X, dtype=np.float64).reshape(A.n, -1, order="F")
+    r = b - Af @ x
+    anorm = np.abs(Af).sum(axis=1).max()
+    return np.abs(r).max(axis=0) / (anorm * np.abs(x).max(axis=0))
+
+
 def solve_check(num, A, tol=1e-14):
     torch = _torch()
     B = torch.from_numpy(np.asfortranarray(A.rhs)).cuda()
@@ -31,6 +42,20 @@ def solve_check(num, A, tol=1e-14):
     num.solve(X)
     be = num.backward_error(B, X)
     assert np.all(be <= tol), be
+    # the host's backward error of the device's x meets the same bound
+    be_cpu = cpu_backward_error(A, A.rhs, X.cpu().numpy())
+    assert np.all(be_cpu <= tol), be_cpu
+    # at roundoff level both are noise; for an x perturbed by 1e-6 (relative)
+    # the residual is A times the perturbation, and the device's residual
+    # and norm kernels must give the host's value closely
+    rng = np.random.default_rng(5)
+    xp = X.cpu().numpy() * (1.0 + 1e-6 * rng.uniform(-1.0, 1.0, X.shape))
+    Xp = torch.from_numpy(np.asfortranarray(xp)).cuda()
+    Xp = Xp.T.contiguous().T if Xp.dim() == 2 else Xp
+    bp = num.backward_error(B, Xp)
+    bp_cpu = cpu_backward_error(A, A.rhs, xp)
+    assert np.all(bp_cpu > 1e-9), bp_cpu
+    assert np.allclose(bp, bp_cpu, rtol=1e-8, atol=0.0), (bp, bp_cpu)
     return be
 
 

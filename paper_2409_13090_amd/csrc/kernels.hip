@@ -1363,8 +1363,9 @@ __global__ __launch_bounds__(256) void k_pair_inverse(const DiagTile* __restrict
 // tiles and the off-diagonal block formed after the factorization), a
 // workgroup of the first chunk forms x_A = V0 y_A, one of the second x_B =
 // W y_A + V1 y_B, redundantly (x stored into z by the half's writer, flags
-// bit 0), then y(rows r0..r1 of the supernode) -= L(rows, its chunk) x_chunk,
-// one row per thread; plainly for own rows of a one-chunk step, else with
+// bit 0), then y(rows r0..r1 of the supernode, at most 64) -= L(rows, its
+// chunk) x_chunk: wave g sums columns 16g..16g+15 of a row, the four partial
+// sums meet in LDS; plainly for own rows of a one-chunk step, else with
 // atomics (the other chunk's workgroups and other supernodes add too)
 __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ gl,
@@ -1372,7 +1373,7 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
                                                   double* __restrict__ y, double* __restrict__ z,
                                                   int nrhs, int64_t ldy) {
   const SolveTile t = tiles[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6;
   const double* Lj = L + t.off;
   const int64_t ld = t.ld;
   const int nbA = min(t.nb, 64), nbB = t.nb - nbA;
@@ -1380,21 +1381,24 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
   const int cc = t.c0 + 64 * half;          // first column of this workgroup's chunk
   const int nbc = half ? nbB : nbA;         // its width
   __shared__ double V0[64 * VP];  // this chunk's inverse
-  __shared__ double W[64 * VP];   // second chunk: the off-diagonal inverse block
-  __shared__ double ys[MAXRHS][128];
-  __shared__ double xs[MAXRHS][64];
-  // this thread's row of the GEMV: all 64 loads issued before the chunk solve
-  const int q = t.r0 + tid;
+  __shared__ double W[64 * VP];   // second chunk: the off-diagonal inverse block; then the partial sums
+  // y of the step's columns [r][128] and x of the chunk [r][64], sized by
+  // nrhs at launch
+  extern __shared__ double fwd_dyn[];
+  double* const ys = fwd_dyn;
+  double* const xs = fwd_dyn + 128 * nrhs;
+  // this thread's 16 entries of its row, loaded before the chunk solve
+  const int q = t.r0 + row;
   const int qq = min(q, t.ld - 1);
   const int gq = gl[t.gl + min(q, t.r1 - 1)];
-  double l[64];
+  double l[16];
 #pragma unroll
-  for (int c = 0; c < 64; ++c) l[c] = Lj[(int64_t)(cc + min(c, nbc - 1)) * ld + qq];
+  for (int c = 0; c < 16; ++c) l[c] = Lj[(int64_t)(cc + min(16 * cg + c, nbc - 1)) * ld + qq];
   stage_inv(V0, Lj, ld, cc, nbc, tid);
   if (half) stage_w(W, Lj, ld, t.c0, nbB, tid);
   for (int e = tid; e < 128 * nrhs; e += 256) {
     const int i = e & 127, r = e >> 7;
-    ys[r][i] = i < t.nb ? y[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
+    ys[r * 128 + i] = i < t.nb ? y[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
   }
   __syncthreads();
   for (int e = tid; e < 64 * nrhs; e += 256) {
@@ -1402,39 +1406,44 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll 8
     for (int j = 0; j < 64; j += 2) {
-      a0 += V0[i * VP + j] * ys[r][64 * half + j];
-      a1 += V0[i * VP + j + 1] * ys[r][64 * half + j + 1];
+      a0 += V0[i * VP + j] * ys[r * 128 + 64 * half + j];
+      a1 += V0[i * VP + j + 1] * ys[r * 128 + 64 * half + j + 1];
     }
     if (half) {
 #pragma unroll 8
       for (int j = 0; j < 64; j += 2) {
-        a0 += W[i * VP + j] * ys[r][j];
-        a1 += W[i * VP + j + 1] * ys[r][j + 1];
+        a0 += W[i * VP + j] * ys[r * 128 + j];
+        a1 += W[i * VP + j + 1] * ys[r * 128 + j + 1];
       }
     }
-    xs[r][i] = a0 + a1;
+    xs[r * 64 + i] = a0 + a1;
   }
   __syncthreads();
   if (t.flags & 1)
     for (int e = tid; e < 64 * nrhs; e += 256) {
       const int i = e & 63, r = e >> 6;
-      if (i < nbc) z[(int64_t)r * ldy + t.f + cc + i] = xs[r][i];
+      if (i < nbc) z[(int64_t)r * ldy + t.f + cc + i] = xs[r * 64 + i];
     }
-  if (q < t.r1) {
-    for (int r = 0; r < nrhs; ++r) {
-      double a0 = 0.0, a1 = 0.0;
+  double* part = W;  // [cg][r][row], 4 * nrhs * 64 <= 64 * VP doubles
+  for (int r = 0; r < nrhs; ++r) {
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int c = 0; c < 64; c += 2) {
-        a0 += l[c] * xs[r][c];  // xs is 0 beyond the chunk
-        a1 += l[c + 1] * xs[r][c + 1];
-      }
-      const double acc = a0 + a1;
+    for (int c = 0; c < 16; c += 2) {
+      a0 += l[c] * xs[r * 64 + 16 * cg + c];  // xs is 0 beyond the chunk
+      a1 += l[c + 1] * xs[r * 64 + 16 * cg + c + 1];
+    }
+    part[(cg * nrhs + r) * 64 + row] = a0 + a1;
+  }
+  __syncthreads();
+  if (q < t.r1)
+    for (int r = cg; r < nrhs; r += 4) {
+      const double acc = (part[(0 * nrhs + r) * 64 + row] + part[(1 * nrhs + r) * 64 + row]) +
+                         (part[(2 * nrhs + r) * 64 + row] + part[(3 * nrhs + r) * 64 + row]);
       if (q < t.w && nbB == 0)
         y[(int64_t)r * ldy + gq] -= acc;
       else
         atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
     }
-  }
 }
 
 // backward, ancestor rows: z(chunk columns) -= L(rows r0..r1, chunk)^T x(glbind rows),
@@ -1808,7 +1817,8 @@ void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStr
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                      double* y, double* z, int nrhs, int64_t ldy, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_step, dim3((unsigned)count), dim3(256), 0, st, tiles, gl, L, y, z,
+  const size_t dyn = sizeof(double) * (128 + 64) * (size_t)nrhs;
+  hipLaunchKernelGGL(k_fwd_step, dim3((unsigned)count), dim3(256), dyn, st, tiles, gl, L, y, z,
                      nrhs, ldy);
 }
 void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,

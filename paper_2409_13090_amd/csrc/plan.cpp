@@ -47,6 +47,7 @@ constexpr int64_t DEVICE_CUS = 256;
 // rows of a backward-solve workgroup against ancestor rows: each 64-row block
 // of them waits on a dependent pair of loads (the row's index, then x), so
 // the blocks a workgroup walks through are kept few
+constexpr int64_t FWD_ROWS = 64;  // rows of a forward-solve workgroup below its chunk
 #ifndef BELOW_ROWS
 #define BELOW_ROWS 64
 #endif
@@ -529,7 +530,7 @@ int build_plan(Symbolic& s, std::string& err) {
       if (nb > NB) p.ptiles.push_back(DiagTile{p.off[J] + c0 * M(J) + c0, (int32_t)M(J), (int32_t)nb});
     }
   // solves: forward by level and step of two 64-column chunks (row tiles of
-  // 256 below them, for each chunk), backward by level from the root: first
+  // FWD_ROWS below them, for each chunk), backward by level from the root: first
   // every 64-column chunk against the ancestor rows (segments of BELOW_ROWS rows),
   // then the steps of two chunks from the last down, each chunk pushing into
   // the earlier 64-column chunks of its supernode
@@ -562,11 +563,11 @@ int build_plan(Symbolic& s, std::string& err) {
           t.c0 = (int32_t)(k * SB);
           t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
           int64_t lo = t.c0 + t.nb;
-          int64_t nt = std::max<int64_t>(1, (m - lo + 255) / 256);
+          int64_t nt = std::max<int64_t>(1, (m - lo + FWD_ROWS - 1) / FWD_ROWS);
           for (int32_t half = 0; half < (t.nb > NB ? 2 : 1); ++half)
             for (int64_t i = 0; i < nt; ++i) {
-              t.r0 = (int32_t)std::min<int64_t>(m, lo + 256 * i);
-              t.r1 = (int32_t)std::min<int64_t>(m, lo + 256 * (i + 1));
+              t.r0 = (int32_t)std::min<int64_t>(m, lo + FWD_ROWS * i);
+              t.r1 = (int32_t)std::min<int64_t>(m, lo + FWD_ROWS * (i + 1));
               t.flags = (i == 0 ? 1 : 0) | (half << 1);
               p.stiles.push_back(t);
             }

@@ -542,7 +542,7 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     if (l.kind == LAUNCH_UPDATE) {
       launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
-                    l.variant != 0, st);
+                    l.variant != 0, st, l.nwave);
     } else {
       launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, l.variant,
                    l.pre != 0, h->thr, h->amax, u, h->smax, nfixed, h->d.updates + l.ustart,
@@ -923,6 +923,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
     if (!any) break;
     Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0, bp, 0, 0, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
+    std::vector<UpdTile> narrow;  // update launch: the narrow tiles, placed last
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
     m.ustart = (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
@@ -952,14 +953,22 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
         }
         m.ucount += l.ucount;
       } else {
+        // the regular tiles now, the narrow ones after every matrix's
         for (int64_t t = 0; t < l.count; ++t) {
           UpdTile ut = p.updates[l.start + t];
           ut.c += b->base[i];
           ut.seg0 += (int32_t)segbase[i];
-          b->updates.push_back(ut);
+          if (ut.n <= NARROW_COLS)
+            narrow.push_back(ut);
+          else
+            b->updates.push_back(ut);
         }
       }
       cur[i]++;
+    }
+    if (bk == LAUNCH_UPDATE) {
+      b->updates.insert(b->updates.end(), narrow.begin(), narrow.end());
+      m.nwave = (int32_t)narrow.size();
     }
     m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
               m.start;
@@ -1065,7 +1074,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
-                    l.variant != 0, st);
+                    l.variant != 0, st, l.nwave);
     else {
       // the batch factors with the FP64 panel kernel; its fused update tiles
       // run inside it in the FP64 form and as a short launch of their own in

@@ -32,7 +32,8 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
                   int64_t ucount, hipStream_t st);
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st);
+                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st,
+                   int64_t nwave = 0);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
 // the off-diagonal inverse blocks of the two-chunk solve steps (after

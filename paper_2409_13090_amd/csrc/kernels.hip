@@ -1008,6 +1008,84 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
 
+// Update of narrow target tiles (at most 64 rows and 16 columns: the targets
+// in small supernodes), one wavefront per tile and four tiles per
+// workgroup: C -= sum over the tile's contributions of X * Y^T, the MFMA
+// operands read straight from factor storage (a wavefront's 16 lanes of one
+// k read 16 consecutive source rows), no LDS and no barrier. Row block bi of
+// the tile is MFMA block acc[bi]; rows and k outside a contribution read as 0.
+__global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__ tiles,
+                                                  const UpdSeg* __restrict__ segs,
+                                                  double* __restrict__ L, int count) {
+  const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
+  const int ti = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
+  if (ti >= count) return;
+  const UpdTile t = tiles[ti];
+  double* __restrict__ C = L + t.c;
+  const bool diag = t.flags & 1, atomic = t.flags & 2;
+  double cv[4][4];
+  if (!atomic) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = min(16 * bi + il, t.m - 1), col = min(4 * v + kl, t.n - 1);
+        cv[bi][v] = C[(int64_t)col * t.ldc + row];
+      }
+  }
+  v4d acc[4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi) acc[bi] = v4d{0, 0, 0, 0};
+  for (int e = 0; e < t.nseg; ++e) {
+    const UpdSeg g = segs[t.seg0 + e];
+    const bool yin = il >= g.ca && il < g.cb;
+    const int64_t yo = g.y + min(max(il - g.ca, 0), g.cb - g.ca - 1);
+    bool xin[4];
+    int64_t xo[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+      const int r = 16 * bi + il;
+      xin[bi] = r >= g.ra && r < g.rb;
+      xo[bi] = g.x + min(max(r - g.ra, 0), g.rb - g.ra - 1);
+    }
+#pragma unroll 1
+    for (int k0 = 0; k0 < g.k; k0 += 16) {
+      // all loads of the 16-deep chunk in flight before its products
+      double ya[4], xb[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = k0 + 4 * q + kl;
+        const int64_t kc = min(kk, g.k - 1);
+        ya[q] = L[yo + kc * g.lds];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool kin = k0 + 4 * q + kl < g.k;
+        const double a = (kin && yin) ? ya[q] : 0.0;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+          acc[bi] = mfma64(a, (kin && xin[bi]) ? xb[q][bi] : 0.0, acc[bi]);
+      }
+    }
+  }
+  // acc[bi][v] is the update of target row 16*bi + il, column 4*v + kl
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * bi + il, col = 4 * v + kl;
+      if (row < t.m && col < t.n && (!diag || row >= col)) {
+        double* p = C + (int64_t)col * t.ldc + row;
+        if (atomic)
+          atomicAdd(p, -acc[bi][v]);
+        else
+          *p = cv[bi][v] - acc[bi][v];
+      }
+    }
+}
+
 // The trailing updates of a step as a launch of their own.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_short(const UpdTile* __restrict__ tiles,
@@ -1776,8 +1854,18 @@ void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* 
     hipLaunchKernelGGL(k_tile_inverse<4>, g, b, 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st) {
+                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st,
+                   int64_t nwave) {
   if (count <= 0) return;
+  if (precision == 0 && nwave >= WAVE_SPLIT_MIN) {
+    // the last nwave tiles are narrow: one wavefront each (a launch of its
+    // own pays off for many of them, as in the merged launches of a batch)
+    const int64_t nw = std::min(nwave, count);
+    hipLaunchKernelGGL(k_update_w, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, st,
+                       tiles + (count - nw), segs, L, (int)nw);
+    count -= nw;
+    if (count <= 0) return;
+  }
   const dim3 g((unsigned)count), b(256);
   if (shortk && precision <= 1) {
     if (precision == 1)

@@ -228,6 +228,7 @@ int build_plan(Symbolic& s, std::string& err) {
   // form)
   auto commit = [&](const PendingUpdate& u, int64_t fused_into) {
     const int64_t start = (int64_t)p.updates.size();
+    int64_t nwave = 0;
     bool shortk = true;
     int64_t counts[2] = {0, 0};
     for (int part = 0; part < 2; ++part) {
@@ -244,6 +245,18 @@ int build_plan(Symbolic& s, std::string& err) {
                        [](const std::pair<int64_t, size_t>& x, const std::pair<int64_t, size_t>& y) {
                          return x.first < y.first;
                        });
+      // a launch of its own with enough narrow tiles puts them last
+      if (fused_into < 0) {
+        int64_t nn = 0;
+        for (auto& o : order) nn += u.tiles[o.second].n <= NARROW_COLS;
+        if (nn >= WAVE_SPLIT_MIN) {
+          std::stable_partition(order.begin(), order.end(),
+                                [&](const std::pair<int64_t, size_t>& o) {
+                                  return u.tiles[o.second].n > NARROW_COLS;
+                                });
+          nwave = nn;
+        }
+      }
       for (auto& o : order) {
         UpdTile t = u.tiles[o.second];
         const int32_t s0 = t.seg0;
@@ -260,7 +273,8 @@ int build_plan(Symbolic& s, std::string& err) {
       p.launches[fused_into].ucount = counts[0];
       p.launches[fused_into].ncount = counts[1];
     } else if (counts[0]) {
-      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, counts[0], 0, 0, 0, 0, 0};
+      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, counts[0], 0, (int32_t)nwave,
+                0, 0, 0};
       p.launches.push_back(lu);
     }
   };

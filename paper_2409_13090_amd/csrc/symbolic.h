@@ -110,6 +110,12 @@ struct SolveLaunch {
 constexpr int32_t LAUNCH_PANEL = 0;
 constexpr int32_t LAUNCH_UPDATE = 1;
 
+// Narrow update tiles (at most NARROW_COLS columns) run one per wavefront
+// (k_update_w, FP64) when a launch holds at least WAVE_SPLIT_MIN of them;
+// fewer do not repay a launch of their own.
+constexpr int32_t NARROW_COLS = 16;
+constexpr int64_t WAVE_SPLIT_MIN = 1024;
+
 struct Launch {
   int32_t kind;   // LAUNCH_*
   int32_t level;
@@ -119,7 +125,8 @@ struct Launch {
   int64_t start;  // first tile
   int64_t count;  // number of tiles
   int32_t pre;    // panel: its tiles first apply the previous block's trailing update
-  int32_t pad;
+  int32_t nwave;  // update: its last nwave tiles are narrow (<= 16 columns), run one per
+                  // wavefront in the FP64 form
   int64_t ustart; // panel: update tiles of the previous step run in the same launch
   int64_t ucount; //   (single-contribution tiles, k <= 64); the ncount tiles after
   int64_t ncount; //   them are the ones pre applies (kept for the unfused form)

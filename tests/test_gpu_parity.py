@@ -110,6 +110,28 @@ def test_panel_workgroups_with_several_row_tiles():
     solve_check(num, A)
 
 
+def test_narrow_tiles_run_one_per_wavefront():
+    """A 2D grid large enough that an update launch holds more than 1024 narrow
+    target tiles (<= 16 columns), which then run one per wavefront."""
+    A = W.small_grid("9pt", (320, 300, 1), seed=41)
+    s = rlb.Symbolic.from_matrix(A)
+    T = s.array("update_tiles").reshape(-1, 7)
+    L = s.array("launches").reshape(-1, 10)
+    most = 0
+    for l in L[L[:, 0] == 1]:
+        c = 0
+        for _, _, m, n, _, _, _ in T[l[3]:l[3] + l[4]]:
+            if n <= 16:
+                c += 1
+        most = max(most, c)
+    assert most >= 1024, most
+    o, f = oracle_factor(A)
+    s2, num, vals, info = gpu_factor(A)
+    assert info == 0
+    compare_factor(num.export(), f, A.n)
+    solve_check(num, A)
+
+
 def test_edge_cases_tiny_diagonal_chain():
     torch = _torch()
     # n = 1
@@ -186,9 +208,20 @@ def test_batched_matches_unbatched_and_oracle():
     vals = [torch.from_numpy(A.values).cuda() for A in mats]
     info = b.factor(vals)
     assert np.all(info == 0)
+    # the batch workspace holds each matrix's factor storage in turn; its
+    # merged launches (with narrow tiles run one per wavefront) give each
+    # matrix's factor of the unbatched path, element by element
+    ws_b = b.workspace.cpu().numpy()
+    elems = [s.info()["factor_bytes"] // 8 for s in syms]
+    assert sum(elems) <= ws_b.size
+    base = np.concatenate([[0], np.cumsum(elems)])
     for i, A in enumerate(mats):
         num = rlb.Numeric(syms[i])
         num.factor(vals[i])
+        ws_s = num.workspace[:elems[i]].cpu().numpy()
+        part = ws_b[base[i]:base[i] + elems[i]]
+        err = np.linalg.norm(part - ws_s) / np.linalg.norm(ws_s)
+        assert err <= 1e-12, (i, err)
         # the batch's factor of matrix i, solved through the batch handle
         B = torch.from_numpy(A.rhs[:, 0].copy()).cuda()
         X = B.clone()

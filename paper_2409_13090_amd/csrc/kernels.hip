@@ -766,6 +766,52 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
   }
 }
 
+// LDS written by a wavefront is read back by other lanes of the same
+// wavefront: order the accesses without a workgroup barrier
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The inverse of diagonal tiles of at most 16 columns, one wavefront per tile
+// and four tiles per workgroup (small supernodes: one wavefront does all of
+// the work), stored as k_tile_inverse stores it.
+__global__ __launch_bounds__(256) void k_tile_inverse_w(const DiagTile* __restrict__ tiles,
+                                                        double* __restrict__ L, int count) {
+  constexpr int TP = 17;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double Ts[4][16 * TP];
+  __shared__ double Is[4][16 * TP];
+  const int ti = (int)blockIdx.x * 4 + wave;
+  if (ti >= count) return;  // no workgroup barrier below
+  const DiagTile t = tiles[ti];
+  double* const T = Ts[wave];
+  double* const I = Is[wave];
+  const int nb = t.nb, ldi = t.ld;
+  double* D = L + t.diag;
+  {
+    const int row = lane & 15, cg = lane >> 4;
+    const int dr = min(row, nb - 1);
+    double dv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dv[i] = D[(int64_t)min(cg + 4 * i, nb - 1) * ldi + dr];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = cg + 4 * i;
+      T[row * TP + j] = (row < nb && j < nb && j <= row) ? dv[i] : (j == row ? 1.0 : 0.0);
+    }
+  }
+  wave_sync_lds();
+  inv16(T, TP, 0, I, TP, lane);
+  wave_sync_lds();
+  // inv(i, j), i > j, at row j of column i
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e >> 4, j = e & 15;
+    if (i > j && i < nb) D[(int64_t)i * ldi + j] = I[i * TP + j];
+  }
+}
+
 // Inverse of every diagonal tile of the factor, for the solves: inv(L_kk)
 // of the <=64x64 tile goes, strict lower part transposed, into the tile's
 // unused strict upper triangle (inv(L)(i,j), i > j, at row j of column i).
@@ -1847,7 +1893,8 @@ void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* 
   if (count <= 0) return;
   const dim3 g((unsigned)count), b(256);
   if (nbb <= 1)
-    hipLaunchKernelGGL(k_tile_inverse<1>, g, b, 0, st, tiles, L);
+    hipLaunchKernelGGL(k_tile_inverse_w, dim3((unsigned)((count + 3) / 4)), b, 0, st, tiles, L,
+                       (int)count);
   else if (nbb == 2)
     hipLaunchKernelGGL(k_tile_inverse<2>, g, b, 0, st, tiles, L);
   else

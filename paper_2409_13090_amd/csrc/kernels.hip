@@ -812,6 +812,87 @@ __global__ __launch_bounds__(256) void k_tile_inverse_w(const DiagTile* __restri
   }
 }
 
+// k_panel for column blocks of at most 16 columns without a previous-block
+// update, FP64 form, one wavefront per group member and four per workgroup
+// (small supernodes leave most of a 256-thread workgroup idle): the
+// wavefront factors the diagonal tile (pivot chain as in k_panel), the last
+// reader of the group writes it back, and each 64-row tile is solved with
+// the tile's inverse on MFMA, its operands read straight from factor storage.
+__global__ __launch_bounds__(256) void k_panel_w(const PanelTile* __restrict__ tiles,
+                                                 double* __restrict__ L,
+                                                 int* __restrict__ status,
+                                                 int* __restrict__ counters, int count) {
+  constexpr int TP = 17;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int il = lane & 15, kl = lane >> 4;
+  __shared__ double Ts[4][16 * TP];
+  __shared__ double Is[4][16 * TP];
+  __shared__ double Lcs[4][16 * 64];
+  const int ti = (int)blockIdx.x * 4 + wave;
+  if (ti >= count) return;  // no workgroup barrier below
+  const PanelTile t = tiles[ti];
+  double* const T = Ts[wave];
+  double* const I = Is[wave];
+  const int nb = t.nb, ldi = t.ld;
+  double* D = L + t.diag;
+  {
+    const int dr = min(il, nb - 1);
+    double dv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dv[i] = D[(int64_t)min(kl + 4 * i, nb - 1) * ldi + dr];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = kl + 4 * i;
+      T[il * TP + j] = (il < nb && j < nb && j <= il) ? dv[i] : (j == il ? 1.0 : 0.0);
+    }
+  }
+  wave_sync_lds();
+  // this member has read the unfactored tile
+  int old = 0;
+  if (lane == 0) old = atomicAdd(&counters[t.grp], 1);
+  const bool last = __builtin_amdgcn_readfirstlane(old) == t.gcnt - 1;
+  const int bad = panel16<false>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr);
+  wave_sync_lds();
+  inv16(T, TP, 0, I, TP, lane);
+  if (last) {
+    if (lane == 0) {
+      atomicExch(&counters[t.grp], 0);
+      if (bad != 0x7fffffff) atomicMin(status + t.slot, bad);
+    }
+    for (int e = lane; e < 256; e += 64) {
+      const int i = e >> 4, j = e & 15;
+      if (i < nb && j <= i) D[(int64_t)j * ldi + i] = T[i * TP + j];
+    }
+  }
+  wave_sync_lds();
+  // X = A inv(L)^T for the member's row tiles, 16 rows per MFMA block
+  for (int rt = 0; rt < t.nrt; ++rt) {
+    const int row0 = t.row0 + 64 * rt;
+    const int nrows = min(64, t.nrows - row0);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (16 * rb >= nrows) break;
+      const int rr = 16 * rb + il;
+      const int ar = row0 + min(rr, nrows - 1);
+      v4d r;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 4 * v + kl;
+        const double a = D[(int64_t)min(c, nb - 1) * ldi + ar];
+        r[v] = (rr < nrows && c < nb) ? a : 0.0;
+      }
+      v4d x = {0, 0, 0, 0};
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) x = mfma64(I[il * TP + 4 * kq + kl], r[kq], x);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 4 * v + kl;
+        if (c < nb && rr < nrows) D[(int64_t)c * ldi + row0 + rr] = x[v];
+      }
+    }
+  }
+}
+
 // Inverse of every diagonal tile of the factor, for the solves: inv(L_kk)
 // of the <=64x64 tile goes, strict lower part transposed, into the tile's
 // unused strict upper triangle (inv(L)(i,j), i > j, at row j of column i).
@@ -1873,6 +1954,13 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   int64_t ucount, hipStream_t st) {
   if (count <= 0) return;
   if (precision == 2 || nbb < 4) ucount = 0;  // (the plan fuses into 64-column launches only)
+  if (precision == 0 && nbb <= 1 && !pre && count >= WAVE_SPLIT_MIN) {
+    // many small column blocks (as in a batch's merged launches): one
+    // wavefront per group member
+    hipLaunchKernelGGL(k_panel_w, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, st, tiles, L,
+                       status, counters, (int)count);
+    return;
+  }
 #define RLB_PANEL_N(N, P)                                                                       \
   launch_panel_n<N, P>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed, \
                        utiles, usegs, ucount, st)

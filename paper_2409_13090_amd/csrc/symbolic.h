@@ -112,7 +112,9 @@ constexpr int32_t LAUNCH_UPDATE = 1;
 
 // Narrow update tiles (at most NARROW_COLS columns) run one per wavefront
 // (k_update_w, FP64) when a launch holds at least WAVE_SPLIT_MIN of them;
-// fewer do not repay a launch of their own.
+// fewer do not repay a launch of their own. Panel launches of at least
+// WAVE_SPLIT_MIN column blocks of at most 16 columns likewise run one group
+// member per wavefront (k_panel_w).
 constexpr int32_t NARROW_COLS = 16;
 constexpr int64_t WAVE_SPLIT_MIN = 1024;
 

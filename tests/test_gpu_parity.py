@@ -112,7 +112,8 @@ def test_panel_workgroups_with_several_row_tiles():
 
 def test_narrow_tiles_run_one_per_wavefront():
     """A 2D grid large enough that an update launch holds more than 1024 narrow
-    target tiles (<= 16 columns), which then run one per wavefront."""
+    target tiles (<= 16 columns) and a panel launch more than 1024 column
+    blocks of at most 16 columns, which then run one per wavefront."""
     A = W.small_grid("9pt", (320, 300, 1), seed=41)
     s = rlb.Symbolic.from_matrix(A)
     T = s.array("update_tiles").reshape(-1, 7)
@@ -125,6 +126,8 @@ def test_narrow_tiles_run_one_per_wavefront():
                 c += 1
         most = max(most, c)
     assert most >= 1024, most
+    narrow_panels = [l[4] for l in L if l[0] == 0 and l[5] == 1 and l[6] == 0]
+    assert max(narrow_panels) >= 1024, narrow_panels
     o, f = oracle_factor(A)
     s2, num, vals, info = gpu_factor(A)
     assert info == 0

@@ -1140,37 +1140,36 @@ template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*)
 // workgroup: C -= sum over the tile's contributions of X * Y^T, the MFMA
 // operands read straight from factor storage (a wavefront's 16 lanes of one
 // k read 16 consecutive source rows), no LDS and no barrier. Row block bi of
-// the tile is MFMA block acc[bi]; rows and k outside a contribution read as 0.
-__global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__ tiles,
-                                                  const UpdSeg* __restrict__ segs,
-                                                  double* __restrict__ L, int count) {
-  const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
-  const int ti = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
-  if (ti >= count) return;
-  const UpdTile t = tiles[ti];
+// the tile is MFMA block acc[bi]; NBI blocks cover the tile's rows (rows past
+// the tile are clamped reads, not stored); rows and k outside a contribution
+// read as 0.
+template <int NBI>
+__device__ __forceinline__ void update_w_tile(const UpdTile& t, const UpdSeg* __restrict__ segs,
+                                              double* __restrict__ L, int lane) {
+  const int il = lane & 15, kl = lane >> 4;
   double* __restrict__ C = L + t.c;
   const bool diag = t.flags & 1, atomic = t.flags & 2;
-  double cv[4][4];
+  double cv[NBI][4];
   if (!atomic) {
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < NBI; ++bi)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = min(16 * bi + il, t.m - 1), col = min(4 * v + kl, t.n - 1);
         cv[bi][v] = C[(int64_t)col * t.ldc + row];
       }
   }
-  v4d acc[4];
+  v4d acc[NBI];
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi) acc[bi] = v4d{0, 0, 0, 0};
+  for (int bi = 0; bi < NBI; ++bi) acc[bi] = v4d{0, 0, 0, 0};
   for (int e = 0; e < t.nseg; ++e) {
     const UpdSeg g = segs[t.seg0 + e];
     const bool yin = il >= g.ca && il < g.cb;
     const int64_t yo = g.y + min(max(il - g.ca, 0), g.cb - g.ca - 1);
-    bool xin[4];
-    int64_t xo[4];
+    bool xin[NBI];
+    int64_t xo[NBI];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < NBI; ++bi) {
       const int r = 16 * bi + il;
       xin[bi] = r >= g.ra && r < g.rb;
       xo[bi] = g.x + min(max(r - g.ra, 0), g.rb - g.ra - 1);
@@ -1178,28 +1177,27 @@ __global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__
 #pragma unroll 1
     for (int k0 = 0; k0 < g.k; k0 += 16) {
       // all loads of the 16-deep chunk in flight before its products
-      double ya[4], xb[4][4];
+      double ya[4], xb[4][NBI];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int kk = k0 + 4 * q + kl;
-        const int64_t kc = min(kk, g.k - 1);
+        const int64_t kc = min(k0 + 4 * q + kl, g.k - 1);
         ya[q] = L[yo + kc * g.lds];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
+        for (int bi = 0; bi < NBI; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bool kin = k0 + 4 * q + kl < g.k;
         const double a = (kin && yin) ? ya[q] : 0.0;
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
+        for (int bi = 0; bi < NBI; ++bi)
           acc[bi] = mfma64(a, (kin && xin[bi]) ? xb[q][bi] : 0.0, acc[bi]);
       }
     }
   }
   // acc[bi][v] is the update of target row 16*bi + il, column 4*v + kl
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
+  for (int bi = 0; bi < NBI; ++bi)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * bi + il, col = 4 * v + kl;
@@ -1211,6 +1209,21 @@ __global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__
           *p = cv[bi][v] - acc[bi][v];
       }
     }
+}
+
+__global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__ tiles,
+                                                     const UpdSeg* __restrict__ segs,
+                                                     double* __restrict__ L, int count) {
+  const int lane = threadIdx.x & 63;
+  const int ti = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
+  if (ti >= count) return;
+  const UpdTile t = tiles[ti];
+  if (t.m <= 16)
+    update_w_tile<1>(t, segs, L, lane);
+  else if (t.m <= 32)
+    update_w_tile<2>(t, segs, L, lane);
+  else
+    update_w_tile<4>(t, segs, L, lane);
 }
 
 // The trailing updates of a step as a launch of their own.

@@ -313,7 +313,7 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
 // column indices are larger); afterwards each pivot lane checks its own raw
 // pivot and the smallest failing column (1-based, factored order) is
 // returned, or INT_MAX.
-template <bool FIX>
+template <bool FIX, int NC = 16>
 __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, int o, int nb,
                                        int col0, int lane, double thr, double rep, int* nfix) {
   const int lr = min(lane, tr - 1);
@@ -323,7 +323,9 @@ __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, in
   double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
   double dn = lane_bcast(v[0], o);  // the next pivot, before any patching
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
+  for (int c = 0; c < NC; ++c) {
+    // NC < 16 (callers with nb <= o + NC): columns from nb on are the
+    // identity with zeros below, they change nothing and are not visited
     double d = dn;
     if (FIX) {
       if (d <= lane_bcast(thr, o + c) && o + c < nb) {
@@ -818,7 +820,7 @@ __global__ __launch_bounds__(256) void k_tile_inverse_w(const DiagTile* __restri
 // wavefront factors the diagonal tile (pivot chain as in k_panel), the last
 // reader of the group writes it back, and each 64-row tile is solved with
 // the tile's inverse on MFMA, its operands read straight from factor storage.
-__global__ __launch_bounds__(256) void k_panel_w(const PanelTile* __restrict__ tiles,
+__global__ __launch_bounds__(256, 3) void k_panel_w(const PanelTile* __restrict__ tiles,
                                                  double* __restrict__ L,
                                                  int* __restrict__ status,
                                                  int* __restrict__ counters, int count) {
@@ -851,7 +853,11 @@ __global__ __launch_bounds__(256) void k_panel_w(const PanelTile* __restrict__ t
   int old = 0;
   if (lane == 0) old = atomicAdd(&counters[t.grp], 1);
   const bool last = __builtin_amdgcn_readfirstlane(old) == t.gcnt - 1;
-  const int bad = panel16<false>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr);
+  // the pivot chain visits the block's columns only (nb <= 4, 8 or 16)
+  const int bad =
+      nb <= 4 ? panel16<false, 4>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr)
+      : nb <= 8 ? panel16<false, 8>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr)
+                : panel16<false, 16>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr);
   wave_sync_lds();
   inv16(T, TP, 0, I, TP, lane);
   if (last) {

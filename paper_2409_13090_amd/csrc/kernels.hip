@@ -45,16 +45,30 @@ __global__ void k_zero_u64(unsigned long long* p, int count) {
 
 // A-load of many matrices: entry e of the concatenated entry space belongs to
 // the matrix k with nnz_ptr[k] <= e < nnz_ptr[k+1]
-__global__ void k_scatter_batch(const double* const* __restrict__ vals,
-                                const int64_t* __restrict__ nnz_ptr, int32_t count, int64_t total,
-                                const int64_t* __restrict__ amap, double* __restrict__ L) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  int lo = 0, hi = count;  // largest k with nnz_ptr[k] <= e
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (nnz_ptr[mid] <= e) lo = mid; else hi = mid;
+// every matrix's input entries into its factor storage: matrix k holds
+// entries nnz_ptr[k] .. nnz_ptr[k+1]-1 of the concatenated list; the matrix
+// of a workgroup's first entry is found once (every matrix has at least 256
+// entries in practice, and a thread walks on past the ones it crosses)
+__global__ __launch_bounds__(256) void k_scatter_batch(const double* const* __restrict__ vals,
+                                                       const int64_t* __restrict__ nnz_ptr,
+                                                       int32_t count, int64_t total,
+                                                       const int64_t* __restrict__ amap,
+                                                       double* __restrict__ L) {
+  __shared__ int s_lo;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = count;  // largest k with nnz_ptr[k] <= e0
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nnz_ptr[mid] <= e0) lo = mid; else hi = mid;
+    }
+    s_lo = lo;
   }
+  __syncthreads();
+  const int64_t e = e0 + threadIdx.x;
+  if (e >= total) return;
+  int lo = s_lo;
+  while (lo + 1 < count && nnz_ptr[lo + 1] <= e) ++lo;
   L[amap[e]] = vals[lo][e - nnz_ptr[lo]];
 }
 
@@ -1830,16 +1844,32 @@ __global__ void k_perm_out(const int64_t* __restrict__ perm, const double* __res
 
 // r = b - A x in the original order (full symmetric CSR, values gathered
 // from the caller's lower-triangle array)
-__global__ void k_residual(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const int64_t* __restrict__ src, const double* __restrict__ vals,
-                           const double* __restrict__ x, int64_t ldx, const double* __restrict__ b,
-                           int64_t ldb, double* __restrict__ r, int64_t ldr, int nrhs) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * nrhs) return;
-  int64_t row = i % n, k = i / n;
-  double acc = 0.0;
-  for (int64_t e = rp[row]; e < rp[row + 1]; ++e) acc += vals[src[e]] * x[k * ldx + ci[e]];
-  r[k * ldr + row] = (b ? b[k * ldb + row] : 0.0) - acc;
+// r[:, k] = b[:, k] - A x[:, k] (b may be null: r = -A x) for up to MAXRHS
+// columns: one thread per row reads the row's entries once and sums every
+// column, entries in CSR order
+__global__ __launch_bounds__(256) void k_residual(int64_t n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci,
+                                                  const int64_t* __restrict__ src,
+                                                  const double* __restrict__ vals,
+                                                  const double* __restrict__ x, int64_t ldx,
+                                                  const double* __restrict__ b, int64_t ldb,
+                                                  double* __restrict__ r, int64_t ldr, int nrhs) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double acc[MAXRHS];
+#pragma unroll
+  for (int q = 0; q < MAXRHS; ++q) acc[q] = 0.0;
+  const int64_t e1 = rp[row + 1];
+  for (int64_t e = rp[row]; e < e1; ++e) {
+    const double a = vals[src[e]];
+    const int64_t c = ci[e];
+#pragma unroll
+    for (int q = 0; q < MAXRHS; ++q)
+      if (q < nrhs) acc[q] += a * x[q * ldx + c];
+  }
+#pragma unroll
+  for (int q = 0; q < MAXRHS; ++q)
+    if (q < nrhs) r[q * ldr + row] = (b ? b[q * ldb + row] : 0.0) - acc[q];
 }
 
 // out[k] += sum_i x[i + k*ldx] * y[i + k*ldy] (block sums added atomically)
@@ -2092,10 +2122,13 @@ void launch_perm_out(const int64_t* perm, const double* y, int64_t ldy, double* 
 void launch_residual(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* src,
                      const double* vals, const double* x, int64_t ldx, const double* b,
                      int64_t ldb, double* r, int64_t ldr, int nrhs, hipStream_t st) {
-  int64_t tot = n * nrhs;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(tot, 256, INT32_MAX)), dim3(256), 0, st, n, rp,
-                     ci, src, vals, x, ldx, b, ldb, r, ldr, nrhs);
+  if (n <= 0) return;
+  for (int c0 = 0; c0 < nrhs; c0 += MAXRHS) {
+    const int nr = std::min(MAXRHS, nrhs - c0);
+    hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, INT32_MAX)), dim3(256), 0, st, n, rp, ci,
+                       src, vals, x + c0 * ldx, ldx, b ? b + c0 * ldb : nullptr, ldb, r + c0 * ldr,
+                       ldr, nr);
+  }
 }
 void launch_absmax(const double* v, int64_t n, int64_t ld, int nrhs, unsigned long long* out,
                    hipStream_t st) {

@@ -1601,10 +1601,11 @@ __global__ __launch_bounds__(256) void k_pair_inverse(const DiagTile* __restrict
 // tiles and the off-diagonal block formed after the factorization), a
 // workgroup of the first chunk forms x_A = V0 y_A, one of the second x_B =
 // W y_A + V1 y_B, redundantly (x stored into z by the half's writer, flags
-// bit 0), then y(rows r0..r1 of the supernode, at most 64) -= L(rows, its
-// chunk) x_chunk: wave g sums columns 16g..16g+15 of a row, the four partial
-// sums meet in LDS; plainly for own rows of a one-chunk step, else with
-// atomics (the other chunk's workgroups and other supernodes add too)
+// bit 0), then y(rows r0..r1 of the supernode) -= L(rows, its chunk) x_chunk
+// in blocks of 64 rows (the next block's entries loaded during the current
+// one): wave g sums columns 16g..16g+15 of a row, the four partial sums meet
+// in LDS; plainly for own rows of a one-chunk step, else with atomics (the
+// other chunk's workgroups and other supernodes add too)
 __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ tiles,
                                                   const int32_t* __restrict__ gl,
                                                   const double* __restrict__ L,
@@ -1625,13 +1626,18 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
   extern __shared__ double fwd_dyn[];
   double* const ys = fwd_dyn;
   double* const xs = fwd_dyn + 128 * nrhs;
-  // this thread's 16 entries of its row, loaded before the chunk solve
-  const int q = t.r0 + row;
-  const int qq = min(q, t.ld - 1);
-  const int gq = gl[t.gl + min(q, t.r1 - 1)];
+  // this thread's 16 entries of its row of a 64-row block (and the row's
+  // index in the full vector), loaded ahead
   double l[16];
+  int gq;
+  auto load_rows = [&](int q0) {
+    const int q = q0 + row;
+    const int qq = min(q, t.ld - 1);
+    gq = gl[t.gl + min(q, t.r1 - 1)];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) l[c] = Lj[(int64_t)(cc + min(16 * cg + c, nbc - 1)) * ld + qq];
+    for (int c = 0; c < 16; ++c) l[c] = Lj[(int64_t)(cc + min(16 * cg + c, nbc - 1)) * ld + qq];
+  };
+  load_rows(t.r0);
   stage_inv(V0, Lj, ld, cc, nbc, tid);
   if (half) stage_w(W, Lj, ld, t.c0, nbB, tid);
   for (int e = tid; e < 128 * nrhs; e += 256) {
@@ -1663,25 +1669,33 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
       if (i < nbc) z[(int64_t)r * ldy + t.f + cc + i] = xs[r * 64 + i];
     }
   double* part = W;  // [cg][r][row], 4 * nrhs * 64 <= 64 * VP doubles
-  for (int r = 0; r < nrhs; ++r) {
-    double a0 = 0.0, a1 = 0.0;
+  for (int q0 = t.r0; q0 < t.r1; q0 += 64) {
+    const int q = q0 + row, gqb = gq;
+    double lb[16];
 #pragma unroll
-    for (int c = 0; c < 16; c += 2) {
-      a0 += l[c] * xs[r * 64 + 16 * cg + c];  // xs is 0 beyond the chunk
-      a1 += l[c + 1] * xs[r * 64 + 16 * cg + c + 1];
+    for (int c = 0; c < 16; ++c) lb[c] = l[c];
+    if (q0 + 64 < t.r1) load_rows(q0 + 64);
+    for (int r = 0; r < nrhs; ++r) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; c += 2) {
+        a0 += lb[c] * xs[r * 64 + 16 * cg + c];  // xs is 0 beyond the chunk
+        a1 += lb[c + 1] * xs[r * 64 + 16 * cg + c + 1];
+      }
+      part[(cg * nrhs + r) * 64 + row] = a0 + a1;
     }
-    part[(cg * nrhs + r) * 64 + row] = a0 + a1;
+    __syncthreads();
+    if (q < t.r1)
+      for (int r = cg; r < nrhs; r += 4) {
+        const double acc = (part[(0 * nrhs + r) * 64 + row] + part[(1 * nrhs + r) * 64 + row]) +
+                           (part[(2 * nrhs + r) * 64 + row] + part[(3 * nrhs + r) * 64 + row]);
+        if (q < t.w && nbB == 0)
+          y[(int64_t)r * ldy + gqb] -= acc;
+        else
+          atomicAdd(&y[(int64_t)r * ldy + gqb], -acc);
+      }
+    __syncthreads();  // the block's partial sums are read before the next block's
   }
-  __syncthreads();
-  if (q < t.r1)
-    for (int r = cg; r < nrhs; r += 4) {
-      const double acc = (part[(0 * nrhs + r) * 64 + row] + part[(1 * nrhs + r) * 64 + row]) +
-                         (part[(2 * nrhs + r) * 64 + row] + part[(3 * nrhs + r) * 64 + row]);
-      if (q < t.w && nbB == 0)
-        y[(int64_t)r * ldy + gq] -= acc;
-      else
-        atomicAdd(&y[(int64_t)r * ldy + gq], -acc);
-    }
 }
 
 // backward, ancestor rows: z(chunk columns) -= L(rows r0..r1, chunk)^T x(glbind rows),

@@ -48,6 +48,8 @@ constexpr int64_t DEVICE_CUS = 256;
 // of them waits on a dependent pair of loads (the row's index, then x), so
 // the blocks a workgroup walks through are kept few
 constexpr int64_t FWD_ROWS = 64;  // rows of a forward-solve workgroup below its chunk
+constexpr int64_t FWD_ROWS_BIG = 256;     // the same in launches of many workgroups
+constexpr int64_t FWD_BIG_LAUNCH = 2048;
 #ifndef BELOW_ROWS
 #define BELOW_ROWS 64
 #endif
@@ -570,6 +572,17 @@ int build_plan(Symbolic& s, std::string& err) {
         steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + SB - 1) / SB);
       for (int64_t k = 0; k < steps; ++k) {
         int64_t start = (int64_t)p.stiles.size();
+        // rows per workgroup: FWD_ROWS, or FWD_ROWS_BIG when the launch would
+        // otherwise hold more than FWD_BIG_LAUNCH workgroups (then each
+        // workgroup's chunk solve serves more rows)
+        int64_t nwg = 0;
+        for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+          int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
+          if (k * SB >= w) continue;
+          const int64_t nb = std::min<int64_t>(SB, w - k * SB), lo = k * SB + nb;
+          nwg += (nb > NB ? 2 : 1) * std::max<int64_t>(1, (m - lo + FWD_ROWS - 1) / FWD_ROWS);
+        }
+        const int64_t rows = nwg > FWD_BIG_LAUNCH ? FWD_ROWS_BIG : FWD_ROWS;
         for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
           int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
           if (k * SB >= w) continue;
@@ -577,11 +590,11 @@ int build_plan(Symbolic& s, std::string& err) {
           t.c0 = (int32_t)(k * SB);
           t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
           int64_t lo = t.c0 + t.nb;
-          int64_t nt = std::max<int64_t>(1, (m - lo + FWD_ROWS - 1) / FWD_ROWS);
+          int64_t nt = std::max<int64_t>(1, (m - lo + rows - 1) / rows);
           for (int32_t half = 0; half < (t.nb > NB ? 2 : 1); ++half)
             for (int64_t i = 0; i < nt; ++i) {
-              t.r0 = (int32_t)std::min<int64_t>(m, lo + FWD_ROWS * i);
-              t.r1 = (int32_t)std::min<int64_t>(m, lo + FWD_ROWS * (i + 1));
+              t.r0 = (int32_t)std::min<int64_t>(m, lo + rows * i);
+              t.r1 = (int32_t)std::min<int64_t>(m, lo + rows * (i + 1));
               t.flags = (i == 0 ? 1 : 0) | (half << 1);
               p.stiles.push_back(t);
             }

@@ -10,11 +10,15 @@
 //    storage: the in-supernode trailing update and the SYRK/GEMM updates
 //    written directly into ancestors (Alg. 5), on MFMA 16x16x4
 //    (FP64, or FP32 operands with FP32 accumulation in the mixed form).
-//  * k_fwd_step / k_bwd_below / k_bwd_step -- supernodal solves in 64-column
-//    steps, the diagonal chunks as products with the stored inv(L_kk).
+//  * k_update_w / k_panel_w / k_tile_inverse_w -- the same work for narrow
+//    items (at most 16 columns), one wavefront each, four per workgroup, for
+//    launches that hold many of them (the batched form).
+//  * k_tile_inverse / k_pair_inverse -- inverses of the diagonal tiles and of
+//    the two-chunk solve steps' diagonal blocks, for the solves.
+//  * k_fwd_step / k_bwd_below / k_bwd_step -- supernodal solves in steps of
+//    two 64-column chunks, the diagonal block as a product with its inverse.
 //  * SpMV residual, norms.
 #include <hip/hip_runtime.h>
-#include <type_traits>
 #include <stdint.h>
 
 #include <algorithm>

@@ -1186,8 +1186,10 @@ __device__ __forceinline__ void update_w_tile(const UpdTile& t, const UpdSeg* __
   v4d acc[NBI];
 #pragma unroll
   for (int bi = 0; bi < NBI; ++bi) acc[bi] = v4d{0, 0, 0, 0};
+  UpdSeg gn = segs[t.seg0];
   for (int e = 0; e < t.nseg; ++e) {
-    const UpdSeg g = segs[t.seg0 + e];
+    const UpdSeg g = gn;
+    if (e + 1 < t.nseg) gn = segs[t.seg0 + e + 1];  // the next record, read ahead
     const bool yin = il >= g.ca && il < g.cb;
     const int64_t yo = g.y + min(max(il - g.ca, 0), g.cb - g.ca - 1);
     bool xin[NBI];
@@ -1200,22 +1202,28 @@ __device__ __forceinline__ void update_w_tile(const UpdTile& t, const UpdSeg* __
     }
 #pragma unroll 1
     for (int k0 = 0; k0 < g.k; k0 += 16) {
-      // all loads of the 16-deep chunk in flight before its products
+      // all loads of the 16-deep chunk in flight before its products; the
+      // 4-deep steps past the contribution's k (uniform) are skipped
+      const int nq = min(4, (g.k - k0 + 3) >> 2);
       double ya[4], xb[4][NBI];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t kc = min(k0 + 4 * q + kl, g.k - 1);
-        ya[q] = L[yo + kc * g.lds];
+        if (q < nq) {
+          const int64_t kc = min(k0 + 4 * q + kl, g.k - 1);
+          ya[q] = L[yo + kc * g.lds];
 #pragma unroll
-        for (int bi = 0; bi < NBI; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
+          for (int bi = 0; bi < NBI; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
+        }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const bool kin = k0 + 4 * q + kl < g.k;
-        const double a = (kin && yin) ? ya[q] : 0.0;
+        if (q < nq) {
+          const bool kin = k0 + 4 * q + kl < g.k;
+          const double a = (kin && yin) ? ya[q] : 0.0;
 #pragma unroll
-        for (int bi = 0; bi < NBI; ++bi)
-          acc[bi] = mfma64(a, (kin && xin[bi]) ? xb[q][bi] : 0.0, acc[bi]);
+          for (int bi = 0; bi < NBI; ++bi)
+            acc[bi] = mfma64(a, (kin && xin[bi]) ? xb[q][bi] : 0.0, acc[bi]);
+        }
       }
     }
   }

@@ -165,6 +165,9 @@ __device__ __forceinline__ void syrk16(double* T, int tp, int q, int p, int b, i
 // inverse of the 16x16 lower-triangular block at (o, o) of T (row pitch tp)
 // into the 16x16 block Io (row pitch ip); lane r (< 16) forms column r by
 // forward substitution, reading row i of L with same-address LDS loads
+// NC < 16 (blocks whose rows from NC on are those of the identity): those
+// rows of the inverse are the identity's and are not computed
+template <int NC = 16>
 __device__ __forceinline__ void inv16(const double* T, int tp, int o, double* Io, int ip,
                                       int lane) {
   const int r = lane & 15;
@@ -172,7 +175,9 @@ __device__ __forceinline__ void inv16(const double* T, int tp, int o, double* Io
   const double* Lo = T + o * tp + o;
   double yv[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = NC; i < 16; ++i) yv[i] = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
     double q0 = (i == r) ? 1.0 : 0.0, q1 = 0.0;
 #pragma unroll
     for (int k = 0; k + 1 < i; k += 2) {
@@ -823,7 +828,12 @@ __global__ __launch_bounds__(256) void k_tile_inverse_w(const DiagTile* __restri
     }
   }
   wave_sync_lds();
-  inv16(T, TP, 0, I, TP, lane);
+  if (nb <= 4)
+    inv16<4>(T, TP, 0, I, TP, lane);
+  else if (nb <= 8)
+    inv16<8>(T, TP, 0, I, TP, lane);
+  else
+    inv16<16>(T, TP, 0, I, TP, lane);
   wave_sync_lds();
   // inv(i, j), i > j, at row j of column i
   for (int e = lane; e < 256; e += 64) {
@@ -877,7 +887,12 @@ __global__ __launch_bounds__(256, 3) void k_panel_w(const PanelTile* __restrict_
       : nb <= 8 ? panel16<false, 8>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr)
                 : panel16<false, 16>(T, TP, 16, Lcs[wave], 0, nb, t.col, lane, 0.0, 0.0, nullptr);
   wave_sync_lds();
-  inv16(T, TP, 0, I, TP, lane);
+  if (nb <= 4)
+    inv16<4>(T, TP, 0, I, TP, lane);
+  else if (nb <= 8)
+    inv16<8>(T, TP, 0, I, TP, lane);
+  else
+    inv16<16>(T, TP, 0, I, TP, lane);
   if (last) {
     if (lane == 0) {
       atomicExch(&counters[t.grp], 0);

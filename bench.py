@@ -1,20 +1,24 @@
 """Benchmark of the RLB supernodal Cholesky hot path on one MI355X.
 
-Workload: 3D 7-point Laplacian on a 48^3 grid (n = 110592), edge weights
-10^U(-2,2), diagonal shift 1e-6 * max diagonal, nested dissection with
-reordering inside supernodes, 4 right-hand sides (seeded synthetic data).
+Default workload: 3D 27-point stencil on a 64^3 grid (n = 262144), weights
+U[0.1, 1], diagonal shift 1e-4, nested dissection with reordering inside
+supernodes, 8 right-hand sides (seeded synthetic data) -- the workload on
+which the FP64 path and the FP32-update form with FP64 refinement are
+compared. --workload lap3d7_48 (the 48^3 7-point workload), batch512 and
+elast3_40 select the others.
 
 One step = one pass of the device hot path in FP64: factor (A-load, then per
 level the POTRF+TRSM of every supernode and its SYRK/GEMM updates written
-straight into ancestor storage), solve of the 4 right-hand sides, and the
-FP64 residual / backward error. The analysis (host symbolic phase) and the
-upload of the integer plan happen once, before timing.
+straight into ancestor storage), solve of the right-hand sides, and the FP64
+residual / backward error. The analysis (host symbolic phase) and the upload
+of the integer plan happen once, before timing.
 
 value = factorization GFLOP/s = F_exact / t_factor, where F_exact is the sum
 over columns of (column count)^2 on the exact structure and t_factor is the
-mean device time of the factor (HIP events on the factor's stream, timed
-steps only). The same matrix is also factored with FP32-operand updates and
-refined in FP64 to backward error <= 1e-14 (reported under "fp32_ir").
+median device time of the factor over the timed steps (HIP events on the
+factor's stream). The same matrix is also factored with FP32-operand updates
+and refined in FP64 to backward error <= 1e-14 ("mixed_ir"); the times to
+solution of both forms are medians over the same number of repetitions.
 
 Prints ONE JSON line.
 """
@@ -66,7 +70,7 @@ def measured_traffic(workload, side):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(A, sym, label, budget_flops=3.0e10):
+def cpu_baseline(A, sym, label, budget_flops=1.0e11):
     """Time the CPU oracle (Algorithm 1, one thread) on a bounded sample of the
     same workload: the first k columns of the factored matrix, whose factor
     columns Algorithm 1 computes exactly on their own."""
@@ -89,7 +93,19 @@ def cpu_baseline(A, sym, label, budget_flops=3.0e10):
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"Algorithm 1 on the first {k} of {A.n} columns of the {label} factor "
                       f"({flops:.3e} flops, {dt:.1f} s, info={info})",
-            "seconds": dt}
+            "seconds": dt, "cpu_model": host_cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -98,10 +114,11 @@ def main():
     ap.add_argument("--steps", type=int, default=7)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--side", type=int, default=48)
-    ap.add_argument("--workload", default="lap3d7_48",
-                    choices=["lap3d7_48", "batch512", "lap3d27_64", "elast3_40"],
-                    help="lap3d7_48 is the headline; the others are the batched form, the "
-                         "27-point 64^3 workload and the 3-dof elasticity workload")
+    ap.add_argument("--workload", default="lap3d27_64",
+                    choices=["lap3d27_64", "lap3d7_48", "batch512", "elast3_40"],
+                    help="lap3d27_64 (default) carries the FP64 vs FP32-update+refinement "
+                         "comparison; the others are the 48^3 7-point workload, the batched "
+                         "form and the 3-dof elasticity workload")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB device to device (calibrates the HBM byte counters)")
@@ -115,6 +132,8 @@ def main():
                     help="launch the factor's kernels one by one instead of replaying a HIP graph")
     ap.add_argument("--prof-reps", type=int, default=3,
                     help="factorizations timed launch by launch for the roofline")
+    ap.add_argument("--mixed-reps", type=int, default=7,
+                    help="timed repetitions of each time to solution (after one untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
@@ -165,6 +184,8 @@ def main():
     def step():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         e0.record(stream)
         num.factor(vals, ws, check=False)
         e1.record(stream)
@@ -172,8 +193,8 @@ def main():
         assert st == 0, f"factor reported info={st}"
         X.copy_(B)
         num.solve(X)
-        be = num.backward_error(B, X)
-        return e0, e1, be
+        be = num.backward_error(B, X)  # synchronizes
+        return e0, e1, be, time.perf_counter() - t0
 
     for _ in range(args.warmup):
         step()
@@ -182,10 +203,11 @@ def main():
     recs = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    fac_ms = [a.elapsed_time(b) for a, b, _ in recs]
+    fac_ms = [r[0].elapsed_time(r[1]) for r in recs]
     be = np.max([r[2] for r in recs], axis=0)
-    t_fac = statistics.mean(fac_ms) / 1e3
+    t_fac = statistics.median(fac_ms) / 1e3
     gflops = F / t_fac / 1e9
+    tts64 = statistics.median([r[3] for r in recs])
 
     # per-launch HIP events on the factor's stream (eager launches of the same
     # kernels) for the roofline of the dominant kernel
@@ -200,7 +222,7 @@ def main():
     n_upd = profs[0]["n_update"]
 
     # dominant kernel: the SYRK/GEMM update tiles (FP64 MFMA)
-    upd_s = statistics.mean(upd_ms) / 1e3
+    upd_s = statistics.median(upd_ms) / 1e3
     # (the algorithmic flops of the tiles these launches run; the previous
     # block's update inside the panel launches is not part of them)
     ach = info["flops_upd_launch"] / upd_s / 1e12
@@ -211,7 +233,7 @@ def main():
             "traffic": measured_traffic(args.workload, args.side),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
             "launches_per_factor": n_upd,
-            "avg_launch_us": round(statistics.mean(upd_ms) / n_upd * 1e3, 2),
+            "avg_launch_us": round(statistics.median(upd_ms) / n_upd * 1e3, 2),
             "alg_flops_per_launch": info["flops_upd_launch"] / n_upd}
 
     out = {
@@ -228,15 +250,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, "").format(side=args.side, n=A.n),
-                   "n": A.n, "nrhs": int(A.rhs.shape[1]), "graph": graph},
+                   "n": A.n, "nrhs": int(A.rhs.shape[1]), "graph": graph,
+                   "timing": f"median of {args.steps} timed steps after {args.warmup} warm-up"},
         "pct_fp64_peak": round(gflops / 1e3 / PEAK_FP64_TFLOPS * 100, 3),
         "factor_ms": round(t_fac * 1e3, 3),
         "factor_ms_min": round(min(fac_ms), 3),
-        "panel_ms": round(statistics.mean(pan_ms), 3),
-        "update_ms": round(statistics.mean(upd_ms), 3),
+        "factor_ms_max": round(max(fac_ms), 3),
+        "panel_ms": round(statistics.median(pan_ms), 3),
+        "update_ms": round(statistics.median(upd_ms), 3),
         "n_panel_launches": profs[0]["n_panel"],
         "flops_exact": F,
         "backward_error": [float(f"{v:.3e}") for v in be],
+        "time_to_solution_ms": round(tts64 * 1e3, 3),
         "analyze_s": round(t_analyze, 3),
         "plan": {k: info[k] for k in ("n_supernodes", "n_levels", "n_launches",
                                       "n_update_tiles", "n_panel_tiles", "n_merged_tiles", "n_split_tiles",
@@ -251,10 +276,12 @@ def main():
         num32 = rlb.Numeric(sym, prec)
         num32.set_graph_mode(graph)
         ws32 = torch.empty_like(ws)
-        ms32, its, tts, be32 = [], [], [], []
-        pcg_from = None
+        X32 = torch.zeros_like(B).T.contiguous().T
+        reps = []
         info32 = 0
-        for rep in range(3):
+        # one untimed repetition (graph capture), then mixed_reps timed ones;
+        # time to solution = factor + first solve + refinement to <= 1e-14
+        for rep in range(1 + args.mixed_reps):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -265,43 +292,35 @@ def main():
             info32 = num32.status()
             if info32 != 0:
                 break
-            X32 = torch.zeros_like(B).T.contiguous().T
+            X32.zero_()
             r = num32.refine(B, X32, tol=1e-14, max_iter=args.max_iter)
             torch.cuda.synchronize()
-            tts.append(time.perf_counter() - t0)
-            ms32.append(e0.elapsed_time(e1))
-            its.append(r["iterations"])
-            pcg_from = r["pcg_from"]
-            be32.append(max(r["backward_error"]))
-        if info32 != 0:
-            ms32 = [e0.elapsed_time(e1)] * 2
-            tts = [float("nan")] * 2
-            its = [None]
-            be32 = [float("nan")]
-        t32 = statistics.mean(ms32[1:]) / 1e3
-        # FP64 time to solution for comparison: factor + solve + residual check
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        num.factor(vals, ws)
-        X.copy_(B)
-        num.solve(X)
-        num.backward_error(B, X)
-        torch.cuda.synchronize()
-        tts64 = time.perf_counter() - t0
+            if rep > 0:
+                reps.append((e0.elapsed_time(e1), time.perf_counter() - t0, r))
         peak_m = PEAK_FP32_TFLOPS if mixed == "fp32" else PEAK_16BIT_TFLOPS
-        out["mixed_ir"] = {"precision": f"{mixed} update operands, FP32 accumulation, FP64 "
-                                        "POTRF/TRSM/storage, FP64 refinement",
-                          "factor_info": info32,
-                          "pivots_patched": num32.pivots_patched() if info32 == 0 else None,
-                          "converged": bool(be32[-1] <= 1e-14),
-                          "factor_gflops": round(F / t32 / 1e9, 2),
-                          "pct_update_precision_peak": round(F / t32 / 1e12 / peak_m * 100, 3),
-                          "pcg_from": pcg_from,
-                          "factor_ms": round(t32 * 1e3, 3),
-                          "ir_iterations": its[-1],
-                          "backward_error": float(f"{max(be32):.3e}"),
-                          "time_to_solution_ms": round(statistics.mean(tts[1:]) * 1e3, 3),
-                          "fp64_time_to_solution_ms": round(tts64 * 1e3, 3)}
+        if info32 != 0 or not reps:
+            out["mixed_ir"] = {"precision": mixed, "factor_info": info32, "converged": False}
+        else:
+            t32 = statistics.median([x[0] for x in reps]) / 1e3
+            tts32 = statistics.median([x[1] for x in reps])
+            be32 = max(max(x[2]["backward_error"]) for x in reps)
+            its = [x[2]["iterations"] for x in reps]
+            out["mixed_ir"] = {
+                "precision": f"{mixed} update operands, FP32 accumulation, FP64 "
+                             "POTRF/TRSM/storage, FP64 refinement",
+                "factor_info": info32,
+                "pivots_patched": num32.pivots_patched(),
+                "converged": bool(all(x[2]["converged"] for x in reps)),
+                "factor_gflops": round(F / t32 / 1e9, 2),
+                "pct_update_precision_peak": round(F / t32 / 1e12 / peak_m * 100, 3),
+                "pcg_from": reps[-1][2]["pcg_from"],
+                "factor_ms": round(t32 * 1e3, 3),
+                "ir_iterations": its[-1],
+                "ir_iterations_all": its,
+                "backward_error": float(f"{be32:.3e}"),
+                "time_to_solution_ms": round(tts32 * 1e3, 3),
+                "fp64_time_to_solution_ms": round(tts64 * 1e3, 3),
+                "timing": f"medians of {len(reps)} repetitions after one untimed, both forms"}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, sym, args.workload)
@@ -344,7 +363,7 @@ def bench_batch(args):
         ms.append(e0.elapsed_time(e1))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    t_fac = statistics.mean(ms) / 1e3
+    t_fac = statistics.median(ms) / 1e3
     # backward error of every member's solve (one RHS each)
     worst = 0.0
     for i, A in enumerate(mats):

@@ -70,6 +70,13 @@ typedef struct rlb_options {
   int32_t precision;        /* RLB_PREC_* used by rlb_numeric_create */
   int32_t panel_spread;     /* panel launches with more 64-row tiles than this give a
                                workgroup several consecutive row tiles; 0 = 512 */
+  int32_t deterministic;    /* 1 (default): no floating-point atomics in the
+                               factorization -- every target tile of an update launch has
+                               one owner that sums its contributions in a fixed order, so
+                               repeated factorizations of the same values give the same
+                               bits, and a batch gives each matrix the bits of its own
+                               factorization; 0: tiles with many contributions are cut
+                               into parts added atomically (rounding order varies) */
 } rlb_options;
 
 typedef struct rlb_info {
@@ -101,7 +108,8 @@ typedef struct rlb_symbolic_s* rlb_symbolic;
 typedef struct rlb_numeric_s* rlb_numeric;
 
 /* Fill *opt with the defaults of the paper: grid ND ordering (grid must still
- * be set), merge cap 0.125, reordering on, maximal blocks on, FP64. */
+ * be set), merge cap 0.125, reordering on, maximal blocks on, FP64; and
+ * deterministic = 1. */
 rlb_status rlb_default_options(rlb_options* opt);
 
 /* Symbolic phase (host only, no device use): ordering, elimination tree,
@@ -172,8 +180,11 @@ rlb_status rlb_factor_pivots_patched(rlb_numeric num, int64_t* count);
 /* Solve A X = B in place with the computed factor (forward solve with L,
  * backward solve with L^T, Section 1 step 4).
  *   B : (device) n x nrhs column-major FP64 in the ORIGINAL order, ld = ldb
- * Uses a library scratch buffer of n*nrhs doubles. Errors: RLB_ERR_ARG,
- * RLB_ERR_STATE (no successful factor), RLB_ERR_HIP. */
+ * Uses a library scratch buffer of n*nrhs doubles (allocated on first use).
+ * If rlb_factor_status has not been called since the last rlb_factor, the
+ * pivot status is read first (this synchronizes the factor's stream once).
+ * Errors: RLB_ERR_ARG, RLB_ERR_STATE (no factor, or the last one failed),
+ * RLB_ERR_HIP. */
 rlb_status rlb_solve(rlb_numeric num, int64_t nrhs, double* B, int64_t ldb, void* stream);
 
 typedef struct rlb_refine_report {
@@ -195,13 +206,16 @@ typedef struct rlb_refine_report {
  * CG restarts from it when the backward error has not halved in 8 steps).
  *   values : (device) the same FP64 values that were factored (for A X)
  *   B, X   : (device) n x nrhs column-major, ORIGINAL order, ld = ld; nrhs <= 16
- * Returns RLB_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not met. */
+ * Like rlb_solve, reads the factor's pivot status first if it has not been
+ * read. Returns RLB_ERR_NOT_CONVERGED (X holds the last iterate) if tol is not
+ * met, RLB_ERR_STATE if the last factorization failed. */
 rlb_status rlb_refine(rlb_numeric num, const double* values, int64_t nrhs, const double* B,
                       double* X, int64_t ld, double tol, int32_t max_iter, void* stream,
                       rlb_refine_report* rep);
 
 /* Backward error ||B - A X||_inf / (||A||_inf ||X||_inf) per column (device
- * FP64 residual; synchronizes). out: (host) nrhs doubles. */
+ * FP64 residual; synchronizes). ||A||_inf is formed from `values` on every
+ * call. out: (host) nrhs doubles. */
 rlb_status rlb_backward_error(rlb_numeric num, const double* values, int64_t nrhs,
                               const double* B, const double* X, int64_t ld, void* stream,
                               double* out);
@@ -229,7 +243,9 @@ rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* work
                             size_t workspace_bytes, void* stream);
 /* info[count] (host): 0 or the failing column of each matrix. Synchronizes. */
 rlb_status rlb_batch_status(rlb_batch b, int64_t* info);
-/* Solve matrix i of the batch in place (B in its original order). */
+/* Solve matrix i of the batch in place (B in its original order). Reads the
+ * batch's statuses first if rlb_batch_status has not been called since the
+ * last rlb_batch_factor; RLB_ERR_STATE if matrix i's factorization failed. */
 rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int64_t ldb,
                            void* stream);
 void rlb_batch_free(rlb_batch b);
@@ -239,7 +255,9 @@ void rlb_batch_free(rlb_batch b);
  * ROOTS aligns the roots, CENTERED shifts each matrix by half the difference.
  * Every schedule gives the same factors; they differ in launch count and
  * balance. rlb_batch_create starts with LEAVES. Synchronizes the device and
- * drops the captured graph. Errors: RLB_ERR_ARG, RLB_ERR_HIP, RLB_ERR_ALLOC. */
+ * drops the captured graph; a factorization already in the workspace stays
+ * valid (the factor storage does not depend on the schedule).
+ * Errors: RLB_ERR_ARG, RLB_ERR_HIP, RLB_ERR_ALLOC. */
 #define RLB_BATCH_SCHED_LEAVES 0
 #define RLB_BATCH_SCHED_ROOTS 1
 #define RLB_BATCH_SCHED_CENTERED 2

@@ -198,10 +198,14 @@ def supernodal_parent(sn_ptr, glb):
 # supernode merging (Section 3.1)
 
 
-def merge_supernodes(fund_ptr, structs, cap=0.125):
+def merge_supernodes(fund_ptr, structs, cap=0.125, trace=None):
     """Greedy child/parent merging with a cumulative storage-growth cap.
 
     Returns (sn_ptr, glbind per merged supernode, added entries, base entries).
+    When `trace` is a list, every decision is appended to it, in order:
+    ("merge", first column of the child, first column of the parent, cost),
+    then ("stop", first column of the child, cost) for the merge that would
+    pass the cap, or ("exhausted",) when no candidate is left.
     """
     S = len(fund_ptr) - 1
     first = np.array(fund_ptr[:-1], np.int64)
@@ -232,11 +236,17 @@ def merge_supernodes(fund_ptr, structs, cap=0.125):
     while True:
         J = int(np.argmin(key))
         if key[J] == INF:
+            if trace is not None:
+                trace.append(("exhausted",))
             break
         cost = int(key[J]) // SHIFT
         if float(added + cost) > cap * float(base):
+            if trace is not None:
+                trace.append(("stop", int(first[J]), cost))
             break
         P = int(par[J])
+        if trace is not None:
+            trace.append(("merge", int(first[J]), int(first[P]), cost))
         added += cost
         # J absorbs P: the merged supernode keeps J's slot
         last[J] = last[P]

@@ -218,11 +218,10 @@ struct rlb_numeric_s {
   unsigned long long* amax = nullptr;
   unsigned long long* smax = nullptr;
   double* L = nullptr;
-  bool factored = false;
+  bool factored = false;        // a factorization was enqueued into L
+  bool status_checked = false;  // its pivot status has been read since
   hipStream_t stream = nullptr;
   SolveScratch sc;
-  double anorm = -1.0;
-  const double* anorm_vals = nullptr;
   // graph replay
   bool graph_mode = false;
   hipGraphExec_t gexec = nullptr;
@@ -277,7 +276,8 @@ struct rlb_batch_s {
   int32_t schedule = -1;         // RLB_BATCH_SCHED_*
   SolveScratch sc;
   double* L = nullptr;
-  bool factored = false;
+  bool factored = false;         // a factorization was enqueued into L
+  std::vector<int64_t> h_info;   // per-matrix status, once read since that factorization
   hipStream_t stream = nullptr;
   bool graph_mode = false;
   hipGraphExec_t gexec = nullptr;
@@ -327,6 +327,7 @@ rlb_status rlb_default_options(rlb_options* o) {
   o->ordering = RLB_ORDER_GRID_ND;
   o->grid[3] = 1;
   o->merge_cap = 0.125;
+  o->deterministic = 1;
   o->reorder = 1;
   o->maximal_blocks = 1;
   o->precision = RLB_PREC_FP64;
@@ -354,6 +355,9 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     ao.precision = opt->precision;
     if (opt->panel_spread < 0) return fail(RLB_ERR_ARG, "bad panel_spread");
     ao.panel_spread = opt->panel_spread ? opt->panel_spread : 512;
+    if (opt->deterministic < 0 || opt->deterministic > 1)
+      return fail(RLB_ERR_ARG, "bad deterministic (0 or 1)");
+    ao.deterministic = opt->deterministic;
   } else {
     ao.ordering = 0;
   }
@@ -573,7 +577,7 @@ rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size
   h->L = (double*)workspace;
   h->stream = st;
   h->factored = false;
-  if (h->anorm_vals != values) h->anorm = -1.0;
+  h->status_checked = false;
   if (h->profiling) {
     size_t need = 2 * s.plan.launches.size();
     while (h->ev.size() < need) {
@@ -636,8 +640,23 @@ rlb_status rlb_factor_status(rlb_numeric h, int64_t* info) {
   HIP_OK(hipMemcpyAsync(&v, h->status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   *info = (v == 0x7fffffff) ? 0 : v;
+  h->status_checked = true;
   if (*info) h->factored = false;
   return (rlb_status)*info;
+}
+
+// rlb_solve and rlb_refine need a successful factor: read the pivot status of
+// the last factorization once (synchronizing its stream) if the caller has
+// not done so through rlb_factor_status
+static rlb_status require_factor(rlb_numeric h) {
+  if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
+  if (!h->status_checked) {
+    int64_t info = 0;
+    rlb_status st = rlb_factor_status(h, &info);
+    if (st < 0) return st;
+    if (info) return fail(RLB_ERR_STATE, "the last factorization failed (matrix not positive definite)");
+  }
+  return RLB_OK;
 }
 
 rlb_status rlb_factor_pivots_patched(rlb_numeric h, int64_t* count) {
@@ -655,7 +674,8 @@ rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* 
   if (!h || nrhs < 0 || (nrhs > 0 && !B)) return fail(RLB_ERR_ARG, "bad argument");
   const Symbolic& s = h->sym->s;
   if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
-  if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
+  rlb_status e = require_factor(h);
+  if (e) return e;
   if (nrhs == 0 || s.n == 0) return RLB_OK;
   return solve_into(s, h->d, h->sc, h->L, nrhs, B, ldb, B, ldb, (hipStream_t)stream);
 }
@@ -665,14 +685,13 @@ rlb_status rlb_backward_error(rlb_numeric h, const double* values, int64_t nrhs,
   if (!h || !values || !B || !X || !out || nrhs < 0) return fail(RLB_ERR_ARG, "bad argument");
   const Symbolic& s = h->sym->s;
   if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
-  if (h->anorm_vals != values) {
-    h->anorm = -1.0;
-    h->anorm_vals = values;
-  }
+  // ||A||_inf is recomputed from `values` on every call (the caller may have
+  // changed them in place since the last one)
+  double anorm = -1.0;
   for (int64_t c0 = 0; c0 < nrhs; c0 += SOLVE_MAXRHS) {
     int nr = (int)std::min<int64_t>(SOLVE_MAXRHS, nrhs - c0);
     rlb_status e = backward_errors(s, h->d, h->sc, values, nr, B + c0 * ld, X + c0 * ld, ld,
-                                   (hipStream_t)stream, out + c0, &h->anorm);
+                                   (hipStream_t)stream, out + c0, &anorm);
     if (e) return e;
   }
   return RLB_OK;
@@ -685,7 +704,8 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
     return fail(RLB_ERR_ARG, "bad argument (1 <= nrhs <= 16)");
   const Symbolic& s = h->sym->s;
   if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
-  if (!h->factored) return fail(RLB_ERR_STATE, "no successful factorization");
+  rlb_status e = require_factor(h);
+  if (e) return e;
   hipStream_t st = (hipStream_t)stream;
   const int nr = (int)nrhs;
   const int64_t n = s.n;
@@ -693,12 +713,9 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
   rlb_refine_report r;
   std::memset(&r, 0, sizeof(r));
   r.pcg_from = -1;
-  rlb_status e = solve_into(s, h->d, sc, h->L, nrhs, B, ld, X, ld, st);
+  e = solve_into(s, h->d, sc, h->L, nrhs, B, ld, X, ld, st);
   if (e) return e;
-  if (h->anorm_vals != values) {
-    h->anorm = -1.0;
-    h->anorm_vals = values;
-  }
+  double anorm = -1.0;  // ||A||_inf of `values`, formed once per call
   // column scalars: r.z, p.(-Ap) and |d| of the last correction
   auto dots = [&](const double* x, const double* y, double* out) -> rlb_status {
     launch_zero_u64(reinterpret_cast<unsigned long long*>(sc.dots), SOLVE_MAXRHS, st);
@@ -722,7 +739,7 @@ rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const d
     zero.v[k] = 0.0;
   }
   for (;;) {
-    e = backward_errors(s, h->d, sc, values, nr, B, X, ld, st, be, &h->anorm);
+    e = backward_errors(s, h->d, sc, values, nr, B, X, ld, st, be, &anorm);
     if (e) return e;
     double worst = 0;
     for (int k = 0; k < nr; ++k) worst = std::max(worst, be[k]);
@@ -872,13 +889,17 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
   // the previous block's update itself (and runs the rest of that step's
   // update beside its workgroups) becomes that step's update launch followed
   // by a plain panel launch -- one merged launch then holds the work of many
-  // matrices, more than one fused launch runs beside its panels
+  // matrices, more than one fused launch runs beside its panels. When every
+  // matrix was analysed deterministic the fused launches are kept, so that
+  // each matrix's tiles run the very arithmetic of its own factorization.
+  bool keep_fused = true;
+  for (int32_t i = 0; i < count; ++i) keep_fused = keep_fused && syms[i]->s.opt.deterministic;
   std::vector<std::vector<Launch>> lists(count);
   for (int32_t i = 0; i < count; ++i) {
     const std::vector<Launch>& L = syms[i]->s.plan.launches;
     for (size_t j = 0; j < L.size(); ++j) {
       Launch l = L[j];
-      if (l.kind == LAUNCH_PANEL && l.pre) {
+      if (l.kind == LAUNCH_PANEL && l.pre && !keep_fused) {
         const bool first = j == 0 || L[j - 1].kind != LAUNCH_PANEL || L[j - 1].level != l.level ||
                            L[j - 1].step != l.step;
         for (size_t q = j; first && q < L.size() && L[q].kind == LAUNCH_PANEL &&
@@ -1141,6 +1162,7 @@ rlb_status rlb_batch_factor(rlb_batch b, const double* const* values, void* work
   }
   HIP_OK(hipGetLastError());
   b->factored = true;
+  b->h_info.clear();
   return RLB_OK;
 }
 
@@ -1153,8 +1175,10 @@ rlb_status rlb_batch_status(rlb_batch b, int64_t* info) {
                         b->stream));
   HIP_OK(hipStreamSynchronize(b->stream));
   rlb_status worst = RLB_OK;
+  b->h_info.assign(count, 0);
   for (int32_t i = 0; i < count; ++i) {
     info[i] = v[i] == 0x7fffffff ? 0 : v[i];
+    b->h_info[i] = info[i];
     if (info[i] && !worst) worst = (rlb_status)info[i];
   }
   return worst;
@@ -1165,6 +1189,12 @@ rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int6
   if (!b || i < 0 || i >= (int32_t)b->syms.size() || nrhs < 0 || (nrhs && !B))
     return fail(RLB_ERR_ARG, "bad argument");
   if (!b->factored) return fail(RLB_ERR_STATE, "no factorization");
+  if (b->h_info.empty()) {  // the statuses of the last factorization, read once
+    std::vector<int64_t> info(b->syms.size());
+    rlb_status e = rlb_batch_status(b, info.data());
+    if (e < 0) return e;
+  }
+  if (b->h_info[i]) return fail(RLB_ERR_STATE, "this matrix's factorization failed");
   const Symbolic& s = b->syms[i]->s;
   if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
   if (nrhs == 0 || s.n == 0) return RLB_OK;
@@ -1176,7 +1206,8 @@ rlb_status rlb_batch_set_schedule(rlb_batch b, int32_t schedule) {
     return fail(RLB_ERR_ARG, "bad schedule");
   if (schedule == b->schedule) return RLB_OK;
   HIP_OK(hipDeviceSynchronize());
-  b->factored = false;
+  // the factor storage of every matrix does not depend on the schedule, so a
+  // factorization already in the workspace stays valid for the solves
   return batch_schedule(b, schedule);
 }
 

@@ -27,6 +27,7 @@
 
 namespace rlb {
 
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -1913,21 +1914,21 @@ __global__ __launch_bounds__(256) void k_residual(int64_t n, const int64_t* __re
     if (q < nrhs) r[q * ldr + row] = (b ? b[q * ldb + row] : 0.0) - acc[q];
 }
 
-// out[k] += sum_i x[i + k*ldx] * y[i + k*ldy] (block sums added atomically)
+// out[k] = sum_i x[i + k*ldx] * y[i + k*ldy]: one workgroup per column, the
+// terms summed in a fixed order (repeated calls give the same bits)
 __global__ void k_dot_cols(const double* __restrict__ x, int64_t ldx, const double* __restrict__ y,
                            int64_t ldy, int64_t n, double* __restrict__ out) {
   __shared__ double red[256];
   const int k = blockIdx.y;
   double a = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    a += x[k * ldx + i] * y[k * ldy + i];
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += x[k * ldx + i] * y[k * ldy + i];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(out + k, red[0]);
+  if (threadIdx.x == 0) out[k] = red[0];
 }
 
 // y[:, k] = a[k] * x[:, k] + b[k] * y[:, k]
@@ -2186,8 +2187,7 @@ void launch_anorm(int64_t n, const int64_t* rp, const int64_t* src, const double
 void launch_dot_cols(const double* x, int64_t ldx, const double* y, int64_t ldy, int64_t n,
                      int nrhs, double* out, hipStream_t st) {
   if (n <= 0 || nrhs <= 0) return;
-  hipLaunchKernelGGL(k_dot_cols, dim3(grid_for(n, 256, 128), nrhs), dim3(256), 0, st, x, ldx, y,
-                     ldy, n, out);
+  hipLaunchKernelGGL(k_dot_cols, dim3(1, nrhs), dim3(256), 0, st, x, ldx, y, ldy, n, out);
 }
 void launch_axpby_cols(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int nrhs,
                        const ColCoef& a, const ColCoef& b, hipStream_t st) {

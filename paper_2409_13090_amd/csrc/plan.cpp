@@ -494,7 +494,7 @@ int build_plan(Symbolic& s, std::string& err) {
         // contribution's k range where needed), each added atomically
         int64_t chunks = 0;
         for (const UpdSeg& g : kv.second) chunks += (g.k + KCH - 1) / KCH;
-        if (chunks <= WG_CHUNKS) {
+        if (chunks <= WG_CHUNKS || s.opt.deterministic) {
           add_tile(t, kv.second, 0, kv.second.size(), false);
           continue;
         }

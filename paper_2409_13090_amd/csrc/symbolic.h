@@ -17,6 +17,9 @@ struct AnalyzeOptions {
   int maximal_blocks = 1;
   int precision = 0;
   int panel_spread = 512;  // row tiles a panel launch spreads over workgroups
+  int deterministic = 1;   // 1: no floating-point atomics in the factorization (every
+                           // target tile has one owner); 0: heavy tiles split, parts
+                           // added atomically
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its

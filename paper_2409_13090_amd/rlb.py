@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("user_perm", _c_i64p), ("grid", ctypes.c_int64 * 4),
                 ("merge_cap", ctypes.c_double), ("reorder", ctypes.c_int32),
                 ("maximal_blocks", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("panel_spread", ctypes.c_int32)]
+                ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -159,7 +159,8 @@ class Symbolic:
     """rlb_analyze: host symbolic phase of a lower-triangle CSC pattern."""
 
     def __init__(self, n, colptr, rowidx, ordering="grid", grid=(0, 0, 0, 1), merge_cap=0.125,
-                 reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0):
+                 reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0,
+                 deterministic=True):
         L = lib()
         self._cp = np.ascontiguousarray(colptr, np.int64)
         self._ri = np.ascontiguousarray(rowidx, np.int64)
@@ -173,6 +174,7 @@ class Symbolic:
         o.reorder = 1 if reorder else 0
         o.maximal_blocks = 1 if maximal_blocks else 0
         o.panel_spread = int(panel_spread)
+        o.deterministic = 1 if deterministic else 0
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)
             o.user_perm = self._up.ctypes.data_as(_c_i64p)

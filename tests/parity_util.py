@@ -71,3 +71,37 @@ def probe_residual(A, perm, gpu_csc, nprobe=4, seed=0):
         r = Ap @ v - L @ (L.T @ v)
         worst = max(worst, np.linalg.norm(r) / (an * np.linalg.norm(v)))
     return worst
+
+
+def stored_lower_positions(sym):
+    """Positions in factor storage of the stored factor entries (the lower
+    trapezoid of every supernode's m x w block), in the column order of
+    rlb_factor_export, with that CSC's colptr and row indices."""
+    sn = sym.array("sn_ptr")
+    off = sym.array("off")
+    gp = sym.array("gl_ptr")
+    gl = sym.array("gl")
+    n = int(sn[-1])
+    pos, rows = [], []
+    cp = np.zeros(n + 1, np.int64)
+    q = 0
+    for J in range(len(sn) - 1):
+        f, w, m = int(sn[J]), int(sn[J + 1] - sn[J]), int(gp[J + 1] - gp[J])
+        g = gl[gp[J]:gp[J + 1]]
+        for c in range(w):
+            pos.append(off[J] + c * m + np.arange(c, m, dtype=np.int64))
+            rows.append(g[c:])
+            q += m - c
+            cp[f + c + 1] = q
+    return np.concatenate(pos), cp, np.concatenate(rows).astype(np.int64)
+
+
+def export_from_storage(sym, storage):
+    """rlb_factor_export's CSC, read from a host copy of factor storage (a
+    batch member's slice of the batch workspace)."""
+    pos, cp, ri = stored_lower_positions(sym)
+    return cp, ri, np.asarray(storage)[pos]
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float64).view(np.uint64)

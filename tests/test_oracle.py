@@ -368,3 +368,97 @@ def test_partition_refinement_invariants(dims, kind):
     assert nb <= nb0
     if kind != "9pt":
         assert nb < nb0
+
+
+def _simulate_merges(fund_ptr, structs, cap):
+    """Section 3.1's merging, simulated from the row sets alone: every
+    supernode is (first column, last column, set of its rows = union of the
+    exact structures of its columns); a candidate is a supernode whose
+    supernodal parent starts right after it; the new fill of a merge is the
+    stored entries of the merged trapezoid minus those of the two parts,
+    counted from the sets (not from a closed-form cost). The candidate of
+    least new fill goes first (ties: smaller first column); the loop ends at
+    the first merge that would take the added entries past cap * base."""
+    import bisect
+
+    def stored(f, l, rows):
+        return sum(len(rows) - bisect.bisect_left(rows, c) for c in range(f, l + 1))
+
+    sns = {}
+    for J in range(len(fund_ptr) - 1):
+        f, l = int(fund_ptr[J]), int(fund_ptr[J + 1]) - 1
+        U = set()
+        for c in range(f, l + 1):
+            U |= set(int(r) for r in structs[c])
+        sns[f] = (f, l, sorted(U))
+    base = sum(stored(*v) for v in sns.values())
+    owner = {}
+    for f, (_, l, _) in sns.items():
+        for c in range(f, l + 1):
+            owner[c] = f
+
+    def parent(f):
+        _, l, U = sns[f]
+        i = bisect.bisect_right(U, l)
+        return owner[U[i]] if i < len(U) else None
+
+    fill_cache = {}
+
+    def fill(fj, fq):
+        key = (sns[fj][1], fj, sns[fq][1], fq)
+        if key not in fill_cache:
+            (_, lj, Uj), (_, lq, Uq) = sns[fj], sns[fq]
+            Um = sorted(set(Uj) | set(Uq))
+            fill_cache[key] = stored(fj, lq, Um) - stored(*sns[fj]) - stored(*sns[fq])
+        return fill_cache[key]
+
+    added = 0
+    seq = []
+    while True:
+        cands = []
+        for f, (_, l, _) in sns.items():
+            q = parent(f)
+            if q is not None and l + 1 == q:
+                cands.append((fill(f, q), f, q))
+        if not cands:
+            seq.append(("exhausted",))
+            break
+        c, fj, fq = min(cands)
+        if added + c > cap * base:
+            seq.append(("stop", fj, c))
+            break
+        seq.append(("merge", fj, fq, c))
+        added += c
+        (_, _, Uj), (_, lq, Uq) = sns.pop(fj), sns.pop(fq)
+        sns[fj] = (fj, lq, sorted(set(Uj) | set(Uq)))
+        for col in range(fj, lq + 1):
+            owner[col] = fj
+    ptr = sorted(sns) + [int(fund_ptr[-1])]
+    return seq, np.array(ptr, np.int64), added, base
+
+
+@pytest.mark.parametrize("dims,kind", [((30, 30, 1), "5pt"), ((20, 17, 1), "9pt"),
+                                       ((12, 11, 10), "7pt"), ((8, 8, 8), "7pt"),
+                                       ((9, 9, 9), "27pt"), ((6, 7, 6), "27pt")])
+def test_merge_selection_order_and_stop_rule(dims, kind):
+    """Pins the order in which the oracle merges supernodes (Section 3.1:
+    least new fill first) and the point where it stops, against a simulation
+    that recomputes every candidate's new fill from the row sets."""
+    A = W.small_grid(kind, dims, seed=2)
+    r0 = osym.analyze(A, merge_cap=0, reorder=False)
+    cp, ri, _ = osym.permute_lower(A.n, A.colptr, A.rowidx, None, r0["perm_post"])
+    structs, _ = osym.column_structures(A.n, cp, ri)
+    fund = r0["fund_ptr"]
+    trace = []
+    sn_ptr, _, added, base = osym.merge_supernodes(fund, structs, 0.125, trace=trace)
+    seq, ptr, added_s, base_s = _simulate_merges(fund, structs, 0.125)
+    assert base == base_s
+    assert len(trace) == len(seq) and sum(1 for t in seq if t[0] == "merge") > 10
+    for step, (got, want) in enumerate(zip(trace, seq)):
+        assert tuple(int(v) if not isinstance(v, str) else v for v in got) == want, step
+    assert seq[-1][0] == "stop" and added + seq[-1][2] > 0.125 * base
+    assert added == added_s <= 0.125 * base
+    assert np.array_equal(sn_ptr, ptr)
+    # the merged partition is the one the analysis reports
+    r = osym.analyze(A, merge_cap=0.125, reorder=False)
+    assert np.array_equal(r["sn_ptr"], ptr)

@@ -187,6 +187,23 @@ rlb_status rlb_factor_pivots_patched(rlb_numeric num, int64_t* count);
  * RLB_ERR_HIP. */
 rlb_status rlb_solve(rlb_numeric num, int64_t nrhs, double* B, int64_t ldb, void* stream);
 
+/* rlb_solve without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same forward/backward solve kernels, with their three work
+ * vectors in a fixed per-GPU library array of 3 x 2^21 doubles (48 MiB, held
+ * by every GPU the library runs on until the process ends) instead of the
+ * lazily allocated per-handle buffers. Calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   B : (device) n x nrhs column-major FP64, ORIGINAL order, ld = ldb; solved
+ *       in place; requires nrhs <= 16 and n * nrhs <= 2^21
+ * The handle's device must be current. Every call on one GPU shares that
+ * GPU's array (the previous call's contents are overwritten; nothing needs to
+ * start at zero): calls that overlap on one GPU -- on different streams or
+ * host threads -- race and must be serialized by the caller.
+ * Errors: RLB_ERR_ARG (sizes beyond the capacity, bad arguments, wrong
+ * device), RLB_ERR_STATE (no factor, or the last one failed), RLB_ERR_HIP. */
+rlb_status rlb_solve_noalloc(rlb_numeric num, int64_t nrhs, double* B, int64_t ldb, void* stream);
+
 typedef struct rlb_refine_report {
   int32_t iterations;       /* refinement steps taken after the first solve */
   int32_t converged;        /* 1 if every column reached tol */

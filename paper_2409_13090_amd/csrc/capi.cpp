@@ -680,6 +680,35 @@ rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* 
   return solve_into(s, h->d, h->sc, h->L, nrhs, B, ldb, B, ldb, (hipStream_t)stream);
 }
 
+rlb_status rlb_solve_noalloc(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* stream) {
+  if (!h || nrhs < 0 || nrhs > SOLVE_MAXRHS || (nrhs > 0 && !B))
+    return fail(RLB_ERR_ARG, "bad argument (0 <= nrhs <= 16)");
+  const Symbolic& s = h->sym->s;
+  if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
+  if (s.n * nrhs > NOALLOC_SOLVE_ELEMS)
+    return fail(RLB_ERR_ARG, "n * nrhs exceeds the allocation-free solve's capacity (2^21)");
+  rlb_status e = require_factor(h);
+  if (e) return e;
+  if (nrhs == 0 || s.n == 0) return RLB_OK;
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev != h->device) return fail(RLB_ERR_ARG, "the handle's device is not the current device");
+  double* base = nullptr;
+  HIP_OK(noalloc_solve_scratch(&base));
+  // the three work vectors, ld = n, views into the device's scratch (not owned)
+  SolveScratch v;
+  v.y = base;
+  v.z = base + NOALLOC_SOLVE_ELEMS;
+  v.x = base + 2 * NOALLOC_SOLVE_ELEMS;
+  hipStream_t st = (hipStream_t)stream;
+  const int nr = (int)nrhs;
+  launch_perm_in(h->d.perm, B, ldb, v.y, s.n, s.n, nr, st);
+  enqueue_solve_levels(s, h->d, h->L, v, nr, st);
+  launch_perm_out(h->d.perm, v.x, s.n, B, ldb, s.n, nr, st);
+  HIP_OK(hipGetLastError());
+  return RLB_OK;
+}
+
 rlb_status rlb_backward_error(rlb_numeric h, const double* values, int64_t nrhs, const double* B,
                               const double* X, int64_t ld, void* stream, double* out) {
   if (!h || !values || !B || !X || !out || nrhs < 0) return fail(RLB_ERR_ARG, "bad argument");

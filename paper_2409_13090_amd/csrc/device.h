@@ -10,6 +10,15 @@ namespace rlb {
 
 constexpr int SOLVE_MAXRHS = 16;
 
+// capacity of each of the three work vectors of the allocation-free solve
+// (n * nrhs doubles): 2^21, e.g. n = 262144 with 8 right-hand sides; 48 MiB
+// in all per GPU
+constexpr int64_t NOALLOC_SOLVE_ELEMS = int64_t(1) << 21;
+
+// device address of the allocation-free solve's work vectors on the current
+// device (looked up once per device)
+hipError_t noalloc_solve_scratch(double** out);
+
 // one coefficient per right-hand-side column, passed by value
 struct ColCoef {
   double v[SOLVE_MAXRHS];

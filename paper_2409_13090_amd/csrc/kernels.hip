@@ -22,11 +22,42 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.h"
 
 namespace rlb {
 
+// Work vectors of the allocation-free solve (rlb_solve_noalloc): three n x
+// nrhs column-major blocks (right-hand side in the factored order, forward
+// solution, backward solution) of at most NOALLOC_SOLVE_ELEMS doubles each.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device memory:
+// only the address hipGetSymbolAddress returns for the current device is
+// passed to kernels.
+static __device__ __align__(256) double scratch[3 * NOALLOC_SOLVE_ELEMS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_solve_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));

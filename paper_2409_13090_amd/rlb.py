@@ -70,7 +70,7 @@ EXPORTED = [
     "rlb_batch_create", "rlb_batch_factor", "rlb_batch_status", "rlb_batch_solve",
     "rlb_batch_free", "rlb_set_graph_mode", "rlb_batch_set_graph_mode", "rlb_set_profiling",
     "rlb_last_profile", "rlb_status_string", "rlb_last_error", "rlb_factor_pivots_patched",
-    "rlb_batch_set_schedule", "rlb_batch_autotune",
+    "rlb_batch_set_schedule", "rlb_batch_autotune", "rlb_solve_noalloc",
 ]
 
 _lib = None
@@ -96,6 +96,7 @@ def lib():
         "rlb_factor": [_vp, _vp, _vp, ctypes.c_size_t, _vp],
         "rlb_factor_status": [_vp, ctypes.POINTER(i64)],
         "rlb_solve": [_vp, i64, _vp, i64, _vp],
+        "rlb_solve_noalloc": [_vp, i64, _vp, i64, _vp],
         "rlb_refine": [_vp, _vp, i64, _vp, _vp, i64, ctypes.c_double, i32, _vp,
                        ctypes.POINTER(RefineReport)],
         "rlb_backward_error": [_vp, _vp, i64, _vp, _vp, i64, _vp, _vp],
@@ -259,6 +260,13 @@ class Numeric:
         storage expected (use B.T.contiguous().T for an (n, nrhs) tensor)."""
         nrhs, ldb = _cm(B)
         _check(lib().rlb_solve(self.h, nrhs, _ptr(B), ldb, _stream(stream)))
+        return B
+
+    def solve_noalloc(self, B, stream=None):
+        """rlb_solve_noalloc: as solve(), with the library's fixed per-GPU work
+        vectors (no device allocation); nrhs <= 16 and n * nrhs <= 2^21."""
+        nrhs, ldb = _cm(B)
+        _check(lib().rlb_solve_noalloc(self.h, nrhs, _ptr(B), ldb, _stream(stream)))
         return B
 
     def refine(self, B, X, tol=1e-14, max_iter=30, values=None, stream=None):

@@ -77,6 +77,14 @@ typedef struct rlb_options {
                                bits, and a batch gives each matrix the bits of its own
                                factorization; 0: tiles with many contributions are cut
                                into parts added atomically (rounding order varies) */
+  int32_t outer_block;      /* columns of the outer block of wide supernodes: the
+                               trailing columns right of an outer block are updated once,
+                               with inner dimension outer_block, after its last 64-column
+                               panel; a multiple of 64; 0 = 256; 64 = after every panel */
+  int32_t big_tile_min;     /* the long updates of a step (trailing updates by an outer
+                               block, updates into ancestors) take 128x128 target tiles
+                               when there are at least this many; <= 0 (default): never
+                               (on the grid workloads the 64x64 tiles are faster) */
 } rlb_options;
 
 typedef struct rlb_info {
@@ -136,9 +144,9 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* out);
  * "diag_tiles" (3 per 64-column step: diagonal offset, ld, nb),
  * "panel_tiles" (11 per workgroup: diagonal offset, ld, nb, nrows, row0,
  * column, status slot, group counter, group size, first row below the
- * diagonal block, number of 64-row tiles from row0) and "launches" (5 per launch:
- * kind 0 panel (POTRF+TRSM) / 1 update, level, step, first tile, tile
- * count). If out is NULL only *len is set. All arrays are returned as int64. */
+ * diagonal block, number of 64-row tiles from row0) and "launches" (12 per
+ * launch: kind 0 panel (POTRF+TRSM) / 1 update, level, step, first tile, tile
+ * count, variant, pre, ustart, ucount, ncount, alt_start, alt_count). If out is NULL only *len is set. All arrays are returned as int64. */
 rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out, int64_t* len);
 
 void rlb_symbolic_free(rlb_symbolic sym);
@@ -148,7 +156,10 @@ void rlb_symbolic_free(rlb_symbolic sym);
  * the 64x64 diagonal-tile POTRF, the panel TRSM, the factor storage and the
  * solves are FP64; the reduced forms change the operands of the SYRK/GEMM
  * updates (the in-supernode trailing updates and the updates written into
- * ancestors), which accumulate in FP32 and are added to FP64 targets.
+ * ancestors), which accumulate in FP32 and are added to FP64 targets. The
+ * FP32 form keeps an FP32 copy of the finished entries below the diagonal
+ * tiles (a library buffer of factor_bytes / 2), from which the updates read
+ * their operands.
  * Errors: RLB_ERR_HIP, RLB_ERR_ALLOC, RLB_ERR_ARG. */
 rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* out);
 
@@ -252,6 +263,8 @@ void rlb_numeric_free(rlb_numeric num);
  *   workspace       : (device) >= rlb_batch_bytes() bytes, caller-owned
  * rlb_batch_create builds the merged plan once; rlb_batch_factor runs it and
  * may be called again with new values. Per-matrix status via rlb_batch_status.
+ * precision must be RLB_PREC_FP64 (RLB_ERR_UNSUPPORTED otherwise: the reduced
+ * forms are single-matrix).
  */
 typedef struct rlb_batch_s* rlb_batch;
 rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t precision,
@@ -301,6 +314,10 @@ rlb_status rlb_batch_set_graph_mode(rlb_batch b, int32_t on);
 rlb_status rlb_set_profiling(rlb_numeric num, int32_t on);
 rlb_status rlb_last_profile(rlb_numeric num, double* update_ms, double* panel_ms,
                             int64_t* n_update, int64_t* n_panel);
+/* The same profiled factorization launch by launch, in the order of the
+ * "launches" array (ms may be NULL; on entry *count is its capacity, on
+ * return the number of launches). */
+rlb_status rlb_last_profile_launches(rlb_numeric num, double* ms, int64_t* count);
 
 const char* rlb_status_string(rlb_status s);
 const char* rlb_last_error(void);

@@ -217,6 +217,7 @@ struct rlb_numeric_s {
   int64_t* dsrc = nullptr;
   unsigned long long* amax = nullptr;
   unsigned long long* smax = nullptr;
+  float* Ls = nullptr;  // FP32-update form: FP32 copy of the finished factor entries
   double* L = nullptr;
   bool factored = false;        // a factorization was enqueued into L
   bool status_checked = false;  // its pivot status has been read since
@@ -233,6 +234,7 @@ struct rlb_numeric_s {
   std::vector<hipEvent_t> ev;
   double prof_update_ms = 0, prof_panel_ms = 0;
   int64_t prof_nupd = 0, prof_npan = 0;
+  std::vector<double> prof_launch_ms;  // every launch of the plan, in order
   ~rlb_numeric_s() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -244,6 +246,7 @@ struct rlb_numeric_s {
     dfree(dsrc);
     dfree(amax);
     dfree(smax);
+    dfree(Ls);
   }
 };
 
@@ -358,6 +361,10 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     if (opt->deterministic < 0 || opt->deterministic > 1)
       return fail(RLB_ERR_ARG, "bad deterministic (0 or 1)");
     ao.deterministic = opt->deterministic;
+    if (opt->outer_block < 0 || opt->outer_block % 64)
+      return fail(RLB_ERR_ARG, "bad outer_block (a multiple of 64)");
+    ao.outer_block = opt->outer_block ? opt->outer_block : 256;
+    ao.big_tile_min = opt->big_tile_min;
   } else {
     ao.ordering = 0;
   }
@@ -468,11 +475,12 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       tmp.insert(tmp.end(), v, v + 11);
     }
   } else if (w == "launches") {
-    // kind, level, step, start, count, variant, pre, ustart, ucount, ncount
+    // kind, level, step, start, count, variant, pre, ustart, ucount, ncount,
+    // alt_start, alt_count
     for (const Launch& l : s.plan.launches) {
-      int64_t v[10] = {l.kind,  l.level, l.step,   l.start,  l.count,
-                       l.variant, l.pre, l.ustart, l.ucount, l.ncount};
-      tmp.insert(tmp.end(), v, v + 10);
+      int64_t v[12] = {l.kind,    l.level,  l.step,   l.start,     l.count,     l.variant,
+                       l.pre,     l.ustart, l.ucount, l.ncount, l.alt_start, l.alt_count};
+      tmp.insert(tmp.end(), v, v + 12);
     }
   }
   else return fail(RLB_ERR_ARG, "unknown array " + w);
@@ -522,6 +530,8 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
     HIP_OK(hipMalloc((void**)&h->smax,
                      sizeof(unsigned long long) * std::max<int32_t>(1, s.plan.n_scale_slots)));
   }
+  if (precision == RLB_PREC_FP32_UPDATES)
+    HIP_OK(hipMalloc((void**)&h->Ls, sizeof(float) * std::max<int64_t>(1, s.plan.l_elems)));
   *out = h.release();
   return RLB_OK;
 }
@@ -544,17 +554,22 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   size_t ei = 0;
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
+    hipStream_t ls = st;
     if (l.kind == LAUNCH_UPDATE) {
-      launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
-                    l.variant != 0, st, l.nwave);
+      if (l.variant == UPD_BIG && h->precision >= RLB_PREC_BF16_UPDATES)
+        launch_update(h->d.updates + l.alt_start, h->d.segs, l.alt_count, L, h->precision,
+                      h->smax, UPD_TILE, ls, 0);
+      else
+        launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
+                      l.variant, ls, l.nwave, h->Ls);
     } else {
       launch_panel(h->d.panels + l.start, l.count, L, h->status, h->counters, pmode, l.variant,
                    l.pre != 0, h->thr, h->amax, u, h->smax, nfixed, h->d.updates + l.ustart,
-                   h->d.segs, l.ucount, st);
+                   h->d.segs, l.ucount, ls, h->Ls);
       // the 16-bit forms run the fused update tiles as a launch of their own
       if (pmode == 2 && l.ucount)
         launch_update(h->d.updates + l.ustart, h->d.segs, l.ucount, L, h->precision, h->smax,
-                      false, st);
+                      UPD_TILE, ls);
     }
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
   }
@@ -590,10 +605,12 @@ rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size
     HIP_OK(hipStreamSynchronize(st));
     h->prof_update_ms = h->prof_panel_ms = 0;
     h->prof_nupd = h->prof_npan = 0;
+    h->prof_launch_ms.clear();
     size_t ei = 0;
     for (const Launch& l : s.plan.launches) {
       float ms = 0;
       HIP_OK(hipEventElapsedTime(&ms, h->ev[ei], h->ev[ei + 1]));
+      h->prof_launch_ms.push_back(ms);
       ei += 2;
       if (l.kind == LAUNCH_UPDATE) {
         h->prof_update_ms += ms;
@@ -870,6 +887,15 @@ rlb_status rlb_factor_export(rlb_numeric h, int64_t* colptr, int64_t* rowidx, do
   return RLB_OK;
 }
 
+rlb_status rlb_last_profile_launches(rlb_numeric h, double* ms, int64_t* count) {
+  if (!h || !count) return fail(RLB_ERR_ARG, "null argument");
+  const int64_t n = (int64_t)h->prof_launch_ms.size();
+  if (ms)
+    for (int64_t i = 0; i < std::min(n, *count); ++i) ms[i] = h->prof_launch_ms[i];
+  *count = n;
+  return RLB_OK;
+}
+
 void rlb_numeric_free(rlb_numeric h) { delete h; }
 
 rlb_status rlb_set_graph_mode(rlb_numeric h, int32_t on) {
@@ -935,7 +961,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
                            L[q].level == l.level && L[q].step == l.step;
              ++q)
           if (L[q].ucount + L[q].ncount > 0)
-            lists[i].push_back(Launch{LAUNCH_UPDATE, l.level, l.step - 1, 1, L[q].ustart,
+            lists[i].push_back(Launch{LAUNCH_UPDATE, l.level, l.step - 1, UPD_SHORT, L[q].ustart,
                                       L[q].ucount + L[q].ncount, 0, 0, 0, 0, 0});
         l.pre = 0;
         l.ustart = l.ucount = l.ncount = 0;
@@ -958,7 +984,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       if (cur[i] >= L.size()) continue;
       const Launch& l = L[cur[i]];
       const int32_t lv = l.level + shift[i];
-      const int32_t vv = l.kind == LAUNCH_PANEL ? l.variant : 0;
+      const int32_t vv = l.variant;
       const int32_t pp = l.kind == LAUNCH_PANEL ? l.pre : 0;
       if (!any ||
           std::make_tuple(lv, l.step, l.kind, vv, pp) < std::make_tuple(bl, bs, bk, bv, bp)) {
@@ -971,7 +997,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       }
     }
     if (!any) break;
-    Launch m{bk, bl, bs, bk == LAUNCH_PANEL ? bv : 1, 0, 0, bp, 0, 0, 0, 0};
+    Launch m{bk, bl, bs, bv, 0, 0, bp, 0, 0, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
     std::vector<UpdTile> narrow;  // update launch: the narrow tiles, placed last
     m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
@@ -980,9 +1006,8 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       const Plan& p = syms[i]->s.plan;
       if (cur[i] >= lists[i].size()) continue;
       const Launch& l = lists[i][cur[i]];
-      if (l.level + shift[i] != bl || l.step != bs || l.kind != bk) continue;
-      if (bk == LAUNCH_PANEL && (l.variant != bv || l.pre != bp)) continue;
-      if (bk == LAUNCH_UPDATE) m.variant &= l.variant;
+      if (l.level + shift[i] != bl || l.step != bs || l.kind != bk || l.variant != bv) continue;
+      if (bk == LAUNCH_PANEL && l.pre != bp) continue;
       if (bk != LAUNCH_UPDATE) {
         int32_t g_hi = 0;
         for (int64_t t = 0; t < l.count; ++t) {
@@ -1008,7 +1033,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
           UpdTile ut = p.updates[l.start + t];
           ut.c += b->base[i];
           ut.seg0 += (int32_t)segbase[i];
-          if (ut.n <= NARROW_COLS)
+          if (ut.n <= NARROW_COLS && bv != UPD_BIG)
             narrow.push_back(ut);
           else
             b->updates.push_back(ut);
@@ -1047,8 +1072,8 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
   if (count < 1 || !syms || !out) return fail(RLB_ERR_ARG, "bad argument");
   if (precision < RLB_PREC_FP64 || precision > RLB_PREC_FP16_UPDATES)
     return fail(RLB_ERR_ARG, "bad precision");
-  if (precision > RLB_PREC_FP32_UPDATES)
-    return fail(RLB_ERR_UNSUPPORTED, "16-bit update forms are single-matrix only");
+  if (precision != RLB_PREC_FP64)
+    return fail(RLB_ERR_UNSUPPORTED, "the batched form is FP64 (reduced forms are single-matrix)");
   *out = nullptr;
   std::unique_ptr<rlb_batch_s> b(new rlb_batch_s());
   b->precision = precision;
@@ -1124,7 +1149,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
-                    l.variant != 0, st, l.nwave);
+                    l.variant, st, l.nwave);
     else {
       // the batch factors with the FP64 panel kernel; its fused update tiles
       // run inside it in the FP64 form and as a short launch of their own in
@@ -1135,7 +1160,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
                    b->d_updates + l.ustart, b->d_segs, inside ? l.ucount : 0, st);
       if (!inside && l.ucount)
         launch_update(b->d_updates + l.ustart, b->d_segs, l.ucount, L, b->precision, nullptr,
-                      true, st);
+                      UPD_SHORT, st);
     }
   }
   const int cls_nbb[3] = {1, 2, 4};

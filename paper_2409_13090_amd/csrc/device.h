@@ -39,10 +39,12 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   int precision, int nbb, bool pre, const double* thr,
                   const unsigned long long* amax, double ufix, unsigned long long* smax,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
-                  int64_t ucount, hipStream_t st);
+                  int64_t ucount, hipStream_t st, float* Ls = nullptr);
+// variant: UPD_TILE, UPD_SHORT or UPD_BIG (128x128 tiles; FP64 and FP32 forms)
+// Ls: the FP32 copy of the finished factor entries (operands of the FP32 form)
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st,
-                   int64_t nwave = 0);
+                   int precision, const unsigned long long* smax, int variant, hipStream_t st,
+                   int64_t nwave = 0, const float* Ls = nullptr);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
 // the off-diagonal inverse blocks of the two-chunk solve steps (after

@@ -282,8 +282,8 @@ constexpr int KC = 16;  // K chunk staged per LDS buffer
 // are LDS stages of 2 x KC x 64 elements each.
 template <typename T>
 __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g,
-                                               double* __restrict__ L, T (*sX)[KC][64],
-                                               T (*sY)[KC][64]) {
+                                               double* __restrict__ L, const T* __restrict__ S,
+                                               T (*sX)[KC][64], T (*sY)[KC][64]) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -295,12 +295,12 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
   const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
   const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
   const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
-  double xr[16], yr[16];
+  T xr[16], yr[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int64_t kk = min(lk + 4 * q, g.k - 1);
-    xr[q] = L[xo + kk * g.lds];
-    yr[q] = L[yo + kk * g.lds];
+    xr[q] = S[xo + kk * g.lds];
+    yr[q] = S[yo + kk * g.lds];
   }
   double cv[2][2][4];
 #pragma unroll
@@ -327,8 +327,8 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
       for (int u = 0; u < KC / 4; ++u) {
         const int q = 4 * c + u;
         const bool kin = lk + 4 * q < g.k;
-        sX[buf][lk + 4 * u][lr] = (T)((kin && xin) ? xr[q] : 0.0);
-        sY[buf][lk + 4 * u][lr] = (T)((kin && yin) ? yr[q] : 0.0);
+        sX[buf][lk + 4 * u][lr] = (kin && xin) ? xr[q] : T(0);
+        sY[buf][lk + 4 * u][lr] = (kin && yin) ? yr[q] : T(0);
       }
       __syncthreads();
 #pragma unroll
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     int* __restrict__ counters, const double* __restrict__ thr,
     const unsigned long long* __restrict__ amax, double ufix, unsigned long long* __restrict__ smax,
     unsigned int* __restrict__ nfixed, const UpdTile* __restrict__ utiles,
-    const UpdSeg* __restrict__ usegs, int npanel) {
+    const UpdSeg* __restrict__ usegs, int npanel, float* __restrict__ Ls) {
   constexpr int TR = 16 * NBB;  // tile rows and columns
   constexpr int TPn = TR + 1;   // LDS row pitch of the tile images
   // LDS carve (doubles): the tile T (row-major), the inverses of its 16x16
@@ -584,7 +584,13 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     typedef typename PanelUpd<MODE>::type UT;
     UT* su = reinterpret_cast<UT*>(smem);
     const UpdTile ut = utiles[blockIdx.x - npanel];
-    upd_short_tile<UT>(ut, usegs[ut.seg0], L, reinterpret_cast<UT(*)[KC][64]>(su),
+    // operands: the FP64 factor, or its FP32 copy in the FP32-update form
+    const UT* S;
+    if constexpr (MODE == 1)
+      S = Ls;
+    else
+      S = L;
+    upd_short_tile<UT>(ut, usegs[ut.seg0], L, S, reinterpret_cast<UT(*)[KC][64]>(su),
                        reinterpret_cast<UT(*)[KC][64]>(su + 2 * KC * 64));
     return;
   }
@@ -802,6 +808,9 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
           const int c = 16 * b + 4 * v + (lane >> 4);
           const bool ok = c < nb && rr < nrt_rows;
           if (ok) D[(int64_t)c * ldi + row0 + rr] = x[v];
+          // the FP32-update form keeps an FP32 copy of every finished entry
+          // below the diagonal tiles: the operands of all later updates
+          if (MODE == 1 && ok) Ls[t.diag + (int64_t)c * ldi + row0 + rr] = (float)x[v];
           if (MODE == 2) {
             // |x| of a non-negative double orders like its bit pattern
             const double ax = ok ? fabs(x[v]) : 0.0;
@@ -1052,7 +1061,7 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles,
                                                 const UpdSeg* __restrict__ segs,
-                                                double* __restrict__ L) {
+                                                double* __restrict__ L, const T* __restrict__ S) {
   typedef typename Mfma<T>::acc_t acc_t;
   const UpdTile t = tiles[blockIdx.x];
   __shared__ T sX[2][KC][64];  // [k][tile row]
@@ -1095,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
   // are unconditional (clamped addresses) and the zero mask is applied when
   // the chunk is written to LDS, so the loads stay in flight during the
   // multiplication of the previous chunk.
-  double xr[KC / 4], yr[KC / 4];
+  T xr[KC / 4], yr[KC / 4];
   bool xin = false, yin = false;
   int kvalid = 0;  // k offsets (relative to this thread's first k) still inside the contribution
   auto fetch = [&](const UpdSeg& g, int k0) {
@@ -1107,16 +1116,16 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q) {
       const int64_t kk = min(k0 + lk + 4 * q, g.k - 1);
-      xr[q] = L[xo + kk * g.lds];
-      yr[q] = L[yo + kk * g.lds];
+      xr[q] = S[xo + kk * g.lds];
+      yr[q] = S[yo + kk * g.lds];
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q) {
       const bool kin = 4 * q < kvalid;
-      sX[buf][lk + 4 * q][lr] = (T)((kin && xin) ? xr[q] : 0.0);
-      sY[buf][lk + 4 * q][lr] = (T)((kin && yin) ? yr[q] : 0.0);
+      sX[buf][lk + 4 * q][lr] = (kin && xin) ? xr[q] : T(0);
+      sY[buf][lk + 4 * q][lr] = (kin && yin) ? yr[q] : T(0);
     }
   };
   auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
@@ -1203,8 +1212,8 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
       }
 }
 
-template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*);
-template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*);
+template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*, const double*);
+template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*, const float*);
 
 // Update of narrow target tiles (at most 64 rows and 16 columns: the targets
 // in small supernodes), one wavefront per tile and four tiles per
@@ -1309,15 +1318,184 @@ __global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_short(const UpdTile* __restrict__ tiles,
                                                       const UpdSeg* __restrict__ segs,
-                                                      double* __restrict__ L) {
+                                                      double* __restrict__ L,
+                                                      const T* __restrict__ S) {
   __shared__ T sX[2][KC][64];
   __shared__ T sY[2][KC][64];
   const UpdTile t = tiles[blockIdx.x];
-  upd_short_tile<T>(t, segs[t.seg0], L, sX, sY);
+  upd_short_tile<T>(t, segs[t.seg0], L, S, sX, sY);
 }
 
-template __global__ void k_update_short<double>(const UpdTile*, const UpdSeg*, double*);
-template __global__ void k_update_short<float>(const UpdTile*, const UpdSeg*, double*);
+template __global__ void k_update_short<double>(const UpdTile*, const UpdSeg*, double*,
+                                                const double*);
+template __global__ void k_update_short<float>(const UpdTile*, const UpdSeg*, double*,
+                                               const float*);
+
+// C -= sum of X * Y^T on a 128x128 target tile (the updates of launches with
+// many long contributions: the trailing updates of wide supernodes after a
+// 256-column outer block, and the SYRK/GEMM updates into ancestors at the
+// upper levels). Against the 64x64 tile of k_update this halves the operand
+// bytes per flop (16 flop per byte staged in FP64). Four wavefronts, each a
+// 64x64 quadrant held as 4 x 4 MFMA 16x16 accumulators; K is staged through
+// LDS in chunks of 16 (the next chunk's loads in flight during the current
+// chunk's 64 MFMAs per wavefront); thread (row, k parity) stages one tile
+// row for 8 values of k, a wavefront's loads of one k being 64 consecutive
+// rows of a source column. Blocks of a quadrant outside a contribution's
+// rectangle, and blocks of a diagonal tile above its diagonal, are skipped.
+// The target is read and written once, in the epilogue (one owner), or its
+// parts are added with atomics (a split tile).
+constexpr int BT = 128;  // big target tile
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_update_big(const UpdTile* __restrict__ tiles,
+                                                       const UpdSeg* __restrict__ segs,
+                                                       double* __restrict__ L,
+                                                       const T* __restrict__ S) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T sX[2][KC][BT];  // [k][tile row]
+  __shared__ T sY[2][KC][BT];  // [k][tile column]
+  const UpdTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;  // this wave's quadrant
+  const int lr = tid & 127, lk = tid >> 7;                // staging: row lr, k = lk + 2q
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+
+  acc_t acc[4][4];  // [column block][row block]
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  T xr[KC / 2], yr[KC / 2];
+  bool xin = false, yin = false;
+  int kvalid = 0;
+  auto fetch = [&](const UpdSeg& g, int k0) {
+    xin = lr >= g.ra && lr < g.rb;
+    yin = lr >= g.ca && lr < g.cb;
+    kvalid = g.k - k0 - lk;
+    const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+    const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
+#pragma unroll
+    for (int q = 0; q < KC / 2; ++q) {
+      const int64_t kk = min(k0 + lk + 2 * q, g.k - 1);
+      xr[q] = S[xo + kk * g.lds];
+      yr[q] = S[yo + kk * g.lds];
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < KC / 2; ++q) {
+      const bool kin = 2 * q < kvalid;
+      sX[buf][lk + 2 * q][lr] = (kin && xin) ? xr[q] : T(0);
+      sY[buf][lk + 2 * q][lr] = (kin && yin) ? yr[q] : T(0);
+    }
+  };
+  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
+  int e = 0, k0 = 0;
+  UpdSeg g = seg_at(0);
+  fetch(g, 0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (;;) {
+    // the quadrant's 16-row and 16-column blocks that meet the rectangle
+    const int bi0 = max(0, (g.ra - wr) >> 4), bi1 = min(4, (g.rb - wr + 15) >> 4);
+    const int bj0 = max(0, (g.ca - wc) >> 4), bj1 = min(4, (g.cb - wc + 15) >> 4);
+    // a diagonal tile: block (bj, bi) lies above the diagonal when its last
+    // row is above its first column
+    const bool full = bi0 == 0 && bi1 == 4 && bj0 == 0 && bj1 == 4 && (!diag || wr >= wc + 48);
+    int ne = e, nk0 = k0 + KC;
+    if (nk0 >= g.k) {
+      ne = e + 1;
+      nk0 = 0;
+    }
+    const bool more = ne < t.nseg;
+    UpdSeg gn = g;
+    if (more) {
+      if (ne != e) gn = seg_at(ne);
+      fetch(gn, nk0);
+    }
+    if (full) {
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        T a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = sY[buf][kk][wc + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = sX[buf][kk][wr + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[j][i] = Mfma<T>::op(a[j], b[i], acc[j][i]);
+      }
+    } else if (bi0 < bi1 && bj0 < bj1) {
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        T a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = sY[buf][kk][wc + 16 * j + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = sX[buf][kk][wr + 16 * i + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (i >= bi0 && i < bi1 && j >= bj0 && j < bj1 &&
+                (!diag || wr + 16 * i + 15 >= wc + 16 * j))
+              acc[j][i] = Mfma<T>::op(a[j], b[i], acc[j][i]);
+      }
+    }
+    if (!more) break;
+    stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    e = ne;
+    k0 = nk0;
+    g = gn;
+  }
+  // epilogue, one column block at a time: acc[bj][bi][v] is the update of
+  // target row wr+16*bi+(lane&15), column wc+16*bj+drow(lane,v)
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    if (diag && wr + 63 < wc + 16 * bj) continue;  // the whole column block is above
+    double cv[4][4];
+    if (!atomic) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
+          cv[bi][v] = C[(int64_t)col * ldc + row];
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
+        if (row < t.m && col < t.n && (!diag || row >= col)) {
+          double* p = C + (int64_t)col * ldc + row;
+          if (atomic)
+            atomicAdd(p, -(double)acc[bj][bi][v]);
+          else
+            *p = cv[bi][v] - (double)acc[bj][bi][v];
+        }
+      }
+  }
+}
+
+template __global__ void k_update_big<double>(const UpdTile*, const UpdSeg*, double*,
+                                              const double*);
+template __global__ void k_update_big<float>(const UpdTile*, const UpdSeg*, double*,
+                                             const float*);
 
 // 16-bit operand form of the update. Every contribution's X and Y are scaled
 // by the power of two s = 2^e of its source panel (e chosen so that the
@@ -2056,24 +2234,24 @@ static void launch_panel_n(const PanelTile* tiles, int64_t count, double* L, int
                            int* counters, int mode, const double* thr,
                            const unsigned long long* amax, double ufix, unsigned long long* smax,
                            unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
-                           int64_t ucount, hipStream_t st) {
+                           int64_t ucount, float* Ls, hipStream_t st) {
   const int np = (int)count;
   const dim3 b(256);
   if (mode == 0)
     hipLaunchKernelGGL((k_panel<0, NBB, PRE>), dim3((unsigned)(count + ucount)), b, 0, st, tiles,
-                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
+                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np, Ls);
   else if (mode == 1)
     hipLaunchKernelGGL((k_panel<1, NBB, PRE>), dim3((unsigned)(count + ucount)), b, 0, st, tiles,
-                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
+                       L, status, counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np, Ls);
   else
     hipLaunchKernelGGL((k_panel<2, NBB, PRE>), dim3((unsigned)count), b, 0, st, tiles, L, status,
-                       counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np);
+                       counters, thr, amax, ufix, smax, nfixed, utiles, usegs, np, Ls);
 }
 void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status, int* counters,
                   int precision, int nbb, bool pre, const double* thr,
                   const unsigned long long* amax, double ufix, unsigned long long* smax,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
-                  int64_t ucount, hipStream_t st) {
+                  int64_t ucount, hipStream_t st, float* Ls) {
   if (count <= 0) return;
   if (precision == 2 || nbb < 4) ucount = 0;  // (the plan fuses into 64-column launches only)
   if (precision == 0 && nbb <= 1 && !pre && count >= WAVE_SPLIT_MIN) {
@@ -2085,7 +2263,7 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
   }
 #define RLB_PANEL_N(N, P)                                                                       \
   launch_panel_n<N, P>(tiles, count, L, status, counters, precision, thr, amax, ufix, smax, nfixed, \
-                       utiles, usegs, ucount, st)
+                       utiles, usegs, ucount, Ls, st)
   if (nbb <= 1) {
     if (pre) RLB_PANEL_N(1, true);
     else RLB_PANEL_N(1, false);
@@ -2111,9 +2289,21 @@ void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* 
     hipLaunchKernelGGL(k_tile_inverse<4>, g, b, 0, st, tiles, L);
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
-                   int precision, const unsigned long long* smax, bool shortk, hipStream_t st,
-                   int64_t nwave) {
+                   int precision, const unsigned long long* smax, int variant, hipStream_t st,
+                   int64_t nwave, const float* Ls) {
   if (count <= 0) return;
+  if (variant == UPD_BIG) {
+    // 128x128 target tiles: FP64 or FP32 operands (the 16-bit forms run the
+    // same work from its 64x64 tiling)
+    if (precision == 1)
+      hipLaunchKernelGGL(k_update_big<float>, dim3((unsigned)count), dim3(256), 0, st, tiles, segs,
+                         L, Ls);
+    else
+      hipLaunchKernelGGL(k_update_big<double>, dim3((unsigned)count), dim3(256), 0, st, tiles,
+                         segs, L, (const double*)L);
+    return;
+  }
+  const bool shortk = variant == UPD_SHORT;
   if (precision == 0 && nwave >= WAVE_SPLIT_MIN) {
     // the last nwave tiles are narrow: one wavefront each (a launch of its
     // own pays off for many of them, as in the merged launches of a batch)
@@ -2126,17 +2316,17 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
   const dim3 g((unsigned)count), b(256);
   if (shortk && precision <= 1) {
     if (precision == 1)
-      hipLaunchKernelGGL(k_update_short<float>, g, b, 0, st, tiles, segs, L);
+      hipLaunchKernelGGL(k_update_short<float>, g, b, 0, st, tiles, segs, L, Ls);
     else
-      hipLaunchKernelGGL(k_update_short<double>, g, b, 0, st, tiles, segs, L);
+      hipLaunchKernelGGL(k_update_short<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
   } else if (precision == 1)
-    hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L);
+    hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L, Ls);
   else if (precision == 2)
     hipLaunchKernelGGL(k_update16<2>, g, b, 0, st, tiles, segs, L, smax);
   else if (precision == 3)
     hipLaunchKernelGGL(k_update16<3>, g, b, 0, st, tiles, segs, L, smax);
   else
-    hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L);
+    hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
 }
 // pivot thresholds of the reduced-precision forms: thr[j] = u * A_jj, and the
 // largest diagonal entry (bit pattern; all positive on an SPD input)

@@ -19,6 +19,7 @@
 // contributions of all supernodes that touch the tile and writes it once.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <map>
 #include <tuple>
 
@@ -40,6 +41,14 @@ constexpr double PANEL_US[3] = {6.0, 10.0, 16.0};
 constexpr int64_t PANEL_SLOTS[3] = {3 * 256, 2 * 256, 256};
 constexpr double LAUNCH_US = 4.0;
 constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a tile is split
+// Two-level blocking of wide supernodes (options.outer_block, 256 by
+// default): the trailing update of the columns right of an outer block is
+// applied once, with k = the outer block's width, after its last 64-column
+// panel; inside the outer block every panel updates only the outer block's
+// remaining columns (k = 64). The long updates of a step go to 128x128
+// target tiles (k_update_big) when there are at least options.big_tile_min
+// of them (256 by default: about one per compute unit).
+constexpr int64_t BIG = 128;
 // fusion of a step's trailing update into the next panel launch: compute
 // units of the device, and short update tiles one unit runs while the panel
 // workgroups factor (one resident workgroup per unit in a fused launch)
@@ -96,6 +105,13 @@ double seg_exec_flops(int64_t ra, int64_t rb, int64_t ca, int64_t cb, int64_t k)
 int build_plan(Symbolic& s, std::string& err) {
   Plan& p = s.plan;
   p = Plan();
+  if (s.opt.outer_block < NB || s.opt.outer_block % NB) {
+    err = "outer_block must be a positive multiple of 64";
+    return -1;
+  }
+  const int64_t NBO = s.opt.outer_block;
+  const int64_t MIN_BIG_TILES =
+      s.opt.big_tile_min > 0 ? s.opt.big_tile_min : std::numeric_limits<int64_t>::max();
   const int64_t n = s.n;
   const int64_t S = (int64_t)s.sn_ptr.size() - 1;
   auto W = [&](int64_t J) { return s.sn_ptr[J + 1] - s.sn_ptr[J]; };
@@ -221,6 +237,42 @@ int build_plan(Symbolic& s, std::string& err) {
     }
   }
 
+  // Where a wide supernode switches from outer blocks to per-step trailing
+  // updates: once its trailing region holds few enough 64x64 tiles to run
+  // beside the next panel launch (the fused form), every step updates all of
+  // it (k = 64) and that work overlaps the panels; before that, the trailing
+  // columns right of an outer block are updated once per outer block. The
+  // switch falls on an outer-block boundary, where the outer block's update
+  // has brought every trailing column up to date. It is one column for all
+  // supernodes of a level: the previous-block update is a property of a whole
+  // panel launch, so at every step the level's supernodes must agree on
+  // whether their next block still needs it. The budget follows the fusion
+  // rule below: FUSE_TILES_PER_CU tiles per compute unit left free by the
+  // level's panel workgroups.
+  std::vector<int64_t> sw(S, 0);
+  for (int32_t h = 0; h < p.nlevels; ++h) {
+    int64_t wmax = 0;
+    for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
+      wmax = std::max<int64_t>(wmax, W(p.lvl_sn[q]));
+    if (wmax <= NBO) continue;
+    int64_t sl = (wmax + NBO - 1) / NBO * NBO;
+    for (int64_t c = 0; c < wmax; c += NBO) {
+      int64_t tiles = 0, rowt = 0;
+      for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
+        const int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
+        if (w <= c) continue;
+        const int64_t a = (w - c + TN - 1) / TN, b = (m - c + TM - 1) / TM;
+        tiles += a * b - a * (a - 1) / 2;
+        rowt += b;
+      }
+      if (tiles <= FUSE_TILES_PER_CU * std::max<int64_t>(0, DEVICE_CUS - rowt)) {
+        sl = c;
+        break;
+      }
+    }
+    for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) sw[p.lvl_sn[q]] = sl;
+  }
+
   // launches
   p.flops_tiles = 0;
   // places a step's update work in p.updates, heaviest workgroups first: into
@@ -275,8 +327,8 @@ int build_plan(Symbolic& s, std::string& err) {
       p.launches[fused_into].ucount = counts[0];
       p.launches[fused_into].ncount = counts[1];
     } else if (counts[0]) {
-      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? 1 : 0, start, counts[0], 0, (int32_t)nwave,
-                0, 0, 0};
+      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? UPD_SHORT : UPD_TILE, start, counts[0], 0,
+                (int32_t)nwave, 0, 0, 0};
       p.launches.push_back(lu);
     }
   };
@@ -362,8 +414,9 @@ int build_plan(Symbolic& s, std::string& err) {
       bool fuse = false;
       if (pend.valid) {
         int64_t rest = 0, npw = 0;
-        bool short_rest = true;
+        bool short_rest = true, has_next = false;
         for (size_t i = 0; i < pend.tiles.size(); ++i) {
+          has_next = has_next || pend.next[i];
           if (pend.next[i]) continue;
           ++rest;
           const UpdTile& t = pend.tiles[i];
@@ -372,7 +425,9 @@ int build_plan(Symbolic& s, std::string& err) {
         }
         for (int ci = 0; ci < 3; ++ci) npw += (int64_t)cls[ci].size();
         // (the update tiles ride on the 64-column class launch)
-        fuse = short_rest && !cls[2].empty() &&
+        // (after an outer block the next block's update came with the long
+        // part, so no panel of this step has a previous-block update to apply)
+        fuse = has_next && short_rest && !cls[2].empty() &&
                rest <= FUSE_TILES_PER_CU * std::max<int64_t>(0, DEVICE_CUS - npw);
         if (!fuse) commit(pend, -1);
       }
@@ -388,9 +443,16 @@ int build_plan(Symbolic& s, std::string& err) {
         p.max_groups = std::max(p.max_groups, ngroups[ci]);
       }
       if (fuse) commit(pend, widest);
-      // UPDATE work of step k: trailing updates of its block, and the
-      // ancestor updates of supernodes whose last block it is; one target
-      // tile per workgroup with all its contributions
+      // UPDATE work of step k, in two parts. The short part (pend): the
+      // trailing update by block k of the columns of its own 256-column outer
+      // block (k = 64; the next panel launch may apply the tiles of block k+1
+      // itself). The long part: for a supernode whose block k closes an outer
+      // block, the update of every column right of it by the whole outer
+      // block (k = 256), and for a supernode whose last block is k, all of its
+      // SYRK/GEMM updates written straight into the ancestors. The long part
+      // is cut into 128x128 target tiles when that gives enough of them to
+      // fill the device, and then runs as a launch of its own; otherwise it
+      // joins the short part in 64x64 tiles.
       pend = PendingUpdate();
       pend.valid = true;
       pend.level = h;
@@ -409,120 +471,245 @@ int build_plan(Symbolic& s, std::string& err) {
         pend.alg.push_back(alg);
       };
       std::vector<int64_t> finished;
+      struct Outer {
+        int64_t J, c1, ob0;  // trailing columns from c1 on, outer block [ob0, c1)
+      };
+      std::vector<Outer> outer;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
         int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
         if (k * NB >= w) continue;
         int64_t c0 = k * NB, nb = std::min<int64_t>(NB, w - c0), c1 = c0 + nb;
-        if (c1 < w) {
-          for (int64_t tj0 = c1; tj0 < w; tj0 += TN) {
-            int64_t tn = std::min<int64_t>(TN, w - tj0);
-            for (int64_t ti0 = tj0; ti0 < m; ti0 += TM) {
-              int64_t tm = std::min<int64_t>(TM, m - ti0);
-              bool diag = ti0 == tj0;
+        if (c1 >= w) {
+          finished.push_back(J);
+          continue;
+        }
+        const int64_t ob0 = c0 / NBO * NBO;
+        const int64_t ob1 = c0 >= sw[J] ? w : std::min<int64_t>(w, ob0 + NBO);
+        if (c1 == ob1) {
+          outer.push_back(Outer{J, c1, ob0});
+          continue;
+        }
+        for (int64_t tj0 = c1; tj0 < ob1; tj0 += TN) {
+          int64_t tn = std::min<int64_t>(TN, ob1 - tj0);
+          for (int64_t ti0 = tj0; ti0 < m; ti0 += TM) {
+            int64_t tm = std::min<int64_t>(TM, m - ti0);
+            bool diag = ti0 == tj0;
+            UpdTile t;
+            t.c = p.off[J] + tj0 * m + ti0;
+            t.ldc = (int32_t)m;
+            t.m = (int32_t)tm;
+            t.n = (int32_t)tn;
+            t.flags = diag ? FLAG_DIAG : 0;
+            UpdSeg g;
+            g.x = p.off[J] + c0 * m + ti0;
+            g.y = p.off[J] + c0 * m + tj0;
+            g.lds = (int32_t)m;
+            g.k = (int32_t)nb;
+            g.ra = 0;
+            g.rb = (int32_t)tm;
+            g.ca = 0;
+            g.cb = (int32_t)tn;
+            g.src = (int32_t)J;
+            g.sslot = sbase[J] + (int32_t)k;
+            add_tile(t, std::vector<UpdSeg>{g}, 0, 1, tj0 == c1);
+            p.flops_tiles += seg_exec_flops(0, tm, 0, tn, nb);
+            p.flops_upd_alg += 2.0 * (double)nb * seg_entries(0, tm, 0, tn, diag);
+          }
+        }
+      }
+      // the long part cut by a target tile grid of side T; every tile keeps
+      // its contributions in ascending source order
+      struct LongPart {
+        std::vector<UpdTile> tiles;  // seg0 relative to segs
+        std::vector<UpdSeg> segs;
+        std::vector<double> alg;
+        double exec = 0, alg_total = 0;
+        int64_t merged = 0, split = 0, whole = 0;
+      };
+      auto build_long = [&](int64_t T) {
+        LongPart lp;
+        auto put = [&](UpdTile t, const std::vector<UpdSeg>& gs) {
+          const bool diag = (t.flags & FLAG_DIAG) != 0;
+          double alg = 0;
+          for (const UpdSeg& g : gs) {
+            lp.exec += seg_exec_flops(g.ra, g.rb, g.ca, g.cb, g.k);
+            alg += 2.0 * (double)g.k * seg_entries(g.ra, g.rb, g.ca, g.cb, diag);
+          }
+          lp.alg_total += alg;
+          lp.whole++;
+          // one workgroup while the tile's K chunks fit the budget (always in
+          // the deterministic form); otherwise consecutive pieces of its
+          // contribution list (cut inside a contribution's k range where
+          // needed), each added atomically
+          int64_t chunks = 0;
+          for (const UpdSeg& g : gs) chunks += (g.k + KCH - 1) / KCH;
+          auto emit = [&](UpdTile tt, const std::vector<UpdSeg>& part) {
+            double a = 0;
+            for (const UpdSeg& g : part)
+              a += 2.0 * (double)g.k * seg_entries(g.ra, g.rb, g.ca, g.cb, diag);
+            tt.seg0 = (int32_t)lp.segs.size();
+            tt.nseg = (int32_t)part.size();
+            lp.segs.insert(lp.segs.end(), part.begin(), part.end());
+            lp.tiles.push_back(tt);
+            lp.alg.push_back(a);
+          };
+          if (chunks <= WG_CHUNKS || s.opt.deterministic) {
+            emit(t, gs);
+            return;
+          }
+          t.flags |= FLAG_ATOMIC;
+          std::vector<UpdSeg> part;
+          int64_t used = 0;
+          for (const UpdSeg& g : gs) {
+            for (int64_t q0 = 0; q0 < g.k;) {
+              int64_t take = std::min<int64_t>(g.k - q0, (WG_CHUNKS - used) * KCH);
+              UpdSeg piece = g;
+              piece.x += q0 * g.lds;
+              piece.y += q0 * g.lds;
+              piece.k = (int32_t)take;
+              part.push_back(piece);
+              used += (take + KCH - 1) / KCH;
+              q0 += take;
+              if (used >= WG_CHUNKS) {
+                emit(t, part);
+                lp.split++;
+                part.clear();
+                used = 0;
+              }
+            }
+          }
+          if (!part.empty()) {
+            emit(t, part);
+            lp.split++;
+          }
+        };
+        // trailing update by a whole outer block: one contribution per
+        // 64-column block of it (each with its own scale slot in the 16-bit
+        // forms), tiles anchored at the first column right of the block
+        for (const Outer& o : outer) {
+          const int64_t J = o.J, w = W(J), m = M(J);
+          for (int64_t tj0 = o.c1; tj0 < w; tj0 += T) {
+            const int64_t tn = std::min<int64_t>(T, w - tj0);
+            for (int64_t ti0 = tj0; ti0 < m; ti0 += T) {
+              const int64_t tm = std::min<int64_t>(T, m - ti0);
               UpdTile t;
               t.c = p.off[J] + tj0 * m + ti0;
               t.ldc = (int32_t)m;
               t.m = (int32_t)tm;
               t.n = (int32_t)tn;
-              t.flags = diag ? FLAG_DIAG : 0;
-              UpdSeg g;
-              g.x = p.off[J] + c0 * m + ti0;
-              g.y = p.off[J] + c0 * m + tj0;
-              g.lds = (int32_t)m;
-              g.k = (int32_t)nb;
-              g.ra = 0;
-              g.rb = (int32_t)tm;
-              g.ca = 0;
-              g.cb = (int32_t)tn;
-              g.src = (int32_t)J;
-              g.sslot = sbase[J] + (int32_t)k;
-              add_tile(t, std::vector<UpdSeg>{g}, 0, 1, tj0 == c1);
-              p.flops_tiles += seg_exec_flops(0, tm, 0, tn, nb);
-              p.flops_upd_alg += 2.0 * (double)nb * seg_entries(0, tm, 0, tn, diag);
-            }
-          }
-        } else {
-          finished.push_back(J);
-        }
-      }
-      // ancestor updates: cut every rectangle by the 64x64 tile grid of its
-      // target supernode and group the pieces by target tile (key: target,
-      // tile column, tile row), in ascending source order
-      std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<UpdSeg>> by_tile;
-      for (int64_t J : finished) {
-        int64_t mJ = M(J), wJ = W(J);
-        for (const Rect& r : rects[J]) {
-          int64_t mP = M(r.P), wP = W(r.P);
-          for (int64_t TJ = r.c0 / TN; TJ * TN < r.c0 + r.nc; ++TJ)
-            for (int64_t TI = std::max(TJ, r.r0 / TM); TI * TM < r.r0 + r.mr; ++TI) {
-              int64_t rlo = std::max(r.r0, TI * TM), rhi = std::min({r.r0 + r.mr, TI * TM + TM, mP});
-              int64_t clo = std::max(r.c0, TJ * TN), chi = std::min({r.c0 + r.nc, TJ * TN + TN, wP});
-              if (rlo >= rhi || clo >= chi) continue;
-              if (TI == TJ && rhi - 1 < clo) continue;  // entirely above the diagonal
-              UpdSeg g;
-              g.x = p.off[J] + r.sx + (rlo - r.r0);
-              g.y = p.off[J] + r.sy + (clo - r.c0);
-              g.lds = (int32_t)mJ;
-              g.k = (int32_t)wJ;
-              g.ra = (int32_t)(rlo - TI * TM);
-              g.rb = (int32_t)(rhi - TI * TM);
-              g.ca = (int32_t)(clo - TJ * TN);
-              g.cb = (int32_t)(chi - TJ * TN);
-              g.src = (int32_t)J;
-              g.sslot = anc_slot(J);
-              by_tile[std::make_tuple(r.P, TJ, TI)].push_back(g);
-            }
-        }
-      }
-      for (auto& kv : by_tile) {
-        int64_t P = std::get<0>(kv.first), TJ = std::get<1>(kv.first), TI = std::get<2>(kv.first);
-        int64_t mP = M(P), wP = W(P);
-        bool diag = TI == TJ;
-        UpdTile t;
-        t.c = p.off[P] + TJ * TN * mP + TI * TM;
-        t.ldc = (int32_t)mP;
-        t.m = (int32_t)std::min<int64_t>(TM, mP - TI * TM);
-        t.n = (int32_t)std::min<int64_t>(TN, wP - TJ * TN);
-        t.flags = diag ? FLAG_DIAG : 0;
-        if (kv.second.size() > 1) p.n_merged_tiles++;
-        for (const UpdSeg& g : kv.second) {
-          p.flops_tiles += seg_exec_flops(g.ra, g.rb, g.ca, g.cb, g.k);
-          p.flops_upd_alg += 2.0 * (double)g.k * seg_entries(g.ra, g.rb, g.ca, g.cb, diag);
-        }
-        // one workgroup while the tile's K chunks fit the budget; otherwise
-        // consecutive pieces of its contribution list (cut inside a
-        // contribution's k range where needed), each added atomically
-        int64_t chunks = 0;
-        for (const UpdSeg& g : kv.second) chunks += (g.k + KCH - 1) / KCH;
-        if (chunks <= WG_CHUNKS || s.opt.deterministic) {
-          add_tile(t, kv.second, 0, kv.second.size(), false);
-          continue;
-        }
-        t.flags |= FLAG_ATOMIC;
-        std::vector<UpdSeg> part;
-        int64_t used = 0;
-        for (const UpdSeg& g : kv.second) {
-          for (int64_t k0 = 0; k0 < g.k;) {
-            int64_t take = std::min<int64_t>(g.k - k0, (WG_CHUNKS - used) * KCH);
-            UpdSeg piece = g;
-            piece.x += k0 * g.lds;
-            piece.y += k0 * g.lds;
-            piece.k = (int32_t)take;
-            part.push_back(piece);
-            used += (take + KCH - 1) / KCH;
-            k0 += take;
-            if (used >= WG_CHUNKS) {
-              add_tile(t, part, 0, part.size(), false);
-              p.n_split_tiles++;
-              part.clear();
-              used = 0;
+              t.flags = ti0 == tj0 ? FLAG_DIAG : 0;
+              t.seg0 = t.nseg = 0;
+              std::vector<UpdSeg> gs;
+              for (int64_t b0 = o.ob0; b0 < o.c1; b0 += NB) {
+                UpdSeg g;
+                g.x = p.off[J] + b0 * m + ti0;
+                g.y = p.off[J] + b0 * m + tj0;
+                g.lds = (int32_t)m;
+                g.k = (int32_t)std::min<int64_t>(NB, o.c1 - b0);
+                g.ra = 0;
+                g.rb = (int32_t)tm;
+                g.ca = 0;
+                g.cb = (int32_t)tn;
+                g.src = (int32_t)J;
+                g.sslot = sbase[J] + (int32_t)(b0 / NB);
+                gs.push_back(g);
+              }
+              put(t, gs);
             }
           }
         }
-        if (!part.empty()) {
-          add_tile(t, part, 0, part.size(), false);
-          p.n_split_tiles++;
+        // ancestor updates: every rectangle cut by the T x T tile grid of its
+        // target supernode, the pieces grouped by target tile (key: target,
+        // tile column, tile row), in ascending source order
+        std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<UpdSeg>> by_tile;
+        for (int64_t J : finished) {
+          int64_t mJ = M(J), wJ = W(J);
+          for (const Rect& r : rects[J]) {
+            int64_t mP = M(r.P), wP = W(r.P);
+            for (int64_t TJ = r.c0 / T; TJ * T < r.c0 + r.nc; ++TJ)
+              for (int64_t TI = std::max(TJ, r.r0 / T); TI * T < r.r0 + r.mr; ++TI) {
+                int64_t rlo = std::max(r.r0, TI * T), rhi = std::min({r.r0 + r.mr, TI * T + T, mP});
+                int64_t clo = std::max(r.c0, TJ * T), chi = std::min({r.c0 + r.nc, TJ * T + T, wP});
+                if (rlo >= rhi || clo >= chi) continue;
+                if (TI == TJ && rhi - 1 < clo) continue;  // entirely above the diagonal
+                UpdSeg g;
+                g.x = p.off[J] + r.sx + (rlo - r.r0);
+                g.y = p.off[J] + r.sy + (clo - r.c0);
+                g.lds = (int32_t)mJ;
+                g.k = (int32_t)wJ;
+                g.ra = (int32_t)(rlo - TI * T);
+                g.rb = (int32_t)(rhi - TI * T);
+                g.ca = (int32_t)(clo - TJ * T);
+                g.cb = (int32_t)(chi - TJ * T);
+                g.src = (int32_t)J;
+                g.sslot = anc_slot(J);
+                by_tile[std::make_tuple(r.P, TJ, TI)].push_back(g);
+              }
+          }
         }
+        for (auto& kv : by_tile) {
+          int64_t P = std::get<0>(kv.first), TJ = std::get<1>(kv.first), TI = std::get<2>(kv.first);
+          int64_t mP = M(P), wP = W(P);
+          UpdTile t;
+          t.c = p.off[P] + TJ * T * mP + TI * T;
+          t.ldc = (int32_t)mP;
+          t.m = (int32_t)std::min<int64_t>(T, mP - TI * T);
+          t.n = (int32_t)std::min<int64_t>(T, wP - TJ * T);
+          t.flags = TI == TJ ? FLAG_DIAG : 0;
+          t.seg0 = t.nseg = 0;
+          if (kv.second.size() > 1) lp.merged++;
+          put(t, kv.second);
+        }
+        return lp;
+      };
+      // the long part: a launch of its own in 128x128 tiles when there are
+      // enough of them (with the same work in 64x64 tiles kept for the forms
+      // whose kernels take only those, the 16-bit update forms); otherwise it
+      // joins the short part in 64x64 tiles
+      auto place = [&](const LongPart& part) {
+        const int64_t start = (int64_t)p.updates.size();
+        std::vector<std::pair<int64_t, size_t>> order;
+        for (size_t i = 0; i < part.tiles.size(); ++i) {
+          int64_t ch = 0;
+          for (int32_t e = 0; e < part.tiles[i].nseg; ++e)
+            ch += (part.segs[part.tiles[i].seg0 + e].k + KCH - 1) / KCH;
+          order.push_back({-ch * part.tiles[i].m * part.tiles[i].n, i});
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<int64_t, size_t>& x,
+                            const std::pair<int64_t, size_t>& y) { return x.first < y.first; });
+        for (auto& o : order) {
+          UpdTile t = part.tiles[o.second];
+          const int32_t s0 = t.seg0;
+          t.seg0 = (int32_t)p.segs.size();
+          for (int32_t e = 0; e < t.nseg; ++e) p.segs.push_back(part.segs[s0 + e]);
+          p.updates.push_back(t);
+        }
+        return start;
+      };
+      LongPart lp = build_long(BIG);
+      if (lp.whole >= MIN_BIG_TILES) {
+        LongPart alt = build_long(TM);
+        Launch lb{LAUNCH_UPDATE, h, (int32_t)k, UPD_BIG, place(lp), (int64_t)lp.tiles.size(),
+                  0, 0, 0, 0, 0};
+        lb.alt_start = place(alt);
+        lb.alt_count = (int64_t)alt.tiles.size();
+        p.launches.push_back(lb);
+        p.flops_tiles += lp.exec;
+        p.flops_upd_alg += lp.alg_total;
+        p.flops_upd_launch += lp.alg_total;
+        p.n_merged_tiles += lp.merged;
+        p.n_split_tiles += lp.split;
+      } else {
+        LongPart sp = build_long(TM);
+        for (size_t i = 0; i < sp.tiles.size(); ++i) {
+          const UpdTile& t = sp.tiles[i];
+          add_tile(t, sp.segs, t.seg0, t.seg0 + t.nseg, false);
+        }
+        p.flops_tiles += sp.exec;
+        p.flops_upd_alg += sp.alg_total;
+        p.n_merged_tiles += sp.merged;
+        p.n_split_tiles += sp.split;
       }
     }
     if (pend.valid) commit(pend, -1);

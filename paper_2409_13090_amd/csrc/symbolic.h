@@ -20,6 +20,10 @@ struct AnalyzeOptions {
   int deterministic = 1;   // 1: no floating-point atomics in the factorization (every
                            // target tile has one owner); 0: heavy tiles split, parts
                            // added atomically
+  int outer_block = 256;   // columns of the outer block of wide supernodes (a multiple
+                           // of 64; 64 = every panel updates all trailing columns)
+  int big_tile_min = 0;    // the long updates of a step take 128x128 target tiles when
+                           // there are at least this many (<= 0: never)
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its
@@ -121,12 +125,18 @@ constexpr int32_t LAUNCH_UPDATE = 1;
 constexpr int32_t NARROW_COLS = 16;
 constexpr int64_t WAVE_SPLIT_MIN = 1024;
 
+// update launch variants: 64x64 target tiles (k_update), 64x64 tiles that all
+// hold one contribution with k <= 64 and one owner (k_update_short), 128x128
+// target tiles (k_update_big)
+constexpr int32_t UPD_TILE = 0;
+constexpr int32_t UPD_SHORT = 1;
+constexpr int32_t UPD_BIG = 2;
+
 struct Launch {
   int32_t kind;   // LAUNCH_*
   int32_t level;
   int32_t step;   // column block index inside the level
-  int32_t variant; // update: 1 when every tile has one contribution, k <= 64, one owner;
-                   // panel: 16-column blocks of its widest tile (1, 2 or 4)
+  int32_t variant; // update: UPD_*; panel: 16-column blocks of its widest tile (1, 2 or 4)
   int64_t start;  // first tile
   int64_t count;  // number of tiles
   int32_t pre;    // panel: its tiles first apply the previous block's trailing update
@@ -135,6 +145,8 @@ struct Launch {
   int64_t ustart; // panel: update tiles of the previous step run in the same launch
   int64_t ucount; //   (single-contribution tiles, k <= 64); the ncount tiles after
   int64_t ncount; //   them are the ones pre applies (kept for the unfused form)
+  int64_t alt_start = 0;  // UPD_BIG: the same work cut into 64x64 tiles, for the
+  int64_t alt_count = 0;  //   forms whose update kernels take only those (16-bit)
 };
 
 struct Plan {

@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("user_perm", _c_i64p), ("grid", ctypes.c_int64 * 4),
                 ("merge_cap", ctypes.c_double), ("reorder", ctypes.c_int32),
                 ("maximal_blocks", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32),
+                ("outer_block", ctypes.c_int32), ("big_tile_min", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -71,6 +72,7 @@ EXPORTED = [
     "rlb_batch_free", "rlb_set_graph_mode", "rlb_batch_set_graph_mode", "rlb_set_profiling",
     "rlb_last_profile", "rlb_status_string", "rlb_last_error", "rlb_factor_pivots_patched",
     "rlb_batch_set_schedule", "rlb_batch_autotune", "rlb_solve_noalloc",
+    "rlb_last_profile_launches",
 ]
 
 _lib = None
@@ -109,6 +111,7 @@ def lib():
         "rlb_batch_set_graph_mode": [_vp, i32],
         "rlb_set_profiling": [_vp, i32],
         "rlb_last_profile": [_vp, _vp, _vp, _vp, _vp],
+        "rlb_last_profile_launches": [_vp, _vp, ctypes.POINTER(i64)],
         "rlb_factor_pivots_patched": [_vp, ctypes.POINTER(i64)],
         "rlb_batch_set_schedule": [_vp, i32],
         "rlb_batch_autotune": [_vp, _vp, _vp, ctypes.c_size_t, _vp, i32, ctypes.POINTER(i32), _vp],
@@ -161,7 +164,7 @@ class Symbolic:
 
     def __init__(self, n, colptr, rowidx, ordering="grid", grid=(0, 0, 0, 1), merge_cap=0.125,
                  reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0,
-                 deterministic=True):
+                 deterministic=True, outer_block=0, big_tile_min=0):
         L = lib()
         self._cp = np.ascontiguousarray(colptr, np.int64)
         self._ri = np.ascontiguousarray(rowidx, np.int64)
@@ -176,6 +179,8 @@ class Symbolic:
         o.maximal_blocks = 1 if maximal_blocks else 0
         o.panel_spread = int(panel_spread)
         o.deterministic = 1 if deterministic else 0
+        o.outer_block = int(outer_block)
+        o.big_tile_min = int(big_tile_min)
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)
             o.user_perm = self._up.ctypes.data_as(_c_i64p)
@@ -315,6 +320,14 @@ class Numeric:
                                       ctypes.byref(npn)))
         return {"update_ms": u.value, "panel_ms": p.value, "n_update": nu.value,
                 "n_panel": npn.value}
+
+    def last_profile_launches(self):
+        """Milliseconds of every launch of the last profiled factorization."""
+        n = ctypes.c_int64(0)
+        _check(lib().rlb_last_profile_launches(self.h, None, ctypes.byref(n)))
+        out = np.zeros(n.value)
+        _check(lib().rlb_last_profile_launches(self.h, out.ctypes.data, ctypes.byref(n)))
+        return out
 
     def close(self):
         if getattr(self, "h", None):

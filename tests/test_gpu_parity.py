@@ -117,7 +117,7 @@ def test_narrow_tiles_run_one_per_wavefront():
     A = W.small_grid("9pt", (320, 300, 1), seed=41)
     s = rlb.Symbolic.from_matrix(A)
     T = s.array("update_tiles").reshape(-1, 7)
-    L = s.array("launches").reshape(-1, 10)
+    L = s.array("launches").reshape(-1, 12)
     most = 0
     for l in L[L[:, 0] == 1]:
         c = 0

@@ -23,7 +23,7 @@ def unfused(launches):
     apply themselves) followed by plain panel launches, as the batch runs it."""
     out, done = [], set()
     for j, l in enumerate(launches):
-        kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt = (int(v) for v in l)
+        kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt, ast, acnt = (int(v) for v in l)
         if kind == 0 and pre:
             if (lev, step) not in done:
                 done.add((lev, step))
@@ -31,14 +31,28 @@ def unfused(launches):
                     if int(q[0]) != 0 or int(q[1]) != lev or int(q[2]) != step:
                         break
                     if int(q[8]) + int(q[9]) > 0:
-                        out.append((1, lev, step - 1, int(q[7]), int(q[8]) + int(q[9]), 1, 0, 0, 0, 0))
-            out.append((kind, lev, step, st, cnt, variant, 0, 0, 0, 0))
+                        out.append((1, lev, step - 1, int(q[7]), int(q[8]) + int(q[9]), 1, 0, 0, 0,
+                                    0, 0, 0))
+            out.append((kind, lev, step, st, cnt, variant, 0, 0, 0, 0, 0, 0))
         else:
-            out.append((kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt))
+            out.append((kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt, ast, acnt))
     return out
 
 
-def replay_factor(A, expand=False, **kw):
+def with_alt(launches):
+    """Launches of 128x128 target tiles replaced by the same work in 64x64
+    tiles, as the 16-bit update forms run them."""
+    out = []
+    for l in launches:
+        l = [int(v) for v in l]
+        if l[0] == 1 and l[5] == 2:
+            assert l[11] > 0
+            l[3], l[4], l[5] = l[10], l[11], 0
+        out.append(tuple(l))
+    return out
+
+
+def replay_factor(A, expand=False, alt=False, **kw):
     s = rlb.Symbolic.from_matrix(A, **kw)
     size = s.info()["factor_bytes"] // 8
     Lb = np.zeros(size)
@@ -75,10 +89,12 @@ def replay_factor(A, expand=False, **kw):
                 Lb[c + j * ldc: c + j * ldc + m] -= col
         return reads, set(owner)
 
-    launches = s.array("launches").reshape(-1, 10)
+    launches = s.array("launches").reshape(-1, 12)
     if expand:
         launches = unfused(launches)
-    for kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt in launches:
+    if alt:
+        launches = with_alt(launches)
+    for kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt, ast, acnt in launches:
         if kind == 0:
             groups = {}
             for t in P[st:st + cnt]:
@@ -117,6 +133,7 @@ def replay_factor(A, expand=False, **kw):
                     Lb[diag + j * ld + j: diag + j * ld + nb] = Lt[j:, j]
                 for j in range(nb):
                     touched.update(range(diag + j * ld, diag + j * ld + nrows))
+
             if ucnt:
                 # the previous step's remaining update tiles run in the same
                 # launch: they may neither write nor read the column blocks
@@ -127,7 +144,10 @@ def replay_factor(A, expand=False, **kw):
                 assert all(int(U[i][6]) == 1 and G[int(U[i][5])][3] <= 64
                            for i in range(ust, ust + ucnt))
         else:
-            updates(U[st:st + cnt])
+            tiles = U[st:st + cnt]
+            side = 128 if variant == 2 else 64
+            assert all(m <= side and n <= side for _, _, m, n, _, _, _ in tiles)
+            updates(tiles)
     for diag, ld, nb in s.array("diag_tiles").reshape(-1, 3):
         Lt = np.array([[Lb[diag + j * ld + i] if i >= j else 0.0 for j in range(nb)]
                        for i in range(nb)])
@@ -227,6 +247,22 @@ CASES = [
      {"panel_spread": 3}),
     ("elast_6x6x5", lambda: W.elasticity_like((6, 6, 5), np.random.default_rng(7), 1e-6), {}),
     ("batch_member_7", lambda: W.batch_member(7), {}),
+    # outer blocks of 128 columns and 128x128 target tiles in every long part
+    ("lap3d27_13_outer128_big", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1,
+                                                     hi=1.0, shift=1e-4),
+     {"outer_block": 128, "big_tile_min": 1}),
+    ("lap3d7_17_outer64_big", lambda: W.small_grid("7pt", (17, 17, 17), seed=3),
+     {"outer_block": 64, "big_tile_min": 1}),
+    ("lap3d27_11x11x9_atomic_big", lambda: W.small_grid("27pt", (11, 11, 9), seed=26, shift=1e-3),
+     {"outer_block": 128, "big_tile_min": 1, "deterministic": False}),
+    # several wide supernodes in one level, outer blocks of 64 columns
+    ("lap3d27_16_outer64", lambda: W.small_grid("27pt", (16, 16, 16), seed=27, lo=0.1, hi=1.0,
+                                                shift=1e-4),
+     {"outer_block": 64}),
+    # several outer blocks of 64 columns
+    ("lap3d27_14_outer64", lambda: W.small_grid("27pt", (14, 14, 14), seed=25, lo=0.1, hi=1.0,
+                                                shift=1e-4),
+     {"outer_block": 64}),
 ]
 
 
@@ -240,12 +276,18 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     # the unfused form (the batch's) reaches the same factor
     s2, Lb2 = replay_factor(A, expand=True, **kw)
     assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
+    L12 = s.array("launches").reshape(-1, 12)
+    if kw.get("big_tile_min") == 1:
+        # the long parts went to 128x128 tiles; their 64x64 form (16-bit) too
+        assert np.any((L12[:, 0] == 1) & (L12[:, 5] == 2))
+        s3, Lb3 = replay_factor(A, alt=True, **kw)
+        assert compare_factor(export(s3, Lb3), f, A.n) <= 1e-12
     # algorithmic flops of the tiles of update launches of their own, from the
     # exported lists (entries written, lower part only on diagonal tiles)
     U = s.array("update_tiles").reshape(-1, 7)
     G = s.array("update_segs").reshape(-1, 9)
     fl = 0.0
-    for l in s.array("launches").reshape(-1, 10):
+    for l in s.array("launches").reshape(-1, 12):
         if l[0] != 1:
             continue
         for c, ldc, m, n, flags, seg0, nseg in U[l[3]:l[3] + l[4]]:

@@ -134,6 +134,8 @@ def main():
                     help="factorizations timed launch by launch for the roofline")
     ap.add_argument("--mixed-reps", type=int, default=7,
                     help="timed repetitions of each time to solution (after one untimed)")
+    ap.add_argument("--no-rl", action="store_true",
+                    help="skip the RL (Algorithm 4) factorization of the same matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
@@ -268,6 +270,41 @@ def main():
                                       "nnz_stored")},
         "roofline": roof,
     }
+
+    if not args.no_rl:
+        # RL (Algorithm 4) on the same matrix and the same symbolic phase:
+        # update matrices in working storage, assembled into the ancestors
+        sym_rl = rlb.Symbolic.from_matrix(A, method="rl")
+        info_rl = sym_rl.info()
+        num_rl = rlb.Numeric(sym_rl, rlb.RLB_PREC_FP64)
+        num_rl.set_graph_mode(graph)
+        ws_rl = torch.empty(info_rl["factor_bytes"] // 8 + 1, dtype=torch.float64, device=dev)
+        assert num_rl.factor(vals, ws_rl) == 0
+        ms_rl = []
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            num_rl.factor(vals, ws_rl, check=False)
+            e1.record(stream)
+            e1.synchronize()
+            ms_rl.append(e0.elapsed_time(e1))
+        assert num_rl.status() == 0
+        X.copy_(B)
+        num_rl.solve(X)
+        be_rl = num_rl.backward_error(B, X)
+        t_rl = statistics.median(ms_rl) / 1e3
+        out["rl"] = {"method": "RL (Algorithm 4): SYRK into an update matrix per supernode, "
+                               "assembled into the ancestors through relative indices "
+                               "(atomic additions)",
+                     "factor_ms": round(t_rl * 1e3, 3), "gflops": round(F / t_rl / 1e9, 2),
+                     "rlb_factor_ms": round(t_fac * 1e3, 3),
+                     "rl_over_rlb_time": round(t_rl / t_fac, 3),
+                     "fp_storage_bytes": info_rl["factor_bytes"],
+                     "update_matrix_bytes": info_rl["u_bytes"],
+                     "rlb_fp_storage_bytes": info["factor_bytes"],
+                     "backward_error_max": float(f"{max(be_rl):.3e}")}
+        del num_rl, ws_rl
 
     if not args.no_mixed:
         mixed = args.mixed or ("bf16" if args.workload == "elast3_40" else "fp32")

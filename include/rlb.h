@@ -85,7 +85,17 @@ typedef struct rlb_options {
                                block, updates into ancestors) take 128x128 target tiles
                                when there are at least this many; <= 0 (default): never
                                (on the grid workloads the 64x64 tiles are faster) */
+  int32_t method;           /* RLB_METHOD_RLB (default): Algorithm 5, every update written
+                               straight into the ancestors' storage; RLB_METHOD_RL:
+                               Algorithm 4 (Section 2.2.1), each supernode's updates
+                               formed in an update matrix U_J (working storage after the
+                               factor in the workspace) and assembled into the ancestors
+                               through relative indices, with atomic additions; FP64
+                               only, not batched */
 } rlb_options;
+
+#define RLB_METHOD_RLB 0
+#define RLB_METHOD_RL 1
 
 typedef struct rlb_info {
   int64_t n, nnz_a;
@@ -98,7 +108,8 @@ typedef struct rlb_info {
   int64_t n_pairs;       /* (J, ancestor P) update pairs */
   int64_t n_calls;       /* SYRK + GEMM block updates of Alg. 5 */
   int64_t merge_added, merge_base; /* merging: added stored entries, fundamental entries */
-  int64_t factor_bytes;  /* device workspace needed by rlb_factor (FP64 factor storage) */
+  int64_t factor_bytes;  /* device workspace needed by rlb_factor (FP64 factor storage,
+                            and for RL its update-matrix working storage after it) */
   int64_t n_panel_tiles;  /* workgroups of all panel launches */
   int64_t n_update_tiles; /* target tiles of all update launches */
   int64_t n_merged_tiles; /* target tiles that sum contributions of several supernodes */
@@ -110,6 +121,8 @@ typedef struct rlb_info {
   double flops_panel;    /* flops of the panel (POTRF + TRSM) steps */
   double flops_upd_launch; /* the part of flops_upd_alg run by update launches of their
                               own (the rest runs inside panel launches) */
+  int64_t u_bytes;       /* RL: floating-point working storage of the update matrices
+                            (part of factor_bytes); 0 for RLB */
 } rlb_info;
 
 typedef struct rlb_symbolic_s* rlb_symbolic;

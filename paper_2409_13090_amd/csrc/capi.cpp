@@ -62,6 +62,8 @@ struct DevPlan {
   int64_t* a_rowptr = nullptr;
   int32_t* a_col = nullptr;
   int64_t* a_src = nullptr;
+  AsmCol* asmcols = nullptr;    // RL assembly
+  int32_t* asm_rows = nullptr;
   void release() {
     dfree(panels);
     dfree(updates);
@@ -75,6 +77,8 @@ struct DevPlan {
     dfree(a_rowptr);
     dfree(a_col);
     dfree(a_src);
+    dfree(asmcols);
+    dfree(asm_rows);
   }
 };
 
@@ -365,6 +369,8 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
       return fail(RLB_ERR_ARG, "bad outer_block (a multiple of 64)");
     ao.outer_block = opt->outer_block ? opt->outer_block : 256;
     ao.big_tile_min = opt->big_tile_min;
+    if (opt->method < 0 || opt->method > 1) return fail(RLB_ERR_ARG, "bad method");
+    ao.method = opt->method;
   } else {
     ao.ordering = 0;
   }
@@ -401,7 +407,8 @@ rlb_status rlb_symbolic_info(rlb_symbolic sym, rlb_info* o) {
   o->n_calls = s.n_calls;
   o->merge_added = s.merge_added;
   o->merge_base = s.merge_base;
-  o->factor_bytes = s.plan.l_elems * (int64_t)sizeof(double);
+  o->factor_bytes = s.plan.ws_elems * (int64_t)sizeof(double);
+  o->u_bytes = s.plan.u_elems * (int64_t)sizeof(double);
   o->n_panel_tiles = (int64_t)s.plan.panels.size();
   o->n_update_tiles = (int64_t)s.plan.updates.size();
   o->n_merged_tiles = s.plan.n_merged_tiles;
@@ -443,6 +450,13 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
   else if (w == "level") put32(s.plan.level);
   else if (w == "off") put64(s.plan.off);
   else if (w == "amap") put64(s.plan.amap);
+  else if (w == "asm_rows") put32(s.plan.asm_rows);
+  else if (w == "asm_cols") {  // src, dst, rp, len per update-matrix column (RL)
+    for (const AsmCol& c : s.plan.asmcols) {
+      int64_t v[4] = {c.src, c.dst, c.rp, c.len};
+      tmp.insert(tmp.end(), v, v + 4);
+    }
+  }
   else if (w == "update_tiles") {  // c, ldc, m, n, flags, seg0, nseg per tile
     for (const UpdTile& t : s.plan.updates) {
       int64_t v[7] = {t.c, t.ldc, t.m, t.n, t.flags, t.seg0, t.nseg};
@@ -505,6 +519,8 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if (!sym || !out) return fail(RLB_ERR_ARG, "null argument");
   if (precision < RLB_PREC_FP64 || precision > RLB_PREC_FP16_UPDATES)
     return fail(RLB_ERR_ARG, "bad precision");
+  if (sym->s.opt.method != 0 && precision != RLB_PREC_FP64)
+    return fail(RLB_ERR_UNSUPPORTED, "the RL method is FP64 only");
   *out = nullptr;
   std::unique_ptr<rlb_numeric_s> h(new rlb_numeric_s());
   h->sym = sym;
@@ -518,6 +534,8 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if ((st = upload(&h->d.dtiles, s.plan.dtiles))) return st;
   if ((st = upload(&h->d.ptiles, s.plan.ptiles))) return st;
   if ((st = upload(&h->d.amap, s.plan.amap))) return st;
+  if ((st = upload(&h->d.asmcols, s.plan.asmcols))) return st;
+  if ((st = upload(&h->d.asm_rows, s.plan.asm_rows))) return st;
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
   h->ncounters = std::max<int32_t>(1, s.plan.max_groups);
@@ -555,7 +573,9 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
   for (const Launch& l : p.launches) {
     if (timed) (void)hipEventRecord(h->ev[ei++], st);
     hipStream_t ls = st;
-    if (l.kind == LAUNCH_UPDATE) {
+    if (l.kind == LAUNCH_ASSEMBLE) {
+      launch_assemble(h->d.asmcols + l.start, l.count, h->d.asm_rows, L, ls);
+    } else if (l.kind == LAUNCH_UPDATE) {
       if (l.variant == UPD_BIG && h->precision >= RLB_PREC_BF16_UPDATES)
         launch_update(h->d.updates + l.alt_start, h->d.segs, l.alt_count, L, h->precision,
                       h->smax, UPD_TILE, ls, 0);
@@ -582,10 +602,10 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
 
 rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size_t ws_bytes,
                       void* stream) {
-  if (!h || (!values && h->sym->s.nnz_a) || (!workspace && h->sym->s.plan.l_elems))
+  if (!h || (!values && h->sym->s.nnz_a) || (!workspace && h->sym->s.plan.ws_elems))
     return fail(RLB_ERR_ARG, "null argument");
   const Symbolic& s = h->sym->s;
-  if (ws_bytes < (size_t)s.plan.l_elems * sizeof(double))
+  if (ws_bytes < (size_t)s.plan.ws_elems * sizeof(double))
     return fail(RLB_ERR_WORKSPACE, "workspace smaller than factor_bytes");
   if (((uintptr_t)workspace & 7) != 0) return fail(RLB_ERR_ARG, "workspace not 8-byte aligned");
   hipStream_t st = (hipStream_t)stream;
@@ -612,7 +632,7 @@ rlb_status rlb_factor(rlb_numeric h, const double* values, void* workspace, size
       HIP_OK(hipEventElapsedTime(&ms, h->ev[ei], h->ev[ei + 1]));
       h->prof_launch_ms.push_back(ms);
       ei += 2;
-      if (l.kind == LAUNCH_UPDATE) {
+      if (l.kind != LAUNCH_PANEL) {  // update and (RL) assembly launches
         h->prof_update_ms += ms;
         h->prof_nupd++;
       } else {
@@ -1084,6 +1104,8 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
   int32_t maxlev = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (!syms[i]) return fail(RLB_ERR_ARG, "null symbolic handle");
+    if (syms[i]->s.opt.method != 0)
+      return fail(RLB_ERR_UNSUPPORTED, "the batched form runs RLB plans only");
     b->base[i] = run;
     run += syms[i]->s.plan.l_elems;
     b->nnz_ptr[i + 1] = b->nnz_ptr[i] + syms[i]->s.nnz_a;

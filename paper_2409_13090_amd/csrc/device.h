@@ -47,6 +47,9 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
                    int64_t nwave = 0, const float* Ls = nullptr);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
+// RL: update-matrix columns added into their ancestors (atomic adds)
+void launch_assemble(const AsmCol* cols, int64_t count, const int32_t* rows, double* L,
+                     hipStream_t st);
 // the off-diagonal inverse blocks of the two-chunk solve steps (after
 // launch_tile_inverse)
 void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStream_t st);

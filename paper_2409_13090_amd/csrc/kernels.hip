@@ -292,6 +292,7 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
   double* __restrict__ C = L + t.c;
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
+  const bool assign = t.flags & 4;  // write -(sum) without reading the target
   const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
   const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
   const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
@@ -311,7 +312,7 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
       for (int v = 0; v < 4; ++v) {
         const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
         const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
-        cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        cv[bj][bi][v] = assign ? 0.0 : C[(int64_t)col * ldc + row];
       }
   acc_t acc[2][2];
 #pragma unroll
@@ -1076,11 +1077,12 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
   const bool atomic = t.flags & 2;
+  const bool assign = t.flags & 4;  // write -(sum) without reading the target
 
   // the target values of a tile with a single owner, loaded up front (no
   // other workgroup of the launch writes it); addresses clamped into the tile
-  double cv[2][2][4];
-  if (!atomic) {
+  double cv[2][2][4] = {};
+  if (!atomic && !assign) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
@@ -1312,6 +1314,21 @@ __global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__
     update_w_tile<2>(t, segs, L, lane);
   else
     update_w_tile<4>(t, segs, L, lane);
+}
+
+// RL (Algorithm 4) assembly: column j of an update matrix U_J added into the
+// ancestor column that owns it, at the rows its relative indices give; one
+// wavefront per column, four per workgroup. Update matrices of several
+// supernodes of a step may meet in one ancestor entry: the additions are
+// atomic (their order, and so the rounding, varies from run to run).
+__global__ __launch_bounds__(256) void k_assemble(const AsmCol* __restrict__ cols,
+                                                  const int32_t* __restrict__ rows,
+                                                  double* __restrict__ L, int count) {
+  const int lane = threadIdx.x & 63;
+  const int ci = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
+  if (ci >= count) return;
+  const AsmCol c = cols[ci];
+  for (int i = lane; i < c.len; i += 64) atomicAdd(L + c.dst + rows[c.rp + i], L[c.src + i]);
 }
 
 // The trailing updates of a step as a launch of their own.
@@ -2327,6 +2344,12 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     hipLaunchKernelGGL(k_update16<3>, g, b, 0, st, tiles, segs, L, smax);
   else
     hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
+}
+void launch_assemble(const AsmCol* cols, int64_t count, const int32_t* rows, double* L,
+                     hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, st, cols, rows,
+                     L, (int)count);
 }
 // pivot thresholds of the reduced-precision forms: thr[j] = u * A_jj, and the
 // largest diagonal entry (bit pattern; all positive on an SPD input)

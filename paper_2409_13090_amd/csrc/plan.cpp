@@ -33,6 +33,7 @@ constexpr int TM = 64;   // update tile rows
 constexpr int TN = 64;   // update tile columns
 constexpr int FLAG_DIAG = 1;
 constexpr int FLAG_ATOMIC = 2;
+constexpr int FLAG_ASSIGN = 4;  // the tile is written with -(sum), not read (RL's U_J)
 constexpr int KCH = 16;        // K chunk of the update kernel
 // panel launch cost model by width class (1, 2, 4 blocks of 16 columns):
 // microseconds per workgroup, resident workgroups on the device, and the
@@ -517,6 +518,104 @@ int build_plan(Symbolic& s, std::string& err) {
           }
         }
       }
+      if (s.opt.method == 1 && !finished.empty()) {
+        // RL (Algorithm 4): for every supernode J whose cdiv ends at this
+        // step, one SYRK forms its update matrix U_J = -L_{R,J} L_{R,J}^T
+        // (R: the r_J rows below the diagonal block; lower triangle, r_J x r_J
+        // column-major, in working storage after the factor), then every
+        // column of U_J is added into the ancestor supernode that owns that
+        // column, at the rows its relative indices give (the rows of J below
+        // the column all lie in the ancestor's index list, eq. (1)). The
+        // working storage is reused by the next step.
+        std::vector<UpdTile> ut;
+        std::vector<UpdSeg> ug;
+        double alg = 0;
+        bool shortk = true;
+        int64_t uo = 0;
+        const int64_t ac0 = (int64_t)p.asmcols.size();
+        for (int64_t J : finished) {
+          const int64_t w = W(J), m = M(J), r = m - w;
+          if (r == 0) continue;
+          const int64_t ub = p.l_elems + uo;
+          for (int64_t tj0 = 0; tj0 < r; tj0 += TN) {
+            const int64_t tn = std::min<int64_t>(TN, r - tj0);
+            for (int64_t ti0 = tj0; ti0 < r; ti0 += TM) {
+              const int64_t tm = std::min<int64_t>(TM, r - ti0);
+              const bool diag = ti0 == tj0;
+              UpdTile t;
+              t.c = ub + tj0 * r + ti0;
+              t.ldc = (int32_t)r;
+              t.m = (int32_t)tm;
+              t.n = (int32_t)tn;
+              t.flags = (diag ? FLAG_DIAG : 0) | FLAG_ASSIGN;
+              t.seg0 = (int32_t)ug.size();
+              t.nseg = 1;
+              UpdSeg g;
+              g.x = p.off[J] + w + ti0;
+              g.y = p.off[J] + w + tj0;
+              g.lds = (int32_t)m;
+              g.k = (int32_t)w;
+              g.ra = 0;
+              g.rb = (int32_t)tm;
+              g.ca = 0;
+              g.cb = (int32_t)tn;
+              g.src = (int32_t)J;
+              g.sslot = anc_slot(J);
+              ut.push_back(t);
+              ug.push_back(g);
+              p.flops_tiles += seg_exec_flops(0, tm, 0, tn, w);
+              alg += 2.0 * (double)w * seg_entries(0, tm, 0, tn, diag);
+            }
+          }
+          if (w > 64) shortk = false;
+          // assembly: the columns of U_J grouped by the ancestor owning them
+          const int32_t* gJ = s.gl.data() + s.gl_ptr[J];
+          for (int64_t j0 = 0; j0 < r;) {
+            const int64_t P = snode[gJ[w + j0]];
+            int64_t j1 = j0 + 1;
+            while (j1 < r && snode[gJ[w + j1]] == P) ++j1;
+            const int32_t* gP = s.gl.data() + s.gl_ptr[P];
+            const int64_t mP = M(P);
+            const int64_t rp0 = (int64_t)p.asm_rows.size();
+            for (int64_t i = j0; i < r; ++i) {
+              const int32_t* it = std::lower_bound(gP, gP + mP, gJ[w + i]);
+              if (it == gP + mP || *it != gJ[w + i]) {
+                err = "internal: a row of an update matrix outside its ancestor's structure";
+                return -1;
+              }
+              p.asm_rows.push_back((int32_t)(it - gP));
+            }
+            for (int64_t j = j0; j < j1; ++j)
+              p.asmcols.push_back(AsmCol{ub + j * r + j,
+                                         p.off[P] + (gJ[w + j] - s.sn_ptr[P]) * mP,
+                                         (int32_t)(rp0 + (j - j0)), (int32_t)(r - j)});
+            j0 = j1;
+          }
+          uo += r * r;
+          uo = (uo + 7) & ~int64_t(7);
+        }
+        if (p.asm_rows.size() > (size_t)INT32_MAX) {
+          err = "RL assembly lists too large";
+          return -1;
+        }
+        p.u_elems = std::max(p.u_elems, uo);
+        if (!ut.empty()) {
+          const int64_t start = (int64_t)p.updates.size();
+          for (UpdTile t : ut) {
+            const UpdSeg g = ug[t.seg0];
+            t.seg0 = (int32_t)p.segs.size();
+            p.segs.push_back(g);
+            p.updates.push_back(t);
+          }
+          p.launches.push_back(Launch{LAUNCH_UPDATE, h, (int32_t)k, shortk ? UPD_SHORT : UPD_TILE,
+                                      start, (int64_t)ut.size(), 0, 0, 0, 0, 0});
+          p.launches.push_back(Launch{LAUNCH_ASSEMBLE, h, (int32_t)k, 0, ac0,
+                                      (int64_t)p.asmcols.size() - ac0, 0, 0, 0, 0, 0});
+          p.flops_upd_alg += alg;
+          p.flops_upd_launch += alg;
+        }
+        finished.clear();
+      }
       // the long part cut by a target tile grid of side T; every tile keeps
       // its contributions in ascending source order
       struct LongPart {
@@ -714,6 +813,7 @@ int build_plan(Symbolic& s, std::string& err) {
     }
     if (pend.valid) commit(pend, -1);
   }
+  p.ws_elems = p.l_elems + p.u_elems;
   // diagonal tiles of every 64-column step, inverted after the factorization,
   // grouped by width class
   for (int ci = 0; ci < 3; ++ci) {

@@ -24,6 +24,8 @@ struct AnalyzeOptions {
                            // of 64; 64 = every panel updates all trailing columns)
   int big_tile_min = 0;    // the long updates of a step take 128x128 target tiles when
                            // there are at least this many (<= 0: never)
+  int method = 0;          // 0: RLB (Algorithm 5); 1: RL (Algorithm 4), the updates of a
+                           // supernode into its ancestors through an update matrix
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its
@@ -116,6 +118,18 @@ struct SolveLaunch {
 // launch kinds, in execution order inside one (level, step)
 constexpr int32_t LAUNCH_PANEL = 0;
 constexpr int32_t LAUNCH_UPDATE = 1;
+constexpr int32_t LAUNCH_ASSEMBLE = 2;  // RL: update matrices scatter-added into ancestors
+
+// RL (Algorithm 4): one column of an update matrix U_J, assembled into column
+// `dst` of an ancestor's factor storage: entry i of the column (the U_J
+// entry src + i) is added at dst + rows[rp + i].
+struct AsmCol {
+  int64_t src;  // U_J(j, j): the column's first entry on or below the diagonal
+  int64_t dst;  // the target column's first entry in Lnz(P)
+  int32_t rp;   // offset of the column's target row positions in the row list
+  int32_t len;  // entries (rows j .. r_J - 1 of U_J)
+};
+static_assert(sizeof(AsmCol) == 24, "AsmCol layout");
 
 // Narrow update tiles (at most NARROW_COLS columns) run one per wavefront
 // (k_update_w, FP64) when a launch holds at least WAVE_SPLIT_MIN of them;
@@ -153,6 +167,13 @@ struct Plan {
   // factor storage: Lnz(J) is m_J x w_J column-major at off[J], ld = m_J
   std::vector<int64_t> off;
   int64_t l_elems = 0;
+  // RL: the update matrices of the supernodes whose cdiv ends in one step,
+  // r_J x r_J column-major each, reused from step to step; they follow the
+  // factor storage in the workspace (ws_elems = l_elems + u_elems)
+  int64_t u_elems = 0;
+  int64_t ws_elems = 0;
+  std::vector<AsmCol> asmcols;
+  std::vector<int32_t> asm_rows;
   std::vector<int64_t> amap;  // input CSC entry -> position in factor storage
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;

@@ -39,7 +39,8 @@ class Options(ctypes.Structure):
                 ("merge_cap", ctypes.c_double), ("reorder", ctypes.c_int32),
                 ("maximal_blocks", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32),
-                ("outer_block", ctypes.c_int32), ("big_tile_min", ctypes.c_int32)]
+                ("outer_block", ctypes.c_int32), ("big_tile_min", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -52,7 +53,8 @@ class Info(ctypes.Structure):
                  "n_panel_tiles", "n_update_tiles", "n_merged_tiles", "n_split_tiles",
                  "n_launches")] + [
                 ("flops_tiles", ctypes.c_double), ("flops_upd_alg", ctypes.c_double),
-                ("flops_panel", ctypes.c_double), ("flops_upd_launch", ctypes.c_double)]
+                ("flops_panel", ctypes.c_double), ("flops_upd_launch", ctypes.c_double),
+                ("u_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -164,7 +166,7 @@ class Symbolic:
 
     def __init__(self, n, colptr, rowidx, ordering="grid", grid=(0, 0, 0, 1), merge_cap=0.125,
                  reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0,
-                 deterministic=True, outer_block=0, big_tile_min=0):
+                 deterministic=True, outer_block=0, big_tile_min=0, method="rlb"):
         L = lib()
         self._cp = np.ascontiguousarray(colptr, np.int64)
         self._ri = np.ascontiguousarray(rowidx, np.int64)
@@ -181,6 +183,7 @@ class Symbolic:
         o.deterministic = 1 if deterministic else 0
         o.outer_block = int(outer_block)
         o.big_tile_min = int(big_tile_min)
+        o.method = {"rlb": 0, "rl": 1}[method]
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)
             o.user_perm = self._up.ctypes.data_as(_c_i64p)

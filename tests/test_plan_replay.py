@@ -84,6 +84,10 @@ def replay_factor(A, expand=False, alt=False, **kw):
                     assert prev is None or (prev and (flags & 2)), "two owners"
                     owner[c + j * ldc + r] = bool(flags & 2)
                 col = acc[:, j].copy()
+                if flags & 4:  # RL's update matrix: written, not added (lower part)
+                    lo = j if flags & 1 else 0
+                    Lb[c + j * ldc + lo: c + j * ldc + m] = -col[lo:]
+                    continue
                 if flags & 1:
                     col[:j] = 0.0
                 Lb[c + j * ldc: c + j * ldc + m] -= col
@@ -94,7 +98,14 @@ def replay_factor(A, expand=False, alt=False, **kw):
         launches = unfused(launches)
     if alt:
         launches = with_alt(launches)
+    AC = s.array("asm_cols").reshape(-1, 4)
+    AR = s.array("asm_rows")
     for kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt, ast, acnt in launches:
+        if kind == 2:
+            # RL: every update-matrix column added into its ancestor column
+            for src, dst, rp, ln in AC[st:st + cnt]:
+                Lb[dst + AR[rp:rp + ln]] += Lb[src:src + ln]
+            continue
         if kind == 0:
             groups = {}
             for t in P[st:st + cnt]:
@@ -255,6 +266,10 @@ CASES = [
      {"outer_block": 64, "big_tile_min": 1}),
     ("lap3d27_11x11x9_atomic_big", lambda: W.small_grid("27pt", (11, 11, 9), seed=26, shift=1e-3),
      {"outer_block": 128, "big_tile_min": 1, "deterministic": False}),
+    # RL (Algorithm 4): update matrices in working storage, then assembly
+    ("rl_lap3d27_13", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                           shift=1e-4), {"method": "rl"}),
+    ("rl_lap2d9_45x38", lambda: W.small_grid("9pt", (45, 38, 1), seed=21), {"method": "rl"}),
     # several wide supernodes in one level, outer blocks of 64 columns
     ("lap3d27_16_outer64", lambda: W.small_grid("27pt", (16, 16, 16), seed=27, lo=0.1, hi=1.0,
                                                 shift=1e-4),

@@ -136,6 +136,10 @@ def main():
                     help="timed repetitions of each time to solution (after one untimed)")
     ap.add_argument("--no-rl", action="store_true",
                     help="skip the RL (Algorithm 4) factorization of the same matrix")
+    ap.add_argument("--ablations", action="store_true",
+                    help="only the FP64 factor under the analysis switches one at a time "
+                         "(maximal blocks, reordering, merge cap, outer blocks, atomic "
+                         "splitting, RL); prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
@@ -162,6 +166,8 @@ def main():
         return
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.ablations:
+        return bench_ablations(args)
     if args.workload == "lap3d27_64":
         A = W.config4()
     elif args.workload == "elast3_40":
@@ -361,6 +367,78 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, sym, args.workload)
+    print(json.dumps(out), flush=True)
+
+
+ABLATIONS = [
+    ("default", {}),
+    ("maximal_blocks_off", {"maximal_blocks": False}),
+    ("reordering_off", {"reorder": False}),
+    ("merge_cap_0", {"merge_cap": 0.0}),
+    ("merge_cap_0.0625", {"merge_cap": 0.0625}),
+    ("merge_cap_0.25", {"merge_cap": 0.25}),
+    ("outer_block_64", {"outer_block": 64}),
+    ("outer_block_512", {"outer_block": 512}),
+    ("atomic_split", {"deterministic": False}),
+    ("big_tiles_128", {"big_tile_min": 256}),
+    ("method_rl", {"method": "rl"}),
+]
+
+
+def bench_ablations(args):
+    """The FP64 factorization of one workload under each analysis switch
+    (one at a time): median device time of the graph-replayed factor over
+    args.steps runs, the plan's block and call counts (Alg. 5), stored
+    entries and padded flops, and the backward error of one solve."""
+    import numpy as np
+    import torch
+
+    from paper_2409_13090_amd import rlb
+    from paper_2409_13090_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    A = {"lap3d27_64": W.config4, "elast3_40": W.config5}.get(args.workload,
+                                                             lambda: W.config2(side=args.side))()
+    vals = torch.from_numpy(A.values).to(dev)
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).to(dev).T.contiguous().T
+    stream = torch.cuda.current_stream()
+    rows = {}
+    F = None
+    for name, kw in ABLATIONS:
+        sym = rlb.Symbolic.from_matrix(A, **kw)
+        info = sym.info()
+        num = rlb.Numeric(sym, rlb.RLB_PREC_FP64)
+        num.set_graph_mode(True)
+        assert num.factor(vals) == 0
+        ms = []
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            num.factor(vals, check=False)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        assert num.status() == 0
+        X = B.clone().T.contiguous().T
+        num.solve(X)
+        be = float(max(num.backward_error(B, X)))
+        F = F or info["flops_exact"]
+        t = statistics.median(ms)
+        rows[name] = {"factor_ms": round(t, 3), "gflops": round(info["flops_exact"] / t / 1e6, 1),
+                      "n_supernodes": info["n_supernodes"], "n_blocks": info["n_blocks"],
+                      "n_calls": info["n_calls"], "nnz_stored": info["nnz_stored"],
+                      "flops_padded": info["flops_padded"], "n_launches": info["n_launches"],
+                      "fp_storage_bytes": info["factor_bytes"], "backward_error": float(f"{be:.3e}")}
+        del num
+        print(json.dumps({"ablation": name, **rows[name]}), file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": rows["default"]["gflops"], "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": rows["default"]["factor_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": WORKLOAD_TEXT.get(args.workload, "").format(side=args.side, n=A.n),
+                      "mode": "ablations of the analysis switches, FP64 factor"},
+           "flops_exact": F, "ablations": rows}
     print(json.dumps(out), flush=True)
 
 

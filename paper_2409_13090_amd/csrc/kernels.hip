@@ -1064,6 +1064,8 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
                                                 const UpdSeg* __restrict__ segs,
                                                 double* __restrict__ L, const T* __restrict__ S) {
   typedef typename Mfma<T>::acc_t acc_t;
+  // K chunk: 16 in FP64, 32 in FP32 (the same LDS bytes, half the barriers)
+  constexpr int KC = 16 * (int)(sizeof(double) / sizeof(T));
   const UpdTile t = tiles[blockIdx.x];
   __shared__ T sX[2][KC][64];  // [k][tile row]
   __shared__ T sY[2][KC][64];  // [k][tile column]

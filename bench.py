@@ -40,6 +40,9 @@ WORKLOAD_TEXT = {
                   "nested dissection + reordering within supernodes, 8 RHS",
     "elast3_40": "elast3_40: 3 dofs per node on 40^3 (n={n}), 7-point coupling with 3x3 SPD "
                  "blocks E*R*diag(1,1,1e-2)*R^T, shift 1e-6*I, 16 RHS",
+    "irr3d_150k": "irr3d_150k: k-nearest-neighbour (k=10) graph Laplacian of {n} random points "
+                  "in the unit cube, weights U[0.5,1.5], shift 1e-2, graph nested dissection + "
+                  "reordering within supernodes, 4 RHS",
 }
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
@@ -115,7 +118,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--side", type=int, default=48)
     ap.add_argument("--workload", default="lap3d27_64",
-                    choices=["lap3d27_64", "lap3d7_48", "batch512", "elast3_40"],
+                    choices=["lap3d27_64", "lap3d7_48", "batch512", "elast3_40", "irr3d_150k"],
                     help="lap3d27_64 (default) carries the FP64 vs FP32-update+refinement "
                          "comparison; the others are the 48^3 7-point workload, the batched "
                          "form and the 3-dof elasticity workload")
@@ -168,14 +171,18 @@ def main():
         return bench_batch(args)
     if args.ablations:
         return bench_ablations(args)
+    order_kw = {}
     if args.workload == "lap3d27_64":
         A = W.config4()
     elif args.workload == "elast3_40":
         A = W.config5()
+    elif args.workload == "irr3d_150k":
+        A = W.irregular3d(150000)
+        order_kw = {"ordering": "graph"}
     else:
         A = W.config2(side=args.side)
     t0 = time.perf_counter()
-    sym = rlb.Symbolic.from_matrix(A)
+    sym = rlb.Symbolic.from_matrix(A, **order_kw)
     t_analyze = time.perf_counter() - t0
     info = sym.info()
     F = info["flops_exact"]
@@ -280,7 +287,7 @@ def main():
     if not args.no_rl:
         # RL (Algorithm 4) on the same matrix and the same symbolic phase:
         # update matrices in working storage, assembled into the ancestors
-        sym_rl = rlb.Symbolic.from_matrix(A, method="rl")
+        sym_rl = rlb.Symbolic.from_matrix(A, method="rl", **order_kw)
         info_rl = sym_rl.info()
         num_rl = rlb.Numeric(sym_rl, rlb.RLB_PREC_FP64)
         num_rl.set_graph_mode(graph)

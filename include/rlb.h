@@ -49,6 +49,9 @@ typedef int32_t rlb_status;
 #define RLB_ORDER_NATURAL 0
 #define RLB_ORDER_GRID_ND 1 /* geometric nested dissection on grid[] */
 #define RLB_ORDER_USER 2
+#define RLB_ORDER_GRAPH_ND 3 /* nested dissection of the adjacency graph: level-structure
+                                bisection from pseudo-peripheral roots, components apart
+                                (general sparse input; no grid needed) */
 
 /* Arithmetic of the bulk SYRK/GEMM updates (POTRF and TRSM are FP64 always). */
 #define RLB_PREC_FP64 0

@@ -44,6 +44,84 @@ import numpy as np
 # orderings
 
 
+def graph_nested_dissection(n, colptr, rowidx, leaf=8, trace=None):
+    """Nested dissection of the adjacency graph of a lower-CSC pattern
+    (general sparse input): each vertex set is split into its connected
+    components (in the order of their smallest vertex); a component of at
+    most `leaf` vertices is emitted ascending; otherwise breadth-first levels
+    are grown from a pseudo-peripheral root (start at the component's
+    smallest vertex, then move to the least-degree vertex of the last level,
+    smallest index on ties, while that gives strictly more levels, at most 8
+    moves), each level in ascending order; the separator is the first level m
+    with 1 <= m <= depth-1 whose cumulative count reaches half the component
+    (else depth-1); the vertices before the separator, then those after it,
+    are dissected the same way, and the separator follows, ascending. A
+    component with fewer than three levels is emitted ascending.
+    When `trace` is a list, every split is appended as (before, after,
+    separator) vertex lists. Returns perm[new] = old."""
+    adj = [set() for _ in range(n)]
+    for j in range(n):
+        for e in range(colptr[j], colptr[j + 1]):
+            i = int(rowidx[e])
+            if i != j:
+                adj[i].add(j)
+                adj[j].add(i)
+    out = []
+
+    def bfs_levels(root, allowed):
+        seen = {root}
+        levels = [[root]]
+        while True:
+            nxt = sorted({u for v in levels[-1] for u in adj[v] if u in allowed and u not in seen})
+            if not nxt:
+                return levels
+            seen.update(nxt)
+            levels.append(nxt)
+
+    def do_set(vs):
+        remaining = set(vs)
+        while remaining:
+            v = min(remaining)
+            comp = set(x for lev in bfs_levels(v, remaining) for x in lev)
+            remaining -= comp
+            do_component(sorted(comp))
+
+    def do_component(comp):
+        if len(comp) <= leaf:
+            out.extend(comp)
+            return
+        cset = set(comp)
+        levels = bfs_levels(comp[0], cset)
+        for _ in range(8):
+            last = levels[-1]
+            deg = [len(adj[w] & cset) for w in last]
+            u = last[deg.index(min(deg))]
+            lu = bfs_levels(u, cset)
+            if len(lu) <= len(levels):
+                break
+            levels = lu
+        depth = len(levels) - 1
+        if depth < 2:
+            out.extend(comp)
+            return
+        m, cum = depth - 1, 0
+        for i in range(depth):
+            cum += len(levels[i])
+            if i >= 1 and 2 * cum >= len(comp):
+                m = i
+                break
+        before = sorted(x for lev in levels[:m] for x in lev)
+        after = sorted(x for lev in levels[m + 1:] for x in lev)
+        if trace is not None:
+            trace.append((before, after, list(levels[m])))
+        do_set(before)
+        do_set(after)
+        out.extend(levels[m])
+
+    do_set(range(n))
+    return np.array(out, np.int64)
+
+
 def nested_dissection(nx, ny, nz, dofs=1):
     """Geometric nested dissection of an nx*ny*nz grid; returns perm[new] = old."""
     out = []
@@ -411,6 +489,8 @@ def analyze(A, ordering="grid", merge_cap=0.125, reorder=True, user_perm=None):
         perm0 = nested_dissection(nx, ny, nz, d)
     elif ordering == "natural":
         perm0 = np.arange(n, dtype=np.int64)
+    elif ordering == "graph":
+        perm0 = graph_nested_dissection(n, A.colptr, A.rowidx)
     elif ordering == "user":
         perm0 = np.asarray(user_perm, np.int64)
     else:

@@ -349,7 +349,7 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
   if (opt) {
     if (opt->struct_size != (int32_t)sizeof(rlb_options))
       return fail(RLB_ERR_ARG, "rlb_options.struct_size mismatch");
-    if (opt->ordering < 0 || opt->ordering > 2) return fail(RLB_ERR_ARG, "bad ordering");
+    if (opt->ordering < 0 || opt->ordering > 3) return fail(RLB_ERR_ARG, "bad ordering");
     if (!(opt->merge_cap >= 0) || opt->merge_cap > 10) return fail(RLB_ERR_ARG, "bad merge_cap");
     if (opt->precision < RLB_PREC_FP64 || opt->precision > RLB_PREC_FP16_UPDATES)
       return fail(RLB_ERR_ARG, "bad precision");

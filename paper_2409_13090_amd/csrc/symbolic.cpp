@@ -72,6 +72,122 @@ void nd_rec(int64_t nx, int64_t ny, int64_t dofs, int64_t x0, int64_t x1, int64_
   }
 }
 
+// Graph nested dissection of the adjacency graph of A (general sparse
+// input; the paper orders with METIS nested dissection, Section 3.1, which is
+// not available here). A vertex set is handled one connected component at a
+// time, components in the order of their smallest vertex. A component of at
+// most GND_LEAF vertices is emitted in ascending order. Otherwise a
+// breadth-first level structure is rooted at a pseudo-peripheral vertex
+// (start at the smallest vertex; while the last level holds a vertex of
+// least degree inside the component -- smallest index on ties -- whose own
+// level structure is deeper, move the root there; at most 8 moves); levels
+// are visited in ascending vertex order. The separator is the first level m
+// (1 <= m <= depth-1) by which the levels hold at least half of the
+// component; the levels before it and after it are dissected in turn (in
+// that order) and the separator is emitted last, ascending. A component
+// whose level structure has fewer than three levels is emitted ascending.
+constexpr int64_t GND_LEAF = 8;
+
+struct GraphND {
+  const std::vector<int64_t>& ap;
+  const std::vector<int32_t>& ai;
+  std::vector<int32_t> mark;   // set id of each vertex
+  std::vector<int32_t> lvl;    // BFS level scratch
+  int32_t next_id = 1;
+  std::vector<int64_t>& out;
+  GraphND(const std::vector<int64_t>& ap_, const std::vector<int32_t>& ai_, int64_t n,
+          std::vector<int64_t>& o)
+      : ap(ap_), ai(ai_), mark(n, 0), lvl(n, -1), out(o) {}
+
+  // breadth-first levels from r inside the set `id`; returns the levels
+  std::vector<std::vector<int64_t>> levels(int64_t r, int32_t id) {
+    std::vector<std::vector<int64_t>> L{{r}};
+    lvl[r] = 0;
+    std::vector<int64_t> touched{r};
+    for (;;) {
+      std::vector<int64_t> nxt;
+      for (int64_t v : L.back())
+        for (int64_t e = ap[v]; e < ap[v + 1]; ++e) {
+          const int64_t u = ai[e];
+          if (mark[u] == id && lvl[u] < 0) {
+            lvl[u] = (int32_t)L.size();
+            nxt.push_back(u);
+            touched.push_back(u);
+          }
+        }
+      if (nxt.empty()) break;
+      std::sort(nxt.begin(), nxt.end());
+      L.push_back(std::move(nxt));
+    }
+    for (int64_t v : touched) lvl[v] = -1;
+    return L;
+  }
+  int64_t degree_in(int64_t v, int32_t id) const {
+    int64_t d = 0;
+    for (int64_t e = ap[v]; e < ap[v + 1]; ++e) d += mark[ai[e]] == id;
+    return d;
+  }
+  // dissect the vertices of `set` (ascending) one component at a time
+  void dissect_set(const std::vector<int64_t>& set) {
+    if (set.empty()) return;
+    const int32_t id = next_id++;
+    for (int64_t v : set) mark[v] = id;
+    for (int64_t v : set) {
+      if (mark[v] != id) continue;  // already in an earlier component
+      std::vector<std::vector<int64_t>> L = levels(v, id);
+      std::vector<int64_t> comp;
+      for (auto& l : L) comp.insert(comp.end(), l.begin(), l.end());
+      std::sort(comp.begin(), comp.end());
+      const int32_t cid = next_id++;
+      for (int64_t u : comp) mark[u] = cid;
+      dissect_component(comp, cid);
+    }
+  }
+  void dissect_component(const std::vector<int64_t>& comp, int32_t id) {
+    const int64_t sz = (int64_t)comp.size();
+    if (sz <= GND_LEAF) {
+      out.insert(out.end(), comp.begin(), comp.end());
+      return;
+    }
+    std::vector<std::vector<int64_t>> L = levels(comp[0], id);
+    for (int it = 0; it < 8; ++it) {
+      int64_t u = -1, du = 0;
+      for (int64_t w : L.back()) {
+        const int64_t d = degree_in(w, id);
+        if (u < 0 || d < du) {
+          u = w;
+          du = d;
+        }
+      }
+      std::vector<std::vector<int64_t>> Lu = levels(u, id);
+      if (Lu.size() <= L.size()) break;
+      L = std::move(Lu);
+    }
+    const int64_t depth = (int64_t)L.size() - 1;
+    if (depth < 2) {
+      out.insert(out.end(), comp.begin(), comp.end());
+      return;
+    }
+    int64_t m = depth - 1, cum = 0;
+    for (int64_t i = 0; i <= depth - 1; ++i) {
+      cum += (int64_t)L[i].size();
+      if (i >= 1 && 2 * cum >= sz) {
+        m = i;
+        break;
+      }
+    }
+    std::vector<int64_t> a, b;
+    for (int64_t i = 0; i < m; ++i) a.insert(a.end(), L[i].begin(), L[i].end());
+    for (int64_t i = m + 1; i <= depth; ++i) b.insert(b.end(), L[i].begin(), L[i].end());
+    std::sort(a.begin(), a.end());
+    std::sort(b.begin(), b.end());
+    const std::vector<int64_t> sep = L[m];
+    dissect_set(a);
+    dissect_set(b);
+    out.insert(out.end(), sep.begin(), sep.end());
+  }
+};
+
 // --- graph helpers ------------------------------------------------------------
 
 // Symmetric adjacency (no diagonal) of P A P^T in CSR, rows sorted.
@@ -452,6 +568,14 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx, const Analy
     }
     p0.reserve(n);
     nd_rec(nx, ny, d, 0, nx, 0, ny, 0, nz, p0);
+  } else if (opt.ordering == 3) {
+    std::vector<int64_t> ident(n), ap;
+    std::iota(ident.begin(), ident.end(), 0);
+    std::vector<int32_t> ai;
+    permuted_adjacency(n, s.colptr, s.rowidx, ident, ap, ai);
+    p0.reserve(n);
+    GraphND g(ap, ai, n, p0);
+    g.dissect_set(ident);
   } else if (opt.ordering == 2) {
     if (!opt.user_perm) {
       err = "user ordering without a permutation";

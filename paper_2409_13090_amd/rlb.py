@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librlb.so")
 RLB_ORDER_NATURAL = 0
 RLB_ORDER_GRID_ND = 1
 RLB_ORDER_USER = 2
+RLB_ORDER_GRAPH_ND = 3
 RLB_PREC_FP64 = 0
 RLB_PREC_FP32_UPDATES = 1
 RLB_PREC_BF16_UPDATES = 2
@@ -173,7 +174,7 @@ class Symbolic:
         o = Options()
         _check(L.rlb_default_options(ctypes.byref(o)))
         o.ordering = {"natural": RLB_ORDER_NATURAL, "grid": RLB_ORDER_GRID_ND,
-                      "user": RLB_ORDER_USER}[ordering]
+                      "user": RLB_ORDER_USER, "graph": RLB_ORDER_GRAPH_ND}[ordering]
         for k in range(4):
             o.grid[k] = int(grid[k])
         o.merge_cap = float(merge_cap)

@@ -291,3 +291,31 @@ def from_dense_lower(Ad, grid=(0, 0, 0, 1), name="dense"):
     vals = Ad[rows, cols]
     colptr, rowidx, values = _lower_csc(n, rows, cols, vals)
     return SparseSPD(n, colptr, rowidx, values, grid, name)
+
+
+def irregular3d(n, k=10, seed=6, shift=1e-2, nrhs=4, name=None):
+    """Irregular SPD workload (general sparse input, no grid): n points drawn
+    uniform in the unit cube, each joined to its k nearest neighbours (the
+    union of both directions), one weight U[0.5,1.5] per edge drawn in
+    ascending (lower, upper) endpoint order, A_ij = -w, A_ii = sum of
+    incident weights + shift; the points are numbered in the order drawn, so
+    the natural order has no locality. nrhs right-hand sides N(0,1) last."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, (n, 3))
+    _, nb = cKDTree(pts).query(pts, k=k + 1)
+    a = np.repeat(np.arange(n, dtype=np.int64), k)
+    b = nb[:, 1:].reshape(-1).astype(np.int64)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key = np.unique(lo * n + hi)
+    lo, hi = key // n, key % n
+    w = rng.uniform(0.5, 1.5, lo.size)
+    inc = np.bincount(lo, weights=w, minlength=n) + np.bincount(hi, weights=w, minlength=n)
+    rows = np.concatenate([np.arange(n, dtype=np.int64), hi])
+    cols = np.concatenate([np.arange(n, dtype=np.int64), lo])
+    vals = np.concatenate([inc + shift, -w])
+    colptr, rowidx, values = _lower_csc(n, rows, cols, vals)
+    A = SparseSPD(n, colptr, rowidx, values, (0, 0, 0, 1), name or f"irr3d_{n}_k{k}",
+                  meta={"shift": shift, "k": k})
+    A.rhs = draw_rhs(rng, n, nrhs)
+    return A

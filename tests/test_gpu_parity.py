@@ -369,3 +369,18 @@ def test_rl_method_matches_oracle(name, make):
     print(f"[case] RL {name} rel_err={err:.3e} u_bytes={s.info()['u_bytes']}", flush=True)
     if A.rhs is not None:
         solve_check(num, A)
+
+
+@pytest.mark.parametrize("n,method", [(3000, "rlb"), (6000, "rlb"), (3000, "rl")])
+def test_irregular_graph_ordering_matches_oracle(n, method):
+    """General sparse input: a k-nearest-neighbour graph Laplacian of random
+    points (no grid) ordered by graph nested dissection, the oracle deriving
+    the same ordering on its own."""
+    A = W.irregular3d(n, k=10, seed=40 + n % 7)
+    o, f = oracle_factor(A, ordering="graph")
+    s, num, vals, info = gpu_factor(A, ordering="graph", method=method)
+    assert info == 0
+    assert np.array_equal(s.array("perm"), o["perm"])
+    err = compare_factor(num.export(), f, A.n)
+    print(f"[case] irregular n={n} {method} rel_err={err:.3e}", flush=True)
+    solve_check(num, A)

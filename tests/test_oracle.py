@@ -462,3 +462,55 @@ def test_merge_selection_order_and_stop_rule(dims, kind):
     # the merged partition is the one the analysis reports
     r = osym.analyze(A, merge_cap=0.125, reorder=False)
     assert np.array_equal(r["sn_ptr"], ptr)
+
+
+def _pattern_from_edges(n, edges):
+    A = np.eye(n) * 4.0
+    for a, b in edges:
+        A[a, b] = A[b, a] = -1.0
+    return W.from_dense_lower(A)
+
+
+def test_graph_nested_dissection_hand_cases():
+    """Orderings worked out by hand from the rule (BFS levels from a
+    pseudo-peripheral root, separator = first level reaching half the
+    component, parts before/after dissected, separator last; leaves of at
+    most 8 vertices and components of fewer than three levels ascending)."""
+    path = _pattern_from_edges(20, [(i, i + 1) for i in range(19)])
+    assert osym.graph_nested_dissection(path.n, path.colptr, path.rowidx).tolist() == \
+        [0, 1, 2, 3, 5, 6, 7, 8, 4, 10, 11, 12, 13, 15, 16, 17, 18, 19, 14, 9]
+    # components in the order of their smallest vertex, each on its own: a
+    # path over the even vertices 0..18 (dissected at its fifth vertex), a
+    # path 1-3-5 (a leaf) and the isolated vertices 7, 9, ..., 19, 20, 21
+    two = _pattern_from_edges(22, [(i, i + 2) for i in range(0, 18, 2)] + [(1, 3), (3, 5)])
+    assert osym.graph_nested_dissection(two.n, two.colptr, two.rowidx).tolist() == \
+        [0, 2, 4, 6, 10, 12, 14, 16, 18, 8, 1, 3, 5, 7, 9, 11, 13, 15, 17, 19, 20, 21]
+    # a clique of 12 has two levels from any root: emitted ascending
+    clique = _pattern_from_edges(12, [(a, b) for a in range(12) for b in range(a)])
+    assert osym.graph_nested_dissection(clique.n, clique.colptr, clique.rowidx).tolist() == \
+        list(range(12))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_graph_nested_dissection_separates(seed):
+    """Every split of the graph ordering: the separator removes every edge
+    between the two parts, the three sets partition the component, and the
+    final order is a permutation; and the product's ordering equals it."""
+    from paper_2409_13090_amd import rlb
+    A = W.irregular3d(1500 + 500 * seed, k=8, seed=seed)
+    trace = []
+    perm = osym.graph_nested_dissection(A.n, A.colptr, A.rowidx, trace=trace)
+    assert np.array_equal(np.sort(perm), np.arange(A.n))
+    assert len(trace) > 10
+    adj = [set() for _ in range(A.n)]
+    for j in range(A.n):
+        for i in A.rowidx[A.colptr[j]:A.colptr[j + 1]]:
+            if i != j:
+                adj[i].add(j)
+                adj[j].add(int(i))
+    for before, after, sep in trace:
+        b = set(before)
+        assert not any(adj[v] & b for v in after)
+        assert not (b & set(after)) and not (b & set(sep)) and not (set(after) & set(sep))
+    s = rlb.Symbolic(A.n, A.colptr, A.rowidx, ordering="graph")
+    assert np.array_equal(s.array("perm_nd"), perm)

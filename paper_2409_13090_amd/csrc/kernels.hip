@@ -275,6 +275,41 @@ __device__ __forceinline__ UpdSeg uniform_seg(const UpdSeg& g) {
 
 constexpr int KC = 16;  // K chunk staged per LDS buffer
 
+// Which of this thread's 16 accumulator elements of a 64x64 target tile lie in
+// the rectangle of at least one of the tile's contributions: bit
+// bj*8 + bi*4 + v for element (bj, bi, v) of a wavefront quarter at rows wr,
+// columns wc (Lay gives the accumulator layout). Every other element receives
+// no update, so it is neither read nor written: at the lower levels the
+// rectangles of a target tile cover a quarter to a half of it. Tiles with more
+// than COVER_SEGS contributions are taken as fully covered.
+constexpr int COVER_SEGS = 32;
+template <typename Lay>
+__device__ __forceinline__ unsigned cover_bits(const UpdTile& t, const UpdSeg* __restrict__ segs,
+                                               int wr, int wc, int lane) {
+  if (t.nseg > COVER_SEGS) return 0xffffu;
+  int row[2], col[2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) row[bi] = wr + 16 * bi + (lane & 15);
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) col[bj][v] = wc + 16 * bj + Lay::drow(lane, v);
+  unsigned m = 0;
+  for (int e = 0; e < t.nseg; ++e) {
+    const UpdSeg& g = segs[t.seg0 + e];
+    const int ra = uni32(g.ra), rb = uni32(g.rb), ca = uni32(g.ca), cb = uni32(g.cb);
+    unsigned cbits = 0;  // bits bj*8 + v: column inside [ca, cb)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cbits |= (col[bj][v] >= ca && col[bj][v] < cb) ? 1u << (bj * 8 + v) : 0u;
+    if (row[0] >= ra && row[0] < rb) m |= cbits;
+    if (row[1] >= ra && row[1] < rb) m |= cbits << 4;
+  }
+  return m;
+}
+
 
 // One target tile of a launch whose tiles all hold a single contribution
 // with k <= 64 and a single owner (the trailing updates of a step): every
@@ -1081,6 +1116,8 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
   const bool atomic = t.flags & 2;
   const bool assign = t.flags & 4;  // write -(sum) without reading the target
 
+  // elements met by a contribution (an update matrix of RL is written whole)
+  const unsigned cover = assign ? 0xffffu : cover_bits<Mfma<T>>(t, segs, wr, wc, lane);
   // the target values of a tile with a single owner, loaded up front (no
   // other workgroup of the launch writes it); addresses clamped into the tile
   double cv[2][2][4] = {};
@@ -1093,7 +1130,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
         for (int v = 0; v < 4; ++v) {
           const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
           const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
-          cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+          if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
         }
   }
 
@@ -1206,7 +1243,8 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
       for (int v = 0; v < 4; ++v) {
         const int row = wr + 16 * bi + (lane & 15);
         const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
-        if (row < t.m && col < t.n && (!diag || row >= col)) {
+        if (((cover >> (bj * 8 + bi * 4 + v)) & 1u) && row < t.m && col < t.n &&
+            (!diag || row >= col)) {
           double* p = C + (int64_t)col * ldc + row;
           if (atomic)
             atomicAdd(p, -(double)acc[bj][bi][v]);
@@ -1583,7 +1621,9 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
   const bool atomic = t.flags & 2;
-  double cv[2][2][4];
+  // elements met by a contribution (the FP32 accumulator layout)
+  const unsigned cover = cover_bits<Mfma<float>>(t, segs, wr, wc, lane);
+  double cv[2][2][4] = {};
   if (!atomic) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
@@ -1593,7 +1633,7 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
         for (int v = 0; v < 4; ++v) {
           const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
           const int col = min(wc + 16 * bj + 4 * (lane >> 4) + v, t.n - 1);
-          cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+          if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
         }
   }
   v4f acc[2][2];
@@ -1700,7 +1740,8 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
       for (int v = 0; v < 4; ++v) {
         const int row = wr + 16 * bi + (lane & 15);
         const int col = wc + 16 * bj + 4 * (lane >> 4) + v;
-        if (row < t.m && col < t.n && (!diag || row >= col)) {
+        if (((cover >> (bj * 8 + bi * 4 + v)) & 1u) && row < t.m && col < t.n &&
+            (!diag || row >= col)) {
           double* p = C + (int64_t)col * ldc + row;
           if (atomic)
             atomicAdd(p, -accd[bj][bi][v]);

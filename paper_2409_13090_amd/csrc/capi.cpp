@@ -64,6 +64,16 @@ struct DevPlan {
   int64_t* a_src = nullptr;
   AsmCol* asmcols = nullptr;    // RL assembly
   int32_t* asm_rows = nullptr;
+  // chained solve launches: signals each step counter waits for, and the
+  // counters (step counters, one ticket counter per chained launch, the
+  // timeout word), cleared at the start of every solve
+  int32_t* sneed = nullptr;
+  int32_t* chain = nullptr;
+  int64_t nslots = 0, nchains = 0;
+  ChainArgs chain_args(int32_t c) const {
+    if (c < 0 || !chain) return ChainArgs{nullptr, nullptr, nullptr, nullptr};
+    return ChainArgs{chain + nslots + c, chain, sneed, chain + nslots + nchains};
+  }
   void release() {
     dfree(panels);
     dfree(updates);
@@ -79,6 +89,8 @@ struct DevPlan {
     dfree(a_src);
     dfree(asmcols);
     dfree(asm_rows);
+    dfree(sneed);
+    dfree(chain);
   }
 };
 
@@ -93,6 +105,15 @@ rlb_status upload_solve(const Symbolic& s, int64_t base, DevPlan& d) {
   if ((st = upload(&d.a_rowptr, s.plan.a_rowptr))) return st;
   if ((st = upload(&d.a_col, s.plan.a_col))) return st;
   if ((st = upload(&d.a_src, s.plan.a_src))) return st;
+  d.nslots = (int64_t)s.plan.sneed.size();
+  d.nchains = s.plan.nchains;
+  if (d.nchains > 0) {
+    if ((st = upload(&d.sneed, s.plan.sneed))) return st;
+    HIP_OK(hipMalloc((void**)&d.chain, (d.nslots + d.nchains + 1) * sizeof(int32_t)));
+    // cleared once here as well: the timeout word is read by calls that
+    // synchronize, also on a handle that has not solved yet
+    HIP_OK(hipMemset(d.chain, 0, (d.nslots + d.nchains + 1) * sizeof(int32_t)));
+  }
   return RLB_OK;
 }
 
@@ -144,15 +165,28 @@ struct SolveScratch {
 // already gathered into sc.y (factored order, ld = n); the solution ends in sc.x
 void enqueue_solve_levels(const Symbolic& s, const DevPlan& d, const double* L, SolveScratch& sc,
                           int nrhs, hipStream_t st) {
+  // counters of the chained launches start at zero (a fill kernel, which a
+  // captured graph replays correctly)
+  if (d.chain) launch_zero_i32(d.chain, d.nslots + d.nchains + 1, st);
   for (const SolveLaunch& l : s.plan.slaunches) {
     const SolveTile* t = d.stiles + l.start;
     if (l.kind == SOLVE_FWD)
-      launch_fwd_step(t, l.count, d.gl, L, sc.y, sc.z, nrhs, s.n, st);
+      launch_fwd_step(t, l.count, d.gl, L, sc.y, sc.z, nrhs, s.n, st, d.chain_args(l.chain));
     else if (l.kind == SOLVE_BELOW)
       launch_bwd_below(t, l.count, d.gl, L, sc.x, sc.z, nrhs, s.n, st);
     else
-      launch_bwd_step(t, l.count, L, sc.z, sc.x, nrhs, s.n, st);
+      launch_bwd_step(t, l.count, L, sc.z, sc.x, nrhs, s.n, st, d.chain_args(l.chain));
   }
+}
+
+// after a synchronization: a chained solve launch whose wait timed out (a
+// plan error) makes the solution invalid
+rlb_status chain_status(const DevPlan& d) {
+  if (!d.chain) return RLB_OK;
+  int32_t err = 0;
+  HIP_OK(hipMemcpy(&err, d.chain + d.nslots + d.nchains, sizeof(err), hipMemcpyDeviceToHost));
+  return err ? fail(RLB_ERR_HIP, "a chained solve launch timed out waiting for its inputs")
+             : RLB_OK;
 }
 
 rlb_status solve_into(const Symbolic& s, const DevPlan& d, SolveScratch& sc, const double* L,
@@ -185,6 +219,7 @@ rlb_status backward_errors(const Symbolic& s, const DevPlan& d, SolveScratch& sc
   unsigned long long h[3 * SOLVE_MAXRHS + 1];
   HIP_OK(hipMemcpyAsync(h, sc.norms, sizeof(h), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
+  if (rlb_status ce = chain_status(d)) return ce;
   double an;
   if (need_a) {
     std::memcpy(&an, &h[3 * SOLVE_MAXRHS], sizeof(double));
@@ -467,16 +502,18 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       int64_t v[3] = {t.diag, t.ld, t.nb};
       tmp.insert(tmp.end(), v, v + 3);
     }
-  } else if (w == "solve_tiles") {  // off, ld, f, w, gl, c0, nb, r0, r1, flags, pad per tile
+  } else if (w == "solve_tiles") {  // off, ld, f, w, gl, c0, nb, r0, r1, flags, cslot per tile
     for (const SolveTile& t : s.plan.stiles) {
-      int64_t v[11] = {t.off, t.ld, t.f, t.w, t.gl, t.c0, t.nb, t.r0, t.r1, t.flags, t.pad};
+      int64_t v[11] = {t.off, t.ld, t.f, t.w, t.gl, t.c0, t.nb, t.r0, t.r1, t.flags, t.cslot};
       tmp.insert(tmp.end(), v, v + 11);
     }
-  } else if (w == "solve_launches") {  // kind, level, first tile, tile count per launch
+  } else if (w == "solve_launches") {  // kind, level, first tile, tile count, chain per launch
     for (const SolveLaunch& l : s.plan.slaunches) {
-      int64_t v[4] = {l.kind, l.level, l.start, l.count};
-      tmp.insert(tmp.end(), v, v + 4);
+      int64_t v[5] = {l.kind, l.level, l.start, l.count, l.chain};
+      tmp.insert(tmp.end(), v, v + 5);
     }
+  } else if (w == "solve_need") {  // signals each step counter of the chained launches waits for
+    for (int32_t v : s.plan.sneed) tmp.push_back(v);
   } else if (w == "update_segs") {  // x, y, lds, k, ra, rb, ca, cb, src per contribution
     for (const UpdSeg& g : s.plan.segs) {
       int64_t v[9] = {g.x, g.y, g.lds, g.k, g.ra, g.rb, g.ca, g.cb, g.src};

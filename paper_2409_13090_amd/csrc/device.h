@@ -19,6 +19,16 @@ constexpr int64_t NOALLOC_SOLVE_ELEMS = int64_t(1) << 21;
 // device (looked up once per device)
 hipError_t noalloc_solve_scratch(double** out);
 
+// the counters of a chained solve launch (tick == nullptr: a plain launch,
+// one tile per workgroup in grid order)
+struct ChainArgs {
+  int* tick;        // ticket counter of the launch
+  int* cnt;         // step counters
+  const int* need;  // signals each step counter waits for
+  int* err;         // set when a wait times out
+};
+void launch_zero_i32(int* p, int64_t n, hipStream_t st);
+
 // one coefficient per right-hand-side column, passed by value
 struct ColCoef {
   double v[SOLVE_MAXRHS];
@@ -56,11 +66,11 @@ void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStr
 void launch_pivthr(const double* vals, const int64_t* dsrc, int64_t n, double u, double* thr,
                    unsigned long long* amax, hipStream_t st);
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
-                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st);
+                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st, ChainArgs ca);
 void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                       const double* x, double* z, int nrhs, int64_t ldy, hipStream_t st);
 void launch_bwd_step(const SolveTile* tiles, int64_t count, const double* L, double* z, double* x,
-                     int nrhs, int64_t ldy, hipStream_t st);
+                     int nrhs, int64_t ldy, hipStream_t st, ChainArgs ca);
 void launch_perm_in(const int64_t* perm, const double* b, int64_t ldb, double* y, int64_t ldy,
                     int64_t n, int nrhs, hipStream_t st);
 void launch_perm_out(const int64_t* perm, const double* y, int64_t ldy, double* x, int64_t ldx,

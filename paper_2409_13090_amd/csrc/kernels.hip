@@ -1892,6 +1892,55 @@ __global__ __launch_bounds__(256) void k_pair_inverse(const DiagTile* __restrict
       for (int c = 0; c < 4; ++c) D[(int64_t)(64 + 4 * ti + r) * ld + 4 * tj + c] = -acc[r][c];
 }
 
+// Chained solve launches: all steps of a level in one launch. A workgroup
+// takes the next tile in plan order by ticket when it starts, so every
+// earlier tile is held by a running or finished workgroup and the earliest
+// unfinished tile never waits: the launch cannot deadlock, whatever the
+// number of resident workgroups. A tile waits until the counter of its step
+// has the number of signals the plan counted (one from each earlier tile
+// that writes into the step's columns; agent-scope acquire after the wait,
+// release before each signal, since the tiles run on different XCDs with
+// their own L2), and then signals the counters of the steps it writes into.
+// A wait that exceeds CHAIN_SPIN_LIMIT sleeps sets *err and goes on (a plan
+// error: the result is then wrong but the launch still ends).
+constexpr int CHAIN_SPIN_LIMIT = 1 << 22;
+constexpr int CHAIN_STEP = 128;  // columns of a solve step
+
+__device__ __forceinline__ int chain_tile(const ChainArgs& ca) {
+  if (!ca.tick) return (int)blockIdx.x;
+  __shared__ int s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(ca.tick, 1);
+  __syncthreads();
+  return s_ticket;
+}
+
+__device__ __forceinline__ void chain_wait(const ChainArgs& ca, int slot) {
+  if (threadIdx.x == 0) {
+    const int need = ca.need[slot];
+    for (int spins = 0;
+         __hip_atomic_load(ca.cnt + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need;
+         ++spins) {
+      if (spins >= CHAIN_SPIN_LIMIT) {
+        atomicOr(ca.err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// every thread calls it (a workgroup barrier: all of the tile's writes done)
+__device__ __forceinline__ void chain_signal(const ChainArgs& ca, int slot0, int s_lo, int s_hi) {
+  __syncthreads();
+  if (threadIdx.x == 0 && s_lo <= s_hi) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    for (int st = s_lo; st <= s_hi; ++st)
+      __hip_atomic_fetch_add(ca.cnt + slot0 + st, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // forward step over one or two 64-column chunks of a supernode (nb <= 128),
 // split by chunk over the workgroups (flags bit 1: the second chunk). With
 // inv(L_DD) = [V0 0; W V1] (the stored inverses of the chunks' diagonal
@@ -1907,8 +1956,9 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
                                                   const int32_t* __restrict__ gl,
                                                   const double* __restrict__ L,
                                                   double* __restrict__ y, double* __restrict__ z,
-                                                  int nrhs, int64_t ldy) {
-  const SolveTile t = tiles[blockIdx.x];
+                                                  int nrhs, int64_t ldy, ChainArgs ca) {
+  const SolveTile t = tiles[chain_tile(ca)];
+  const bool chained = ca.tick && t.cslot >= 0;
   const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6;
   const double* Lj = L + t.off;
   const int64_t ld = t.ld;
@@ -1937,6 +1987,8 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
   load_rows(t.r0);
   stage_inv(V0, Lj, ld, cc, nbc, tid);
   if (half) stage_w(W, Lj, ld, t.c0, nbB, tid);
+  // the step's right-hand side is final once every earlier step's rows are in
+  if (chained) chain_wait(ca, t.cslot + t.c0 / CHAIN_STEP);
   for (int e = tid; e < 128 * nrhs; e += 256) {
     const int i = e & 127, r = e >> 7;
     ys[r * 128 + i] = i < t.nb ? y[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
@@ -1986,12 +2038,17 @@ __global__ __launch_bounds__(256) void k_fwd_step(const SolveTile* __restrict__ 
       for (int r = cg; r < nrhs; r += 4) {
         const double acc = (part[(0 * nrhs + r) * 64 + row] + part[(1 * nrhs + r) * 64 + row]) +
                            (part[(2 * nrhs + r) * 64 + row] + part[(3 * nrhs + r) * 64 + row]);
-        if (q < t.w && nbB == 0)
+        if (q < t.w && nbB == 0 && !ca.tick)
           y[(int64_t)r * ldy + gqb] -= acc;
         else
           atomicAdd(&y[(int64_t)r * ldy + gqb], -acc);
       }
     __syncthreads();  // the block's partial sums are read before the next block's
+  }
+  if (chained && t.r0 < t.w) {
+    // the later steps of the supernode whose columns these rows are
+    const int s_lo = max(t.r0 / CHAIN_STEP, t.c0 / CHAIN_STEP + 1);
+    chain_signal(ca, t.cslot, s_lo, (min(t.r1, t.w) - 1) / CHAIN_STEP);
   }
 }
 
@@ -2066,8 +2123,9 @@ __global__ __launch_bounds__(256) void k_bwd_below(const SolveTile* __restrict__
 __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ tiles,
                                                   const double* __restrict__ L,
                                                   double* __restrict__ z, double* __restrict__ x,
-                                                  int nrhs, int64_t ldy) {
-  const SolveTile t = tiles[blockIdx.x];
+                                                  int nrhs, int64_t ldy, ChainArgs ca) {
+  const SolveTile t = tiles[chain_tile(ca)];
+  const bool chained = ca.tick && t.cslot >= 0;
   const int tid = threadIdx.x, row = tid & 63, cg = tid >> 6;
   const double* Lj = L + t.off;
   const int64_t ld = t.ld;
@@ -2091,6 +2149,8 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
   }
   stage_inv(V, Lj, ld, cc, nbc, tid);
   if (!half && nbB > 0) stage_w(W, Lj, ld, t.c0, nbB, tid);
+  // the step's columns are final once every later step has pushed into them
+  if (chained) chain_wait(ca, t.cslot + t.c0 / CHAIN_STEP);
   for (int e = tid; e < 128 * nrhs; e += 256) {
     const int i = e & 127, r = e >> 7;
     zs[r][i] = i < t.nb ? z[(int64_t)r * ldy + t.f + t.c0 + i] : 0.0;
@@ -2129,11 +2189,12 @@ __global__ __launch_bounds__(256) void k_bwd_step(const SolveTile* __restrict__ 
         a1 += Lb[i + 1][c] * xs[r][i + 1];
       }
       double* p = &z[(int64_t)r * ldy + t.f + t.r0 + c];
-      if (nbB > 0)
+      if (nbB > 0 || ca.tick)
         atomicAdd(p, -(a0 + a1));
       else
         *p -= a0 + a1;
     }
+  if (chained && push) chain_signal(ca, t.cslot, t.r0 / CHAIN_STEP, t.r0 / CHAIN_STEP);
 }
 
 // y[k] = b[perm[k]] (gather into the factored order) and back
@@ -2416,11 +2477,11 @@ void launch_pair_inverse(const DiagTile* tiles, int64_t count, double* L, hipStr
   hipLaunchKernelGGL(k_pair_inverse, dim3((unsigned)count), dim3(256), 0, st, tiles, L);
 }
 void launch_fwd_step(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
-                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st) {
+                     double* y, double* z, int nrhs, int64_t ldy, hipStream_t st, ChainArgs ca) {
   if (count <= 0) return;
   const size_t dyn = sizeof(double) * (128 + 64) * (size_t)nrhs;
   hipLaunchKernelGGL(k_fwd_step, dim3((unsigned)count), dim3(256), dyn, st, tiles, gl, L, y, z,
-                     nrhs, ldy);
+                     nrhs, ldy, ca);
 }
 void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, const double* L,
                       const double* x, double* z, int nrhs, int64_t ldy, hipStream_t st) {
@@ -2429,10 +2490,18 @@ void launch_bwd_below(const SolveTile* tiles, int64_t count, const int32_t* gl, 
                      nrhs, ldy);
 }
 void launch_bwd_step(const SolveTile* tiles, int64_t count, const double* L, double* z, double* x,
-                     int nrhs, int64_t ldy, hipStream_t st) {
+                     int nrhs, int64_t ldy, hipStream_t st, ChainArgs ca) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_bwd_step, dim3((unsigned)count), dim3(256), 0, st, tiles, L, z, x, nrhs,
-                     ldy);
+                     ldy, ca);
+}
+__global__ void k_zero_i32(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+void launch_zero_i32(int* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, (int)n);
 }
 void launch_perm_in(const int64_t* perm, const double* b, int64_t ldb, double* y, int64_t ldy,
                     int64_t n, int nrhs, hipStream_t st) {

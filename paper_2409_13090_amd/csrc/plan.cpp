@@ -846,20 +846,39 @@ int build_plan(Symbolic& s, std::string& err) {
       t.f = (int32_t)s.sn_ptr[J];
       t.w = (int32_t)W(J);
       t.gl = (int32_t)s.gl_ptr[J];
-      t.c0 = t.nb = t.r0 = t.r1 = t.flags = t.pad = 0;
+      t.c0 = t.nb = t.r0 = t.r1 = t.flags = 0;
+      t.cslot = -1;
       return t;
     };
-    auto push_launch = [&](int32_t kind, int32_t h, int64_t start) {
+    auto push_launch = [&](int32_t kind, int32_t h, int64_t start, int32_t chain) {
       int64_t cnt = (int64_t)p.stiles.size() - start;
-      if (cnt) p.slaunches.push_back(SolveLaunch{kind, h, start, cnt});
+      if (cnt) p.slaunches.push_back(SolveLaunch{kind, h, start, cnt, chain, 0});
+    };
+    p.sneed.clear();
+    p.nchains = 0;
+    // A level of several steps runs as one chained launch: its supernodes of
+    // two or more steps get a counter per step. Returns the counter base of
+    // supernode J (or -1).
+    auto chain_slots = [&](int64_t J) -> int32_t {
+      const int64_t steps = (W(J) + SB - 1) / SB;
+      if (steps < 2) return -1;
+      const int32_t base = (int32_t)p.sneed.size();
+      p.sneed.resize(p.sneed.size() + steps, 0);
+      return base;
     };
     for (int32_t h = 0; h < p.nlevels; ++h) {
       int64_t steps = 0;
       for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
         steps = std::max<int64_t>(steps, (W(p.lvl_sn[q]) + SB - 1) / SB);
+      const bool chain = steps >= 2;
+      std::vector<int32_t> cslot(p.lvl_ptr[h + 1] - p.lvl_ptr[h], -1);
+      if (chain)
+        for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
+          cslot[q - p.lvl_ptr[h]] = chain_slots(p.lvl_sn[q]);
+      const int64_t lstart = (int64_t)p.stiles.size();
       for (int64_t k = 0; k < steps; ++k) {
         int64_t start = (int64_t)p.stiles.size();
-        // rows per workgroup: FWD_ROWS, or FWD_ROWS_BIG when the launch would
+        // rows per workgroup: FWD_ROWS, or FWD_ROWS_BIG when the step would
         // otherwise hold more than FWD_BIG_LAUNCH workgroups (then each
         // workgroup's chunk solve serves more rows)
         int64_t nwg = 0;
@@ -874,6 +893,7 @@ int build_plan(Symbolic& s, std::string& err) {
           int64_t J = p.lvl_sn[q], w = W(J), m = M(J);
           if (k * SB >= w) continue;
           SolveTile t = base_tile(J);
+          t.cslot = cslot[q - p.lvl_ptr[h]];
           t.c0 = (int32_t)(k * SB);
           t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
           int64_t lo = t.c0 + t.nb;
@@ -884,10 +904,16 @@ int build_plan(Symbolic& s, std::string& err) {
               t.r1 = (int32_t)std::min<int64_t>(m, lo + rows * (i + 1));
               t.flags = (i == 0 ? 1 : 0) | (half << 1);
               p.stiles.push_back(t);
+              // the later steps of J whose columns its rows meet wait for it
+              if (t.cslot >= 0 && t.r0 < t.w) {
+                const int64_t s0 = t.r0 / SB, s1 = (std::min(t.r1, t.w) - 1) / SB;
+                for (int64_t st = std::max<int64_t>(s0, k + 1); st <= s1; ++st) ++p.sneed[t.cslot + st];
+              }
             }
         }
-        push_launch(SOLVE_FWD, h, start);
+        if (!chain) push_launch(SOLVE_FWD, h, start, -1);
       }
+      if (chain) push_launch(SOLVE_FWD, h, lstart, p.nchains++);
     }
     for (int32_t h = p.nlevels - 1; h >= 0; --h) {
       int64_t start = (int64_t)p.stiles.size();
@@ -905,13 +931,20 @@ int build_plan(Symbolic& s, std::string& err) {
             p.stiles.push_back(t);
           }
       }
-      push_launch(SOLVE_BELOW, h, start);
+      push_launch(SOLVE_BELOW, h, start, -1);
+      const bool chain = steps >= 2;
+      std::vector<int32_t> cslot(p.lvl_ptr[h + 1] - p.lvl_ptr[h], -1);
+      if (chain)
+        for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q)
+          cslot[q - p.lvl_ptr[h]] = chain_slots(p.lvl_sn[q]);
+      const int64_t lstart = (int64_t)p.stiles.size();
       for (int64_t k = steps - 1; k >= 0; --k) {
         start = (int64_t)p.stiles.size();
         for (int64_t q = p.lvl_ptr[h]; q < p.lvl_ptr[h + 1]; ++q) {
           int64_t J = p.lvl_sn[q], w = W(J);
           if (k * SB >= w) continue;
           SolveTile t = base_tile(J);
+          t.cslot = cslot[q - p.lvl_ptr[h]];
           t.c0 = (int32_t)(k * SB);
           t.nb = (int32_t)std::min<int64_t>(SB, w - k * SB);
           const int64_t earlier = k * SB / NB;  // 64-column chunks before the step
@@ -921,10 +954,13 @@ int build_plan(Symbolic& s, std::string& err) {
               t.r1 = (int32_t)(earlier == 0 ? 0 : j * NB + NB);  // an empty range: only the solve
               t.flags = (j == 0 ? 1 : 0) | (half << 1);
               p.stiles.push_back(t);
+              // the earlier step whose columns it pushes into waits for it
+              if (t.cslot >= 0 && t.r1 > t.r0) ++p.sneed[t.cslot + t.r0 / SB];
             }
         }
-        push_launch(SOLVE_BWD, h, start);
+        if (!chain) push_launch(SOLVE_BWD, h, start, -1);
       }
+      if (chain) push_launch(SOLVE_BWD, h, lstart, p.nchains++);
     }
   }
   // full symmetric A in the original order, CSR, with the source entry of each value

@@ -100,7 +100,7 @@ struct SolveTile {
   int32_t r0;    // forward / below: first row handled; backward step: first column
   int32_t r1;    //   of the earlier chunk updated here (end of the range)
   int32_t flags; // bit0: writes the chunk's solution
-  int32_t pad;
+  int32_t cslot; // in a chained launch: the first step counter of the supernode, else -1
 };
 static_assert(sizeof(SolveTile) == 48, "SolveTile layout");
 
@@ -108,11 +108,19 @@ constexpr int32_t SOLVE_FWD = 0;    // forward step: chunk solve + rows below
 constexpr int32_t SOLVE_BELOW = 1;  // backward: columns against the ancestor rows
 constexpr int32_t SOLVE_BWD = 2;    // backward step: chunk solve + earlier chunks
 
+// chain >= 0: every step of the level in one launch whose workgroups take
+// their tiles in order by ticket (ticket counter `chain`); a tile with
+// cslot >= 0 first waits until the step counter cslot + (its step) has
+// received sneed[...] signals, one from each earlier tile of the launch that
+// writes into the columns of that step, and signals the counters of the
+// steps it writes into itself
 struct SolveLaunch {
   int32_t kind;
   int32_t level;
   int64_t start;
   int64_t count;
+  int32_t chain;
+  int32_t pad;
 };
 
 // launch kinds, in execution order inside one (level, step)
@@ -185,6 +193,8 @@ struct Plan {
   std::vector<DiagTile> ptiles;       // diagonal blocks of the two-chunk solve steps (nb > 64)
   std::vector<SolveTile> stiles;      // solve work items, launch by launch
   std::vector<SolveLaunch> slaunches; // forward levels upwards, then backward downwards
+  std::vector<int32_t> sneed;         // signals each step counter of a chained launch waits for
+  int32_t nchains = 0;                // chained launches (ticket counters)
   std::vector<Launch> launches;
   int32_t nlevels = 0;
   std::vector<int32_t> level;       // height of every supernode

@@ -215,7 +215,28 @@ def replay_solve(s, Lb, B):
             xa = VA.T @ (rhs[:64] - LBA.T @ xb)
         return np.concatenate([xa, xb])
 
-    for kind, lev, st, cnt in s.array("solve_launches").reshape(-1, 4):
+    need = s.array("solve_need")
+    for kind, lev, st, cnt, chain in s.array("solve_launches").reshape(-1, 5):
+        # a chained launch runs its tiles concurrently, each after the
+        # earlier tiles of the launch that write into the columns it reads
+        # have signalled its step counter: count those writers from the
+        # write sets themselves and compare with the plan's signal counts
+        writers = {}  # global column -> earlier tiles of the launch writing it
+        for ti, (off, ld, f, w, g0, c0, nb, r0, r1, flags, cslot) in enumerate(T[st:st + cnt]):
+            if chain >= 0 and kind != 1:
+                reads = set()
+                for col in range(f + c0, f + c0 + nb):
+                    reads |= writers.get(col, set())
+                if cslot >= 0:
+                    assert len(reads) == need[cslot + c0 // 128], (kind, lev, ti)
+                else:
+                    assert not reads, "a tile without a counter reads what the launch writes"
+                if kind == 0:
+                    written = [gl[g0 + q] for q in range(r0, r1)]
+                else:
+                    written = list(range(f + r0, f + r1))
+                for col in written:
+                    writers.setdefault(col, set()).add(ti)
         for off, ld, f, w, g0, c0, nb, r0, r1, flags, _ in T[st:st + cnt]:
             assert 1 <= nb <= 128
             # kernels of the two-chunk steps split the work by chunk (flags bit 1)

@@ -470,6 +470,7 @@ def bench_batch(args):
     stream = torch.cuda.current_stream()
     # level schedule chosen by timing the candidates on the device
     schedule, schedule_ms = b.autotune(vals, reps=2)
+    narrow_min = b.tuning()[1]
     for _ in range(args.warmup):
         assert np.all(b.factor(vals) == 0)
     ms = []
@@ -501,9 +502,10 @@ def bench_batch(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batch{args.batch_count}: {args.batch_count} 2D 9-point "
                                   "Laplacians, side ~ U{16..96}, weights U[0.5,1.5], shift 1e-3, "
-                                  "merged level schedule (autotuned), HIP graph replay",
+                                  "merged level schedule and narrow-item threshold (autotuned), "
+                                  "HIP graph replay",
                       "count": args.batch_count, "sum_n": int(sum(A.n for A in mats)),
-                      "schedule": schedule},
+                      "schedule": schedule, "narrow_min": narrow_min},
            "schedule_ms": {k: round(v, 3) for k, v in schedule_ms.items()},
            "factor_ms": round(t_fac * 1e3, 3), "flops_exact": F,
            "pct_fp64_peak": round(F / t_fac / 1e12 / PEAK_FP64_TFLOPS * 100, 3),

@@ -309,11 +309,23 @@ void rlb_batch_free(rlb_batch b);
 #define RLB_BATCH_SCHED_CENTERED 2
 rlb_status rlb_batch_set_schedule(rlb_batch b, int32_t schedule);
 
-/* Autotune the level schedule: factor the batch (same arguments as
- * rlb_batch_factor) once untimed and `reps` times timed with HIP events under
- * each schedule, keep the fastest. *chosen (may be NULL) receives it and ms
- * (may be NULL, 3 entries) the mean milliseconds of each. The workspace holds
- * a valid factorization afterwards. Errors: as rlb_batch_factor. */
+/* A merged launch of the batch with at least min_items narrow work items
+ * (update tiles and panel members of at most 16 columns) runs them one per
+ * wavefront, four per workgroup, instead of one per 256-thread workgroup;
+ * min_items <= 0: never. Default 1024. The factor storage does not depend on
+ * it. Errors: RLB_ERR_ARG, RLB_ERR_HIP. */
+rlb_status rlb_batch_set_narrow_min(rlb_batch b, int64_t min_items);
+
+/* The batch's current level schedule and narrow-item threshold (0: never). */
+rlb_status rlb_batch_get_tuning(rlb_batch b, int32_t* schedule, int64_t* narrow_min);
+
+/* Autotune the level schedule and the narrow-item threshold (256, 1024,
+ * 4096 or never): factor the batch (same arguments as rlb_batch_factor) once
+ * untimed and `reps` times timed with HIP events under each pair, keep the
+ * fastest pair. *chosen (may be NULL) receives its schedule and ms (may be
+ * NULL, 3 entries) the best mean milliseconds of each schedule; the chosen
+ * threshold is read back with rlb_batch_get_tuning. The workspace holds a
+ * valid factorization afterwards. Errors: as rlb_batch_factor. */
 rlb_status rlb_batch_autotune(rlb_batch b, const double* const* values, void* workspace,
                               size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen,
                               double* ms);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <vector>
@@ -316,6 +317,10 @@ struct rlb_batch_s {
   std::vector<DevPlan> per;  // solve data of every matrix
   std::vector<int64_t> segbase;  // first contribution of every matrix
   int32_t schedule = -1;         // RLB_BATCH_SCHED_*
+  // a merged launch with at least this many narrow work items (update tiles
+  // of <= 16 columns, panel members of <= 16 columns) runs them one per
+  // wavefront
+  int64_t narrow_min = WAVE_SPLIT_MIN;
   SolveScratch sc;
   double* L = nullptr;
   bool factored = false;         // a factorization was enqueued into L
@@ -1208,7 +1213,7 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
   for (const Launch& l : b->launches) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
-                    l.variant, st, l.nwave);
+                    l.variant, st, l.nwave, nullptr, b->narrow_min);
     else {
       // the batch factors with the FP64 panel kernel; its fused update tiles
       // run inside it in the FP64 form and as a short launch of their own in
@@ -1216,7 +1221,8 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
       const bool inside = b->precision == RLB_PREC_FP64;
       launch_panel(b->d_panels + l.start, l.count, L, b->status, b->counters, 0, l.variant,
                    l.pre != 0, nullptr, nullptr, 0.0, nullptr, nullptr,
-                   b->d_updates + l.ustart, b->d_segs, inside ? l.ucount : 0, st);
+                   b->d_updates + l.ustart, b->d_segs, inside ? l.ucount : 0, st, nullptr,
+                   b->narrow_min);
       if (!inside && l.ucount)
         launch_update(b->d_updates + l.ustart, b->d_segs, l.ucount, L, b->precision, nullptr,
                       UPD_SHORT, st);
@@ -1324,6 +1330,27 @@ rlb_status rlb_batch_set_schedule(rlb_batch b, int32_t schedule) {
   return batch_schedule(b, schedule);
 }
 
+rlb_status rlb_batch_set_narrow_min(rlb_batch b, int64_t min_items) {
+  if (!b) return fail(RLB_ERR_ARG, "null handle");
+  const int64_t v = min_items > 0 ? min_items : std::numeric_limits<int64_t>::max();
+  if (v == b->narrow_min) return RLB_OK;
+  HIP_OK(hipDeviceSynchronize());
+  b->narrow_min = v;
+  if (b->gexec) {  // the launch sequence changed: record the graph again
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_batch_get_tuning(rlb_batch b, int32_t* schedule, int64_t* narrow_min) {
+  if (!b) return fail(RLB_ERR_ARG, "null handle");
+  if (schedule) *schedule = b->schedule;
+  if (narrow_min)
+    *narrow_min = b->narrow_min == std::numeric_limits<int64_t>::max() ? 0 : b->narrow_min;
+  return RLB_OK;
+}
+
 rlb_status rlb_batch_autotune(rlb_batch b, const double* const* values, void* workspace,
                               size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen,
                               double* ms) {
@@ -1332,34 +1359,47 @@ rlb_status rlb_batch_autotune(rlb_batch b, const double* const* values, void* wo
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
+  // the level schedule, and for each the narrow-item threshold of the
+  // one-per-wavefront kernels (0: never)
+  static const int64_t kNarrow[] = {256, 1024, 4096, 0};
   double best = 0;
   int32_t best_s = RLB_BATCH_SCHED_LEAVES;
+  int64_t best_n = WAVE_SPLIT_MIN;
+  bool have = false;
   rlb_status r = RLB_OK;
   for (int32_t sch = RLB_BATCH_SCHED_LEAVES; sch <= RLB_BATCH_SCHED_CENTERED && !r; ++sch) {
     if ((r = rlb_batch_set_schedule(b, sch))) break;
-    // one untimed factorization (graph capture when enabled), then reps timed
-    if ((r = rlb_batch_factor(b, values, workspace, ws_bytes, stream))) break;
-    float total = 0;
-    for (int32_t k = 0; k < reps && !r; ++k) {
-      (void)hipEventRecord(e0, st);
-      r = rlb_batch_factor(b, values, workspace, ws_bytes, stream);
-      (void)hipEventRecord(e1, st);
-      if (hipEventSynchronize(e1) != hipSuccess) r = fail(RLB_ERR_HIP, "event");
-      float t = 0;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      total += t;
+    double best_here = 0;
+    for (int q = 0; q < 4 && !r; ++q) {
+      if ((r = rlb_batch_set_narrow_min(b, kNarrow[q]))) break;
+      // one untimed factorization (graph capture when enabled), then reps timed
+      if ((r = rlb_batch_factor(b, values, workspace, ws_bytes, stream))) break;
+      float total = 0;
+      for (int32_t k = 0; k < reps && !r; ++k) {
+        (void)hipEventRecord(e0, st);
+        r = rlb_batch_factor(b, values, workspace, ws_bytes, stream);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) r = fail(RLB_ERR_HIP, "event");
+        float t = 0;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        total += t;
+      }
+      const double avg = total / reps;
+      if (q == 0 || avg < best_here) best_here = avg;
+      if (!have || avg < best) {
+        best = avg;
+        best_s = sch;
+        best_n = kNarrow[q];
+        have = true;
+      }
     }
-    const double avg = total / reps;
-    if (ms) ms[sch] = avg;
-    if (sch == RLB_BATCH_SCHED_LEAVES || avg < best) {
-      best = avg;
-      best_s = sch;
-    }
+    if (ms) ms[sch] = best_here;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (r) return r;
   if (chosen) *chosen = best_s;
+  if ((r = rlb_batch_set_narrow_min(b, best_n))) return r;
   return rlb_batch_set_schedule(b, best_s);
 }
 

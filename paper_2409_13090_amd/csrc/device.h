@@ -49,12 +49,14 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   int precision, int nbb, bool pre, const double* thr,
                   const unsigned long long* amax, double ufix, unsigned long long* smax,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
-                  int64_t ucount, hipStream_t st, float* Ls = nullptr);
+                  int64_t ucount, hipStream_t st, float* Ls = nullptr,
+                  int64_t wave_min = WAVE_SPLIT_MIN);
 // variant: UPD_TILE, UPD_SHORT or UPD_BIG (128x128 tiles; FP64 and FP32 forms)
 // Ls: the FP32 copy of the finished factor entries (operands of the FP32 form)
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, int variant, hipStream_t st,
-                   int64_t nwave = 0, const float* Ls = nullptr);
+                   int64_t nwave = 0, const float* Ls = nullptr,
+                   int64_t wave_min = WAVE_SPLIT_MIN);
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
 // RL: update-matrix columns added into their ancestors (atomic adds)

@@ -1557,19 +1557,21 @@ template __global__ void k_update_big<float>(const UpdTile*, const UpdSeg*, doub
 // 16-bit operand form of the update. Every contribution's X and Y are scaled
 // by the power of two s = 2^e of its source panel (e chosen so that the
 // panel's largest |entry| times s lies in [2^13, 2^14)), rounded to FP16 or
-// BF16 (round to nearest even, through FP32) and multiplied on MFMA 16x16x16
-// with FP32 accumulation; a contribution's sum is scaled back by 2^-2e into an
-// FP64 accumulator before the next contribution starts. Staging as in
-// k_update, but each thread stages 4 consecutive k of one row, stored
-// row-major so that a lane's 4-element MFMA operand is one 8-byte LDS read.
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+// BF16 (round to nearest even, through FP32) and multiplied on the gfx950
+// MFMA 16x16x32 with FP32 accumulation; a contribution's sum is scaled back by
+// 2^-2e into an FP64 accumulator before the next contribution starts. Staging
+// as in k_update with K chunks of 32, each thread staging 8 consecutive k of
+// one row, stored row-major so that a lane's 8-element MFMA operand (row
+// l % 16, k 8 (l / 16) .. +7) is one 16-byte LDS read; the row pitch of 40
+// elements (5 x 16 bytes) keeps the 16 rows of a read in distinct banks.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 template <int P>
 struct Half;
 template <>
 struct Half<3> {  // FP16
-  typedef v4h vec;
+  typedef v8h vec;
   static __device__ __forceinline__ unsigned short cvt(double x) {
     const _Float16 h = (_Float16)(float)x;
     unsigned short b;
@@ -1577,12 +1579,12 @@ struct Half<3> {  // FP16
     return b;
   }
   static __device__ __forceinline__ v4f op(vec a, vec b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
 };
 template <>
 struct Half<2> {  // BF16
-  typedef v4s vec;
+  typedef v8bf vec;
   static __device__ __forceinline__ unsigned short cvt(double x) {
     const __bf16 h = (__bf16)(float)x;
     unsigned short b;
@@ -1590,7 +1592,7 @@ struct Half<2> {  // BF16
     return b;
   }
   static __device__ __forceinline__ v4f op(vec a, vec b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
 };
 
@@ -1601,7 +1603,8 @@ __device__ __forceinline__ int panel_scale_exp(unsigned long long mbits) {
   return min(max(13 - E, -960), 960);
 }
 
-constexpr int KP16 = 20;  // LDS row pitch of the 16-bit stage (elements)
+constexpr int KC16 = 32;  // K chunk of the 16-bit stage
+constexpr int KP16 = 40;  // LDS row pitch of the 16-bit stage (elements)
 
 template <int P>
 __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ tiles,
@@ -1616,7 +1619,7 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
   const int lr = tid & 63;  // row this thread stages
-  const int lk = tid >> 6;  // it stages k = 4*lk .. 4*lk+3 of the chunk
+  const int lk = tid >> 6;  // it stages k = 8*lk .. 8*lk+7 of the chunk
   double* __restrict__ C = L + t.c;
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
@@ -1656,34 +1659,39 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
   }
   __syncthreads();
   auto seg_at = [&](int i) { return uniform_seg(i < SEGS_LDS ? sg[i] : segs[t.seg0 + i]); };
-  double xr[4], yr[4];
+  double xr[8], yr[8];
   bool xin = false, yin = false;
   int kvalid = 0;
   double fscale = 1.0;  // scale of the fetched chunk's contribution
   auto fetch = [&](const UpdSeg& g, int k0) {
     xin = lr >= g.ra && lr < g.rb;
     yin = lr >= g.ca && lr < g.cb;
-    kvalid = g.k - k0 - 4 * lk;
+    kvalid = g.k - k0 - 8 * lk;
     fscale = ldexp(1.0, panel_scale_exp(smax[g.sslot]));
     const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
     const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t kk = min(k0 + 4 * lk + q, g.k - 1);
+    for (int q = 0; q < 8; ++q) {
+      const int64_t kk = min(k0 + 8 * lk + q, g.k - 1);
       xr[q] = L[xo + kk * g.lds];
       yr[q] = L[yo + kk * g.lds];
     }
   };
   auto stash = [&](int buf) {
-    unsigned long long px = 0, py = 0;
+    uint4 px = {0, 0, 0, 0}, py = {0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const bool kin = q < kvalid;
-      px |= (unsigned long long)Half<P>::cvt((kin && xin) ? xr[q] * fscale : 0.0) << (16 * q);
-      py |= (unsigned long long)Half<P>::cvt((kin && yin) ? yr[q] * fscale : 0.0) << (16 * q);
+      const unsigned hx = Half<P>::cvt((kin && xin) ? xr[q] * fscale : 0.0);
+      const unsigned hy = Half<P>::cvt((kin && yin) ? yr[q] * fscale : 0.0);
+      const int sh = 16 * (q & 1);
+      if (q < 2) { px.x |= hx << sh; py.x |= hy << sh; }
+      else if (q < 4) { px.y |= hx << sh; py.y |= hy << sh; }
+      else if (q < 6) { px.z |= hx << sh; py.z |= hy << sh; }
+      else { px.w |= hx << sh; py.w |= hy << sh; }
     }
-    *reinterpret_cast<unsigned long long*>(&sX[buf][lr][4 * lk]) = px;
-    *reinterpret_cast<unsigned long long*>(&sY[buf][lr][4 * lk]) = py;
+    *reinterpret_cast<uint4*>(&sX[buf][lr][8 * lk]) = px;
+    *reinterpret_cast<uint4*>(&sY[buf][lr][8 * lk]) = py;
   };
   int e = 0, k0 = 0;
   UpdSeg g = seg_at(0);
@@ -1692,7 +1700,7 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
   __syncthreads();
   int buf = 0;
   for (;;) {
-    int ne = e, nk0 = k0 + 16;
+    int ne = e, nk0 = k0 + KC16;
     if (nk0 >= g.k) {
       ne = e + 1;
       nk0 = 0;
@@ -1705,10 +1713,10 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const vec a = *reinterpret_cast<const vec*>(&sY[buf][wc + 16 * bj + (lane & 15)][4 * (lane >> 4)]);
+      const vec a = *reinterpret_cast<const vec*>(&sY[buf][wc + 16 * bj + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const vec b = *reinterpret_cast<const vec*>(&sX[buf][wr + 16 * bi + (lane & 15)][4 * (lane >> 4)]);
+        const vec b = *reinterpret_cast<const vec*>(&sX[buf][wr + 16 * bi + (lane & 15)][8 * (lane >> 4)]);
         acc[bj][bi] = Half<P>::op(a, b, acc[bj][bi]);
       }
     }
@@ -2372,10 +2380,10 @@ void launch_panel(const PanelTile* tiles, int64_t count, double* L, int* status,
                   int precision, int nbb, bool pre, const double* thr,
                   const unsigned long long* amax, double ufix, unsigned long long* smax,
                   unsigned int* nfixed, const UpdTile* utiles, const UpdSeg* usegs,
-                  int64_t ucount, hipStream_t st, float* Ls) {
+                  int64_t ucount, hipStream_t st, float* Ls, int64_t wave_min) {
   if (count <= 0) return;
   if (precision == 2 || nbb < 4) ucount = 0;  // (the plan fuses into 64-column launches only)
-  if (precision == 0 && nbb <= 1 && !pre && count >= WAVE_SPLIT_MIN) {
+  if (precision == 0 && nbb <= 1 && !pre && count >= wave_min) {
     // many small column blocks (as in a batch's merged launches): one
     // wavefront per group member
     hipLaunchKernelGGL(k_panel_w, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, st, tiles, L,
@@ -2411,7 +2419,7 @@ void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* 
 }
 void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, double* L,
                    int precision, const unsigned long long* smax, int variant, hipStream_t st,
-                   int64_t nwave, const float* Ls) {
+                   int64_t nwave, const float* Ls, int64_t wave_min) {
   if (count <= 0) return;
   if (variant == UPD_BIG) {
     // 128x128 target tiles: FP64 or FP32 operands (the 16-bit forms run the
@@ -2425,7 +2433,7 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     return;
   }
   const bool shortk = variant == UPD_SHORT;
-  if (precision == 0 && nwave >= WAVE_SPLIT_MIN) {
+  if (precision == 0 && nwave >= wave_min) {
     // the last nwave tiles are narrow: one wavefront each (a launch of its
     // own pays off for many of them, as in the merged launches of a batch)
     const int64_t nw = std::min(nwave, count);

@@ -75,7 +75,7 @@ EXPORTED = [
     "rlb_batch_free", "rlb_set_graph_mode", "rlb_batch_set_graph_mode", "rlb_set_profiling",
     "rlb_last_profile", "rlb_status_string", "rlb_last_error", "rlb_factor_pivots_patched",
     "rlb_batch_set_schedule", "rlb_batch_autotune", "rlb_solve_noalloc",
-    "rlb_last_profile_launches",
+    "rlb_last_profile_launches", "rlb_batch_set_narrow_min", "rlb_batch_get_tuning",
 ]
 
 _lib = None
@@ -117,6 +117,8 @@ def lib():
         "rlb_last_profile_launches": [_vp, _vp, ctypes.POINTER(i64)],
         "rlb_factor_pivots_patched": [_vp, ctypes.POINTER(i64)],
         "rlb_batch_set_schedule": [_vp, i32],
+        "rlb_batch_set_narrow_min": [_vp, ctypes.c_int64],
+        "rlb_batch_get_tuning": [_vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)],
         "rlb_batch_autotune": [_vp, _vp, _vp, ctypes.c_size_t, _vp, i32, ctypes.POINTER(i32), _vp],
     }
     for name, args in sig.items():
@@ -380,9 +382,21 @@ class Batch:
     def set_schedule(self, name):
         _check(lib().rlb_batch_set_schedule(self.h, self.SCHEDULES.index(name)))
 
+    def set_narrow_min(self, min_items):
+        """Narrow work items per merged launch from which they run one per
+        wavefront (0: never)."""
+        _check(lib().rlb_batch_set_narrow_min(self.h, int(min_items)))
+
+    def tuning(self):
+        """(schedule name, narrow-item threshold; 0 = never)."""
+        sch, nm = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().rlb_batch_get_tuning(self.h, ctypes.byref(sch), ctypes.byref(nm)))
+        return self.SCHEDULES[sch.value], nm.value
+
     def autotune(self, values_list, workspace=None, stream=None, reps=2):
-        """Time the level schedules on the device and keep the fastest;
-        returns (chosen name, {name: ms})."""
+        """Time the level schedules, each with the narrow-item thresholds
+        256, 1024, 4096 and never, on the device and keep the fastest pair;
+        returns (chosen schedule name, {name: best ms of that schedule})."""
         import torch
         if workspace is None:
             if self.workspace is None:

@@ -263,6 +263,36 @@ def test_batch_schedules_agree_and_autotune_picks_one():
     chosen, ms = b.autotune(vals, reps=1)
     assert chosen in rlb.Batch.SCHEDULES and all(v > 0 for v in ms.values())
     assert np.all(b.status() == 0)
+    sch, nmin = b.tuning()
+    assert sch == chosen and nmin in (256, 1024, 4096, 0)
+
+
+def test_batch_narrow_threshold_kernels_agree():
+    """The one-per-wavefront kernels for narrow work items (forced with a
+    threshold of 1) and the 256-thread kernels only (threshold 0: never) give
+    the same factors up to rounding, both solving to <= 1e-14."""
+    torch = _torch()
+    mats = [W.batch_member(i) for i in range(12)]
+    syms = [rlb.Symbolic.from_matrix(A) for A in mats]
+    b = rlb.Batch(syms)
+    vals = [torch.from_numpy(A.values).cuda() for A in mats]
+    xs = {}
+    for nmin in (1, 0):
+        b.set_narrow_min(nmin)
+        assert b.tuning()[1] == nmin
+        assert np.all(b.factor(vals) == 0)
+        out = []
+        for i, A in enumerate(mats):
+            B = torch.from_numpy(A.rhs[:, 0].copy()).cuda()
+            X = B.clone()
+            b.solve(i, X)
+            num = rlb.Numeric(syms[i])
+            num.values = vals[i]
+            assert num.backward_error(B, X)[0] <= 1e-14, (nmin, i)
+            out.append(X.cpu().numpy())
+        xs[nmin] = out
+    for a, c in zip(xs[1], xs[0]):
+        assert np.linalg.norm(a - c) <= 1e-9 * np.linalg.norm(a)
 
 
 def test_fp32_updates_with_refinement_reach_1e14():

@@ -1085,41 +1085,79 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict
   }
 }
 
+
 // ---------------------------------------------------------------------------
 // Update of one <=64x64 target tile: C -= sum over its contributions of
 // X * Y^T. 256 threads = 4 wavefronts in a 2x2 arrangement, each owning a
 // 32x32 quarter = 2x2 MFMA 16x16 blocks; K is staged through LDS in chunks of
-// 16 (column-major, as in factor storage), the next chunk's loads in flight
-// while the current one is multiplied. A tile with one owner is read once at
-// the start and written once at the end; the parts of a split tile are added
-// with atomics.
-//
+// 16 in FP64 and 32 in FP32 (the same LDS bytes), column-major as in factor
+// storage. The operand loads are issued two chunks ahead: two register sets
+// alternate (chunk c is fetched into set c % 2 while chunk c - 3 is
+// multiplied, and written to LDS while chunk c - 1 is), so a chunk's loads
+// have two chunk times to arrive, which the tiles of many short
+// contributions at the lower levels need; the register budget is held to
+// four wavefronts per SIMD. A tile with one owner is read once at the start
+// and written once at the end, only where a contribution's rectangle meets
+// it; the parts of a split tile are added with atomics.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tiles,
-                                                const UpdSeg* __restrict__ segs,
-                                                double* __restrict__ L, const T* __restrict__ S) {
+__global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ tiles,
+                                                   const UpdSeg* __restrict__ segs,
+                                                   double* __restrict__ L, const T* __restrict__ S) {
   typedef typename Mfma<T>::acc_t acc_t;
-  // K chunk: 16 in FP64, 32 in FP32 (the same LDS bytes, half the barriers)
   constexpr int KC = 16 * (int)(sizeof(double) / sizeof(T));
+  constexpr int NQ = KC / 4;
   const UpdTile t = tiles[blockIdx.x];
-  __shared__ T sX[2][KC][64];  // [k][tile row]
-  __shared__ T sY[2][KC][64];  // [k][tile column]
+  __shared__ T sX[2][KC][64];
+  __shared__ T sY[2][KC][64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave & 1) * 32;   // rows of this wave's quarter
-  const int wc = (wave >> 1) * 32;  // columns of this wave's quarter
-  const int lr = tid & 63;  // tile row / column this thread stages
-  const int lk = tid >> 6;  // first k this thread stages (then +4, +8, ...)
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int lr = tid & 63, lk = tid >> 6;
   double* __restrict__ C = L + t.c;
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
   const bool atomic = t.flags & 2;
-  const bool assign = t.flags & 4;  // write -(sum) without reading the target
+  const bool assign = t.flags & 4;
+  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
 
-  // elements met by a contribution (an update matrix of RL is written whole)
+  // register sets: the loaded values and the masks of their chunk
+  T xr[2][NQ], yr[2][NQ];
+  bool xin[2] = {false, false}, yin[2] = {false, false};
+  int kvalid[2] = {0, 0};
+  // fetch cursor
+  int fe = 0, fk = 0;
+  UpdSeg gf = seg_at(0);
+  auto fetch = [&](int set) {
+    xin[set] = lr >= gf.ra && lr < gf.rb;
+    yin[set] = lr >= gf.ca && lr < gf.cb;
+    kvalid[set] = gf.k - fk - lk;
+    const int64_t xo = gf.x + min(max(lr - gf.ra, 0), gf.rb - gf.ra - 1);
+    const int64_t yo = gf.y + min(max(lr - gf.ca, 0), gf.cb - gf.ca - 1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t kk = min(fk + lk + 4 * q, gf.k - 1);
+      xr[set][q] = S[xo + kk * gf.lds];
+      yr[set][q] = S[yo + kk * gf.lds];
+    }
+    fk += KC;
+    if (fk >= gf.k) {
+      fk = 0;
+      if (++fe < t.nseg) gf = seg_at(fe);
+    }
+  };
+  auto stash = [&](int set, int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const bool kin = 4 * q < kvalid[set];
+      sX[buf][lk + 4 * q][lr] = (kin && xin[set]) ? xr[set][q] : T(0);
+      sY[buf][lk + 4 * q][lr] = (kin && yin[set]) ? yr[set][q] : T(0);
+    }
+  };
+  // chunks 0 and 1 in flight first, then the target values
+  fetch(0);
+  const bool two = fe < t.nseg;
+  if (two) fetch(1);
   const unsigned cover = assign ? 0xffffu : cover_bits<Mfma<T>>(t, segs, wr, wc, lane);
-  // the target values of a tile with a single owner, loaded up front (no
-  // other workgroup of the launch writes it); addresses clamped into the tile
   double cv[2][2][4] = {};
   if (!atomic && !assign) {
 #pragma unroll
@@ -1133,51 +1171,19 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
           if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
         }
   }
-
   acc_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  stash(0, 0);
+  if (fe < t.nseg) fetch(0);  // chunk 2
+  __syncthreads();
 
-  // chunks: (contribution e, k0) in order; rows outside a contribution's
-  // rectangle and k beyond its inner dimension are staged as zeros. The loads
-  // are unconditional (clamped addresses) and the zero mask is applied when
-  // the chunk is written to LDS, so the loads stay in flight during the
-  // multiplication of the previous chunk.
-  T xr[KC / 4], yr[KC / 4];
-  bool xin = false, yin = false;
-  int kvalid = 0;  // k offsets (relative to this thread's first k) still inside the contribution
-  auto fetch = [&](const UpdSeg& g, int k0) {
-    xin = lr >= g.ra && lr < g.rb;
-    yin = lr >= g.ca && lr < g.cb;
-    kvalid = g.k - k0 - lk;
-    const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
-    const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
-#pragma unroll
-    for (int q = 0; q < KC / 4; ++q) {
-      const int64_t kk = min(k0 + lk + 4 * q, g.k - 1);
-      xr[q] = S[xo + kk * g.lds];
-      yr[q] = S[yo + kk * g.lds];
-    }
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < KC / 4; ++q) {
-      const bool kin = 4 * q < kvalid;
-      sX[buf][lk + 4 * q][lr] = (kin && xin) ? xr[q] : T(0);
-      sY[buf][lk + 4 * q][lr] = (kin && yin) ? yr[q] : T(0);
-    }
-  };
-  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
+  // compute cursor
   int e = 0, k0 = 0;
   UpdSeg g = seg_at(0);
-  fetch(g, 0);
-  stash(0);
-  __syncthreads();
-  int buf = 0;
-  for (;;) {
-    // this wave's 16x16 blocks that meet the contribution's rectangle
+  auto multiply = [&](int buf) {
     bool use[2][2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
@@ -1186,21 +1192,9 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
         use[bj][bi] = wr + 16 * bi < g.rb && wr + 16 * bi + 16 > g.ra &&
                       wc + 16 * bj < g.cb && wc + 16 * bj + 16 > g.ca;
     const bool all4 = use[0][0] && use[0][1] && use[1][0] && use[1][1];
-    // next chunk
-    int ne = e, nk0 = k0 + KC;
-    if (nk0 >= g.k) {
-      ne = e + 1;
-      nk0 = 0;
-    }
-    const bool more = ne < t.nseg;
-    UpdSeg gn = g;
-    if (more) {
-      if (ne != e) gn = seg_at(ne);
-      fetch(gn, nk0);
-    }
     if (all4) {
 #pragma unroll
-      for (int kq = 0; kq < KC / 4; ++kq) {
+      for (int kq = 0; kq < NQ; ++kq) {
         const int kk = kq * 4 + (lane >> 4);
         const T a0 = sY[buf][kk][wc + (lane & 15)];
         const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
@@ -1213,7 +1207,7 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
       }
     } else if (use[0][0] || use[0][1] || use[1][0] || use[1][1]) {
 #pragma unroll
-      for (int kq = 0; kq < KC / 4; ++kq) {
+      for (int kq = 0; kq < NQ; ++kq) {
         const int kk = kq * 4 + (lane >> 4);
         const T a0 = sY[buf][kk][wc + (lane & 15)];
         const T a1 = sY[buf][kk][wc + 16 + (lane & 15)];
@@ -1225,16 +1219,25 @@ __global__ __launch_bounds__(256) void k_update(const UpdTile* __restrict__ tile
         if (use[1][1]) acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
       }
     }
-    if (!more) break;
-    stash(buf ^ 1);
+    k0 += KC;
+    if (k0 >= g.k) {
+      k0 = 0;
+      if (++e < t.nseg) g = seg_at(e);
+    }
+  };
+  // chunk i (even) is in LDS buffer 0, its successor in register set 1
+  for (;;) {
+    multiply(0);
+    if (e >= t.nseg) break;
+    stash(1, 1);  // chunk i + 1
+    if (fe < t.nseg) fetch(1);  // chunk i + 3
     __syncthreads();
-    buf ^= 1;
-    e = ne;
-    k0 = nk0;
-    g = gn;
+    multiply(1);
+    if (e >= t.nseg) break;
+    stash(0, 0);  // chunk i + 2
+    if (fe < t.nseg) fetch(0);  // chunk i + 4
+    __syncthreads();
   }
-  // epilogue: acc[bj][bi][v] is the update of target row wr+16*bi+(lane&15),
-  // target column wc+16*bj+drow(lane,v)
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj)
 #pragma unroll

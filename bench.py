@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--ablations", action="store_true",
                     help="only the FP64 factor under the analysis switches one at a time "
                          "(maximal blocks, reordering, merge cap, outer blocks, atomic "
-                         "splitting, RL); prints one JSON line")
+                         "splitting, RL, XCD tile order); prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the factorization runs on one GPU; --gpus {args.gpus} is not supported "
@@ -389,6 +389,7 @@ ABLATIONS = [
     ("atomic_split", {"deterministic": False}),
     ("big_tiles_128", {"big_tile_min": 256}),
     ("method_rl", {"method": "rl"}),
+    ("tile_order_xcd", {"tile_order": "xcd"}),
 ]
 
 

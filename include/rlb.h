@@ -95,7 +95,16 @@ typedef struct rlb_options {
                                factor in the workspace) and assembled into the ancestors
                                through relative indices, with atomic additions; FP64
                                only, not batched */
+  int32_t tile_order;       /* target tiles of an update launch of its own:
+                               RLB_TILE_ORDER_WEIGHT (0): heaviest first, dealt round-robin
+                               to the XCDs as dispatched; RLB_TILE_ORDER_XCD (1): in 8x8
+                               blocks of neighbouring tiles of each target supernode, and
+                               each XCD takes a contiguous eighth of that order, so the
+                               tiles running on one XCD (one L2) share their source rows */
 } rlb_options;
+
+#define RLB_TILE_ORDER_WEIGHT 0
+#define RLB_TILE_ORDER_XCD 1
 
 #define RLB_METHOD_RLB 0
 #define RLB_METHOD_RL 1

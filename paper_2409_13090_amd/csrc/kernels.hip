@@ -1102,11 +1102,19 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const DiagTile* __restrict
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ tiles,
                                                    const UpdSeg* __restrict__ segs,
-                                                   double* __restrict__ L, const T* __restrict__ S) {
+                                                   double* __restrict__ L, const T* __restrict__ S,
+                                                   int count, int by_xcd) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int KC = 16 * (int)(sizeof(double) / sizeof(T));
   constexpr int NQ = KC / 4;
-  const UpdTile t = tiles[blockIdx.x];
+  // workgroups are dealt to the 8 XCDs round-robin as dispatched: with
+  // by_xcd, the ones of XCD x take the x-th contiguous eighth of the list
+  int b = (int)blockIdx.x;
+  if (by_xcd) {
+    const int x = b & 7, q = count >> 3, r = count & 7;
+    b = x * q + min(x, r) + (b >> 3);
+  }
+  const UpdTile t = tiles[b];
   __shared__ T sX[2][KC][64];
   __shared__ T sY[2][KC][64];
   const int tid = threadIdx.x;
@@ -1257,8 +1265,10 @@ __global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ t
       }
 }
 
-template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*, const double*);
-template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*, const float*);
+template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*, const double*,
+                                          int, int);
+template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*, const float*,
+                                         int, int);
 
 // Update of narrow target tiles (at most 64 rows and 16 columns: the targets
 // in small supernodes), one wavefront per tile and four tiles per
@@ -2436,6 +2446,7 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     return;
   }
   const bool shortk = variant == UPD_SHORT;
+  const int xcd = variant == UPD_TILE_XCD ? 1 : 0;
   if (precision == 0 && nwave >= wave_min) {
     // the last nwave tiles are narrow: one wavefront each (a launch of its
     // own pays off for many of them, as in the merged launches of a batch)
@@ -2452,13 +2463,14 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     else
       hipLaunchKernelGGL(k_update_short<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
   } else if (precision == 1)
-    hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L, Ls);
+    hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L, Ls, (int)count, xcd);
   else if (precision == 2)
     hipLaunchKernelGGL(k_update16<2>, g, b, 0, st, tiles, segs, L, smax);
   else if (precision == 3)
     hipLaunchKernelGGL(k_update16<3>, g, b, 0, st, tiles, segs, L, smax);
   else
-    hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
+    hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
+                       (int)count, xcd);
 }
 void launch_assemble(const AsmCol* cols, int64_t count, const int32_t* rows, double* L,
                      hipStream_t st) {

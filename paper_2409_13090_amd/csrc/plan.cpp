@@ -50,6 +50,7 @@ constexpr int WG_CHUNKS = 16;  // K chunks one update workgroup takes before a t
 // target tiles (k_update_big) when there are at least options.big_tile_min
 // of them (256 by default: about one per compute unit).
 constexpr int64_t BIG = 128;
+constexpr int64_t XCD_ORDER_MIN = 1024;  // tiles of a launch ordered for the XCDs from this many
 // fusion of a step's trailing update into the next panel launch: compute
 // units of the device, and short update tiles one unit runs while the panel
 // workgroups factor (one resident workgroup per unit in a fused launch)
@@ -300,8 +301,26 @@ int build_plan(Symbolic& s, std::string& err) {
                        [](const std::pair<int64_t, size_t>& x, const std::pair<int64_t, size_t>& y) {
                          return x.first < y.first;
                        });
+      // a launch of its own in 8x8 blocks of neighbouring tiles (each target
+      // supernode's tiles by column-block and row-tile band), read by the
+      // kernel as a contiguous eighth per XCD
+      const bool by_xcd = fused_into < 0 && s.opt.tile_order == 1 && order.size() >= XCD_ORDER_MIN;
+      if (by_xcd) {
+        auto key = [&](size_t i) {
+          const UpdTile& t = u.tiles[i];
+          const int64_t P = std::upper_bound(p.off.begin(), p.off.end() - 1, t.c) - p.off.begin() - 1;
+          const int64_t rel = t.c - p.off[P];
+          const int64_t cb = rel / t.ldc / NB, rt = rel % t.ldc / NB;
+          return std::make_tuple(P, cb / 8, rt / 8, cb, rt);
+        };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](const std::pair<int64_t, size_t>& x,
+                             const std::pair<int64_t, size_t>& y) {
+                           return key(x.second) < key(y.second);
+                         });
+      }
       // a launch of its own with enough narrow tiles puts them last
-      if (fused_into < 0) {
+      if (fused_into < 0 && !by_xcd) {
         int64_t nn = 0;
         for (auto& o : order) nn += u.tiles[o.second].n <= NARROW_COLS;
         if (nn >= WAVE_SPLIT_MIN) {
@@ -328,8 +347,10 @@ int build_plan(Symbolic& s, std::string& err) {
       p.launches[fused_into].ucount = counts[0];
       p.launches[fused_into].ncount = counts[1];
     } else if (counts[0]) {
-      Launch lu{LAUNCH_UPDATE, u.level, u.step, shortk ? UPD_SHORT : UPD_TILE, start, counts[0], 0,
-                (int32_t)nwave, 0, 0, 0};
+      const int32_t var = shortk ? UPD_SHORT
+                          : (s.opt.tile_order == 1 && counts[0] >= XCD_ORDER_MIN) ? UPD_TILE_XCD
+                                                                                  : UPD_TILE;
+      Launch lu{LAUNCH_UPDATE, u.level, u.step, var, start, counts[0], 0, (int32_t)nwave, 0, 0, 0};
       p.launches.push_back(lu);
     }
   };

@@ -26,6 +26,8 @@ struct AnalyzeOptions {
                            // there are at least this many (<= 0: never)
   int method = 0;          // 0: RLB (Algorithm 5); 1: RL (Algorithm 4), the updates of a
                            // supernode into its ancestors through an update matrix
+  int tile_order = 0;      // 0: heaviest tiles first; 1: 8x8 blocks of neighbouring
+                           // tiles, a contiguous eighth of the order per XCD
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its
@@ -153,6 +155,8 @@ constexpr int64_t WAVE_SPLIT_MIN = 1024;
 constexpr int32_t UPD_TILE = 0;
 constexpr int32_t UPD_SHORT = 1;
 constexpr int32_t UPD_BIG = 2;
+constexpr int32_t UPD_TILE_XCD = 3;  // UPD_TILE, workgroup b takes the tile at position
+                                     // (b % 8) * (count / 8) + min(b % 8, count % 8) + b / 8
 
 struct Launch {
   int32_t kind;   // LAUNCH_*

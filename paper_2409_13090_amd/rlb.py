@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("maximal_blocks", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("outer_block", ctypes.c_int32), ("big_tile_min", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -169,7 +169,8 @@ class Symbolic:
 
     def __init__(self, n, colptr, rowidx, ordering="grid", grid=(0, 0, 0, 1), merge_cap=0.125,
                  reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0,
-                 deterministic=True, outer_block=0, big_tile_min=0, method="rlb"):
+                 deterministic=True, outer_block=0, big_tile_min=0, method="rlb",
+                 tile_order="weight"):
         L = lib()
         self._cp = np.ascontiguousarray(colptr, np.int64)
         self._ri = np.ascontiguousarray(rowidx, np.int64)
@@ -187,6 +188,7 @@ class Symbolic:
         o.outer_block = int(outer_block)
         o.big_tile_min = int(big_tile_min)
         o.method = {"rlb": 0, "rl": 1}[method]
+        o.tile_order = {"weight": 0, "xcd": 1}[tile_order]
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)
             o.user_perm = self._up.ctypes.data_as(_c_i64p)

@@ -414,3 +414,18 @@ def test_irregular_graph_ordering_matches_oracle(n, method):
     err = compare_factor(num.export(), f, A.n)
     print(f"[case] irregular n={n} {method} rel_err={err:.3e}", flush=True)
     solve_check(num, A)
+
+
+def test_xcd_tile_order_matches_oracle():
+    """Update launches in 8x8 blocks of neighbouring tiles, a contiguous eighth
+    per XCD (the kernel's workgroup-to-tile remapping): the same factor."""
+    A = W.small_grid("7pt", (30, 30, 30), seed=22, shift=1e-4)
+    s = rlb.Symbolic.from_matrix(A, tile_order="xcd")
+    L = s.array("launches").reshape(-1, 12)
+    assert (L[:, 5] == 3).sum() >= 1
+    o, f = oracle_factor(A)
+    s2, num, vals, info = gpu_factor(A, tile_order="xcd")
+    assert info == 0
+    err = compare_factor(num.export(), f, A.n)
+    print(f"[case] lap3d7_30 xcd order rel_err={err:.3e}", flush=True)
+    solve_check(num, A)

@@ -450,6 +450,35 @@ def bench_ablations(args):
     print(json.dumps(out), flush=True)
 
 
+def _batch_member_alg1(job):
+    """Algorithm 1 on one batch member (oracle): returns (seconds of
+    Algorithm 1 alone, info)."""
+    n, colptr, rowidx, values, perm = job
+    from oracle import onum, osym
+
+    a_cp, a_ri, a_x = osym.permute_lower(n, colptr, rowidx, values, perm)
+    structs, _ = osym.column_structures(n, a_cp, a_ri)
+    l_cp, l_ri = onum.pattern_csc(structs)
+    t0 = time.perf_counter()
+    _, info = onum.alg1(n, a_cp, a_ri, a_x, l_cp, l_ri)
+    return time.perf_counter() - t0, info
+
+
+def cpu_baseline_batch(mats, syms, flops):
+    """The CPU oracle (Algorithm 1, one thread) on every member of the batch,
+    one after the other in this process; only Algorithm 1's own time is summed
+    (as for one matrix: the oracle's symbolic structures are not timed)."""
+    res = [_batch_member_alg1((A.n, A.colptr, A.rowidx, A.values, s.array("perm")))
+           for A, s in zip(mats, syms)]
+    dt = sum(r[0] for r in res)
+    bad = sum(1 for r in res if r[1] != 0)
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"Algorithm 1 on all {len(mats)} matrices ({flops:.3e} flops, {dt:.2f} s "
+                      f"summed over the matrices; {bad} failed)",
+            "seconds": dt, "cpu_model": host_cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
 def bench_batch(args):
     """The batched form: independent 9-point grid Laplacians (side ~ U{16..96})
     factored with one merged level schedule, replayed as a HIP graph."""
@@ -511,6 +540,8 @@ def bench_batch(args):
            "factor_ms": round(t_fac * 1e3, 3), "flops_exact": F,
            "pct_fp64_peak": round(F / t_fac / 1e12 / PEAK_FP64_TFLOPS * 100, 3),
            "backward_error_max": float(f"{worst:.3e}"), "analyze_s": round(t_analyze, 2)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(mats, syms, F)
     print(json.dumps(out), flush=True)
 
 

@@ -1270,6 +1270,234 @@ template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*, const float*,
                                          int, int);
 
+// k_update for launches whose tiles hold many contributions with small
+// rectangles (the lower levels; irregular input): the K chunk takes the shape
+// of the contribution, 64 rows x KC k when its rectangle spans more than one
+// 32-row quarter, 32 x 2KC or 16 x 4KC when it lies inside an aligned 32- or
+// 16-row window (rows and columns alike), so a contribution of a few rows and
+// a long k takes a quarter of the chunk rounds (memory round trips) for the
+// same staging bytes; the k steps of a chunk stop at the contribution's k.
+// The planner picks it per launch when it saves enough rounds: on tiles of
+// full 64-row contributions the general indexing costs a few percent.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_update_win(const UpdTile* __restrict__ tiles,
+                                                   const UpdSeg* __restrict__ segs,
+                                                   double* __restrict__ L, const T* __restrict__ S,
+                                                   int count, int by_xcd) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int KC = 16 * (int)(sizeof(double) / sizeof(T));
+  constexpr int NQ = KC / 4;
+  // workgroups are dealt to the 8 XCDs round-robin as dispatched: with
+  // by_xcd, the ones of XCD x take the x-th contiguous eighth of the list
+  int b = (int)blockIdx.x;
+  if (by_xcd) {
+    const int x = b & 7, q = count >> 3, r = count & 7;
+    b = x * q + min(x, r) + (b >> 3);
+  }
+  const UpdTile t = tiles[b];
+  // a stage holds ELEMS operand values of X and of Y: 64 rows x KC k for a
+  // contribution whose rectangle spans more than one quarter, 32 x 2KC or
+  // 16 x 4KC for one inside an aligned 32- or 16-row window (rows and
+  // columns alike), laid out [k][row] with the window's row pitch
+  constexpr int ELEMS = 64 * KC;
+  __shared__ T sX[2][ELEMS];
+  __shared__ T sY[2][ELEMS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+  const bool assign = t.flags & 4;
+  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
+  // log2 of the window of a contribution: 4, 5 or 6
+  auto window_log = [](const UpdSeg& g) {
+    const bool r16 = (g.ra >> 4) == ((g.rb - 1) >> 4) && (g.ca >> 4) == ((g.cb - 1) >> 4);
+    const bool r32 = (g.ra >> 5) == ((g.rb - 1) >> 5) && (g.ca >> 5) == ((g.cb - 1) >> 5);
+    return r16 ? 4 : (r32 ? 5 : 6);
+  };
+
+  // register sets: the loaded values and the masks of their chunk
+  T xr[2][NQ], yr[2][NQ];
+  bool xin[2] = {false, false}, yin[2] = {false, false};
+  int kvalid[2] = {0, 0};
+  int wlog[2] = {6, 6};  // window of the set's chunk
+  // fetch cursor
+  int fe = 0, fk = 0;
+  UpdSeg gf = seg_at(0);
+  int fwl = window_log(gf);
+  auto fetch_w = [&](int set, int wl) {
+    const int win = 1 << wl;
+    const int r = tid & (win - 1), kb = tid >> wl, kstep = 256 >> wl;
+    const int xrow = (gf.ra & ~(win - 1)) + r, ycol = (gf.ca & ~(win - 1)) + r;
+    xin[set] = xrow >= gf.ra && xrow < gf.rb;
+    yin[set] = ycol >= gf.ca && ycol < gf.cb;
+    kvalid[set] = gf.k - fk - kb;
+    const int64_t xo = gf.x + min(max(xrow - gf.ra, 0), gf.rb - gf.ra - 1);
+    const int64_t yo = gf.y + min(max(ycol - gf.ca, 0), gf.cb - gf.ca - 1);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int64_t kk = min(fk + kb + kstep * q, gf.k - 1);
+      xr[set][q] = S[xo + kk * gf.lds];
+      yr[set][q] = S[yo + kk * gf.lds];
+    }
+  };
+  auto fetch = [&](int set) {
+    const int wl = fwl;
+    wlog[set] = wl;
+    fetch_w(set, wl);
+    fk += ELEMS >> wl;
+    if (fk >= gf.k) {
+      fk = 0;
+      if (++fe < t.nseg) {
+        gf = seg_at(fe);
+        fwl = window_log(gf);
+      }
+    }
+  };
+  auto stash_w = [&](int set, int buf, int wl) {
+    const int r = tid & ((1 << wl) - 1), kb = tid >> wl, kstep = 256 >> wl;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const bool kin = kstep * q < kvalid[set];
+      const int pos = ((kb + kstep * q) << wl) + r;
+      sX[buf][pos] = (kin && xin[set]) ? xr[set][q] : T(0);
+      sY[buf][pos] = (kin && yin[set]) ? yr[set][q] : T(0);
+    }
+  };
+  auto stash = [&](int set, int buf) {
+    if (wlog[set] == 6)
+      stash_w(set, buf, 6);
+    else
+      stash_w(set, buf, wlog[set]);
+  };
+  // chunks 0 and 1 in flight first, then the target values
+  fetch(0);
+  const bool two = fe < t.nseg;
+  if (two) fetch(1);
+  const unsigned cover = assign ? 0xffffu : cover_bits<Mfma<T>>(t, segs, wr, wc, lane);
+  double cv[2][2][4] = {};
+  if (!atomic && !assign) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + Mfma<T>::drow(lane, v), t.n - 1);
+          if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        }
+  }
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  stash(0, 0);
+  if (fe < t.nseg) fetch(0);  // chunk 2
+  __syncthreads();
+
+  // compute cursor
+  int e = 0, k0 = 0;
+  UpdSeg g = seg_at(0);
+  int gwl = window_log(g);
+  auto multiply = [&](int buf) {
+    bool use[2][2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        use[bj][bi] = wr + 16 * bi < g.rb && wr + 16 * bi + 16 > g.ra &&
+                      wc + 16 * bj < g.cb && wc + 16 * bj + 16 > g.ca;
+    // every block of the quarter, in the 64-row window (a rectangle that fills
+    // one quarter has a 32-row window and takes the general form)
+    const bool all4 = gwl == 6 && use[0][0] && use[0][1] && use[1][0] && use[1][1];
+    if (all4) {
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const T a0 = sY[buf][kk * 64 + wc + (lane & 15)];
+        const T a1 = sY[buf][kk * 64 + wc + 16 + (lane & 15)];
+        const T b0 = sX[buf][kk * 64 + wr + (lane & 15)];
+        const T b1 = sX[buf][kk * 64 + wr + 16 + (lane & 15)];
+        acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+      }
+    } else if (use[0][0] || use[0][1] || use[1][0] || use[1][1]) {
+      // the blocks this wavefront uses lie inside the window (windows are
+      // aligned to their size, blocks to 16); indices of the others are kept
+      // in range and their values unused
+      const int wl = gwl, win = 1 << wl;
+      const int wx0 = g.ra & ~(win - 1), wy0 = g.ca & ~(win - 1);
+      const int ya = (wc - wy0 + (lane & 15)) & (ELEMS - 1);
+      const int xa = (wr - wx0 + (lane & 15)) & (ELEMS - 1);
+      // 4-deep k steps of the chunk that the contribution's k reaches
+      const int nq = min(ELEMS >> (wl + 2), (g.k - k0 + 3) >> 2);
+      for (int kq0 = 0; kq0 < nq; kq0 += NQ) {
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+          if (kq0 + u >= nq) break;
+          const int kk = (kq0 + u) * 4 + (lane >> 4);
+          const int ko = kk << wl;
+          const T a0 = sY[buf][(ko + ya) & (ELEMS - 1)];
+          const T a1 = sY[buf][(ko + ya + 16) & (ELEMS - 1)];
+          const T b0 = sX[buf][(ko + xa) & (ELEMS - 1)];
+          const T b1 = sX[buf][(ko + xa + 16) & (ELEMS - 1)];
+          if (use[0][0]) acc[0][0] = Mfma<T>::op(a0, b0, acc[0][0]);
+          if (use[0][1]) acc[0][1] = Mfma<T>::op(a0, b1, acc[0][1]);
+          if (use[1][0]) acc[1][0] = Mfma<T>::op(a1, b0, acc[1][0]);
+          if (use[1][1]) acc[1][1] = Mfma<T>::op(a1, b1, acc[1][1]);
+        }
+      }
+    }
+    k0 += ELEMS >> gwl;
+    if (k0 >= g.k) {
+      k0 = 0;
+      if (++e < t.nseg) {
+        g = seg_at(e);
+        gwl = window_log(g);
+      }
+    }
+  };
+  // chunk i (even) is in LDS buffer 0, its successor in register set 1
+  for (;;) {
+    multiply(0);
+    if (e >= t.nseg) break;
+    stash(1, 1);  // chunk i + 1
+    if (fe < t.nseg) fetch(1);  // chunk i + 3
+    __syncthreads();
+    multiply(1);
+    if (e >= t.nseg) break;
+    stash(0, 0);  // chunk i + 2
+    if (fe < t.nseg) fetch(0);  // chunk i + 4
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<T>::drow(lane, v);
+        if (((cover >> (bj * 8 + bi * 4 + v)) & 1u) && row < t.m && col < t.n &&
+            (!diag || row >= col)) {
+          double* p = C + (int64_t)col * ldc + row;
+          if (atomic)
+            atomicAdd(p, -(double)acc[bj][bi][v]);
+          else
+            *p = cv[bj][bi][v] - (double)acc[bj][bi][v];
+        }
+      }
+}
+
+template __global__ void k_update_win<double>(const UpdTile*, const UpdSeg*, double*,
+                                              const double*, int, int);
+
 // Update of narrow target tiles (at most 64 rows and 16 columns: the targets
 // in small supernodes), one wavefront per tile and four tiles per
 // workgroup: C -= sum over the tile's contributions of X * Y^T, the MFMA
@@ -2446,6 +2674,7 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     return;
   }
   const bool shortk = variant == UPD_SHORT;
+  const bool win = variant == UPD_TILE_WIN;
   const int xcd = variant == UPD_TILE_XCD ? 1 : 0;
   if (precision == 0 && nwave >= wave_min) {
     // the last nwave tiles are narrow: one wavefront each (a launch of its
@@ -2463,11 +2692,16 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
     else
       hipLaunchKernelGGL(k_update_short<double>, g, b, 0, st, tiles, segs, L, (const double*)L);
   } else if (precision == 1)
+    // (the FP32 form stays with the dense kernel: its 32-deep chunks already
+    // halve the rounds, and the windows measured slower there)
     hipLaunchKernelGGL(k_update<float>, g, b, 0, st, tiles, segs, L, Ls, (int)count, xcd);
   else if (precision == 2)
     hipLaunchKernelGGL(k_update16<2>, g, b, 0, st, tiles, segs, L, smax);
   else if (precision == 3)
     hipLaunchKernelGGL(k_update16<3>, g, b, 0, st, tiles, segs, L, smax);
+  else if (win)
+    hipLaunchKernelGGL(k_update_win<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
+                       (int)count, 0);
   else
     hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
                        (int)count, xcd);

@@ -347,8 +347,24 @@ int build_plan(Symbolic& s, std::string& err) {
       p.launches[fused_into].ucount = counts[0];
       p.launches[fused_into].ncount = counts[1];
     } else if (counts[0]) {
+      // K chunks shaped to the contributions' rectangles when that saves at
+      // least 30 % of the launch's chunk rounds (64-row windows: KCH deep;
+      // 32- and 16-row windows: 2 and 4 times deeper)
+      int64_t rounds = 0, rounds_win = 0;
+      for (int64_t i = start; i < start + counts[0]; ++i) {
+        const UpdTile& t = p.updates[i];
+        for (int32_t e = 0; e < t.nseg; ++e) {
+          const UpdSeg& g = p.segs[t.seg0 + e];
+          const bool r16 = (g.ra >> 4) == ((g.rb - 1) >> 4) && (g.ca >> 4) == ((g.cb - 1) >> 4);
+          const bool r32 = (g.ra >> 5) == ((g.rb - 1) >> 5) && (g.ca >> 5) == ((g.cb - 1) >> 5);
+          const int64_t kc = KCH * (r16 ? 4 : (r32 ? 2 : 1));
+          rounds += (g.k + KCH - 1) / KCH;
+          rounds_win += (g.k + kc - 1) / kc;
+        }
+      }
       const int32_t var = shortk ? UPD_SHORT
                           : (s.opt.tile_order == 1 && counts[0] >= XCD_ORDER_MIN) ? UPD_TILE_XCD
+                          : (10 * rounds_win <= 7 * rounds)                       ? UPD_TILE_WIN
                                                                                   : UPD_TILE;
       Launch lu{LAUNCH_UPDATE, u.level, u.step, var, start, counts[0], 0, (int32_t)nwave, 0, 0, 0};
       p.launches.push_back(lu);

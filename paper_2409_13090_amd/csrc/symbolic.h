@@ -155,6 +155,8 @@ constexpr int64_t WAVE_SPLIT_MIN = 1024;
 constexpr int32_t UPD_TILE = 0;
 constexpr int32_t UPD_SHORT = 1;
 constexpr int32_t UPD_BIG = 2;
+constexpr int32_t UPD_TILE_WIN = 4;  // UPD_TILE with K chunks shaped to the contributions'
+                                     // rectangles (tiles of many small contributions)
 constexpr int32_t UPD_TILE_XCD = 3;  // UPD_TILE, workgroup b takes the tile at position
                                      // (b % 8) * (count / 8) + min(b % 8, count % 8) + b / 8
 

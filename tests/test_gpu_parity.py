@@ -410,6 +410,10 @@ def test_irregular_graph_ordering_matches_oracle(n, method):
     o, f = oracle_factor(A, ordering="graph")
     s, num, vals, info = gpu_factor(A, ordering="graph", method=method)
     assert info == 0
+    if method == "rlb":
+        # most update launches take the K chunks shaped to small rectangles
+        L = s.array("launches").reshape(-1, 12)
+        assert ((L[:, 0] == 1) & (L[:, 5] == 4)).sum() >= 4
     assert np.array_equal(s.array("perm"), o["perm"])
     err = compare_factor(num.export(), f, A.n)
     print(f"[case] irregular n={n} {method} rel_err={err:.3e}", flush=True)

@@ -22,6 +22,11 @@ namespace {
 
 thread_local std::string g_err;
 
+// update variants that differ only in how K is staged
+int32_t tile_class(int32_t v) {
+  return v == UPD_TILE_WIN || v == UPD_TILE_PACK ? UPD_TILE : v;
+}
+
 rlb_status fail(rlb_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -1048,7 +1053,10 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       if (cur[i] >= L.size()) continue;
       const Launch& l = L[cur[i]];
       const int32_t lv = l.level + shift[i];
-      const int32_t vv = l.variant;
+      // the dense, windowed and packed staging of one step are one class,
+      // the variant of the merged launch is chosen from its merged tiles
+      // (deterministic: each matrix's tiles keep the kernel of its own plan)
+      const int32_t vv = keep_fused ? l.variant : tile_class(l.variant);
       const int32_t pp = l.kind == LAUNCH_PANEL ? l.pre : 0;
       if (!any ||
           std::make_tuple(lv, l.step, l.kind, vv, pp) < std::make_tuple(bl, bs, bk, bv, bp)) {
@@ -1070,7 +1078,9 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       const Plan& p = syms[i]->s.plan;
       if (cur[i] >= lists[i].size()) continue;
       const Launch& l = lists[i][cur[i]];
-      if (l.level + shift[i] != bl || l.step != bs || l.kind != bk || l.variant != bv) continue;
+      if (l.level + shift[i] != bl || l.step != bs || l.kind != bk ||
+          (keep_fused ? l.variant : tile_class(l.variant)) != bv)
+        continue;
       if (bk == LAUNCH_PANEL && l.pre != bp) continue;
       if (bk != LAUNCH_UPDATE) {
         int32_t g_hi = 0;
@@ -1106,6 +1116,9 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       cur[i]++;
     }
     if (bk == LAUNCH_UPDATE) {
+      if (bv == UPD_TILE && !keep_fused)
+        m.variant = tile_variant(b->updates.data() + m.start,
+                                 (int64_t)b->updates.size() - m.start, b->segs.data());
       b->updates.insert(b->updates.end(), narrow.begin(), narrow.end());
       m.nwave = (int32_t)narrow.size();
     }

@@ -1498,6 +1498,192 @@ __global__ __launch_bounds__(256, 4) void k_update_win(const UpdTile* __restrict
 template __global__ void k_update_win<double>(const UpdTile*, const UpdSeg*, double*,
                                               const double*, int, int);
 
+// A zero word that masked loads read instead of an element (global memory,
+// never written).
+__device__ double k_zero_word[1];
+
+// k_update for launches whose tiles hold many contributions of a small k
+// (the small supernodes of a batch of 2D grids: k of a few columns): the
+// contributions of a tile are laid end to end along one K axis, each padded to
+// a multiple of 4, and staged 16 k at a time, so a chunk round serves several
+// of them. Each group of 4 consecutive k (one MFMA step) belongs to one
+// contribution: its X rows outside that contribution's rectangle and its Y
+// columns outside it are zero, and a wavefront runs the step only on the 16x16
+// blocks of its quarter that the rectangle meets, so every target entry
+// receives exactly the products of the contributions whose rectangles contain
+// it, in no more MFMA steps than the contributions' own k take. Wavefront w
+// stages k w, w+4, w+8, w+12 of each chunk, walking the contribution list
+// (copied to LDS when it is short) with a cursor of its own. FP64 operands.
+constexpr int PACK_SEGS = 21;  // contribution records staged in LDS (12 words each)
+__global__ __launch_bounds__(256, 4) void k_update_pack(const UpdTile* __restrict__ tiles,
+                                                        const UpdSeg* __restrict__ segs,
+                                                        double* __restrict__ L) {
+  constexpr int KC = 16, NQ = 4;
+  const UpdTile t = tiles[blockIdx.x];
+  __shared__ double sX[2][KC][64];
+  __shared__ double sY[2][KC][64];
+  __shared__ UpdSeg sSeg[PACK_SEGS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  const int lr = lane, lk = wave;
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+  const bool assign = t.flags & 4;
+  const int nseg = t.nseg;
+  if (nseg <= 0) return;
+  const bool in_lds = nseg <= PACK_SEGS;
+  constexpr int SEG_WORDS = (int)(sizeof(UpdSeg) / 4);
+  if (in_lds && tid < nseg * SEG_WORDS)
+    reinterpret_cast<int32_t*>(sSeg)[tid] = reinterpret_cast<const int32_t*>(segs + t.seg0)[tid];
+  __syncthreads();
+  auto seg_at = [&](int i) {
+    return in_lds ? uniform_seg(sSeg[i]) : uniform_seg(segs[t.seg0 + i]);
+  };
+  // total K of the tile, contributions padded to multiples of 4
+  int kt = 0;
+  for (int i = 0; i < nseg; ++i) kt += (seg_at(i).k + 3) & ~3;
+  const int nch = (kt + KC - 1) / KC;
+
+  // register sets of loaded values (a staged element outside its
+  // contribution's rectangle or k is read from a zero word) and the blocks
+  // of this wavefront's quarter each MFMA step of the chunk meets (bit
+  // 4 q + 2 bj + bi)
+  double xr[2][NQ], yr[2][NQ];
+  unsigned ub[2] = {0u, 0u};
+  const double* zp = k_zero_word;
+  int fe = 0, fbase = 0, fc = 0;  // contribution fe starts at padded k fbase
+  UpdSeg gf = seg_at(0);
+  auto fetch = [&](int set) {
+    unsigned u = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int v = fc * KC + lk + 4 * q;
+      while (fe + 1 < nseg && v >= fbase + ((gf.k + 3) & ~3)) {
+        fbase += (gf.k + 3) & ~3;
+        gf = seg_at(++fe);
+      }
+      const int kk = v - fbase;
+      const bool kin = kk < gf.k;
+      const int64_t ko = (int64_t)kk * gf.lds;
+      const double* px = kin && lr >= gf.ra && lr < gf.rb ? L + gf.x + ko + (lr - gf.ra) : zp;
+      const double* py = kin && lr >= gf.ca && lr < gf.cb ? L + gf.y + ko + (lr - gf.ca) : zp;
+      xr[set][q] = *px;
+      yr[set][q] = *py;
+      if (kk < ((gf.k + 3) & ~3)) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+            if (wr + 16 * bi < gf.rb && wr + 16 * bi + 16 > gf.ra && wc + 16 * bj < gf.cb &&
+                wc + 16 * bj + 16 > gf.ca)
+              u |= 1u << (4 * q + 2 * bj + bi);
+      }
+    }
+    ub[set] = u;
+    ++fc;
+  };
+  unsigned uu[2] = {0u, 0u};
+  auto stash = [&](int set, int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      sX[buf][lk + 4 * q][lr] = xr[set][q];
+      sY[buf][lk + 4 * q][lr] = yr[set][q];
+    }
+    uu[buf] = ub[set];
+  };
+  fetch(0);
+  if (fc < nch) fetch(1);
+  const unsigned cover = assign ? 0xffffu : cover_bits<Mfma<double>>(t, segs, wr, wc, lane);
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  stash(0, 0);
+  if (fc < nch) fetch(0);
+  __syncthreads();
+
+  auto multiply = [&](int buf) {
+    // step kq of the chunk: the staging wavefronts wrote k kq*4 + w
+    const unsigned u = __builtin_amdgcn_readfirstlane(uu[buf]);
+    if (u == 0xffffu) {
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const double a0 = sY[buf][kk][wc + (lane & 15)];
+        const double a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const double b0 = sX[buf][kk][wr + (lane & 15)];
+        const double b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        acc[0][0] = mfma64(a0, b0, acc[0][0]);
+        acc[0][1] = mfma64(a0, b1, acc[0][1]);
+        acc[1][0] = mfma64(a1, b0, acc[1][0]);
+        acc[1][1] = mfma64(a1, b1, acc[1][1]);
+      }
+    } else {
+#pragma unroll
+      for (int kq = 0; kq < NQ; ++kq) {
+        const unsigned m = (u >> (4 * kq)) & 15u;
+        if (!m) continue;
+        const int kk = kq * 4 + (lane >> 4);
+        const double a0 = sY[buf][kk][wc + (lane & 15)];
+        const double a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const double b0 = sX[buf][kk][wr + (lane & 15)];
+        const double b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        if (m & 1u) acc[0][0] = mfma64(a0, b0, acc[0][0]);
+        if (m & 2u) acc[0][1] = mfma64(a0, b1, acc[0][1]);
+        if (m & 4u) acc[1][0] = mfma64(a1, b0, acc[1][0]);
+        if (m & 8u) acc[1][1] = mfma64(a1, b1, acc[1][1]);
+      }
+    }
+  };
+  // chunk c (even) is in LDS buffer 0, its successor in register set 1
+  for (int c = 0;; c += 2) {
+    multiply(0);
+    if (c + 1 >= nch) break;
+    stash(1, 1);
+    if (fc < nch) fetch(1);
+    __syncthreads();
+    multiply(1);
+    if (c + 2 >= nch) break;
+    stash(0, 0);
+    if (fc < nch) fetch(0);
+    __syncthreads();
+  }
+  double cv[2][2][4] = {};
+  if (!atomic && !assign) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + Mfma<double>::drow(lane, v), t.n - 1);
+          if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        }
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<double>::drow(lane, v);
+        if (((cover >> (bj * 8 + bi * 4 + v)) & 1u) && row < t.m && col < t.n &&
+            (!diag || row >= col)) {
+          double* p = C + (int64_t)col * ldc + row;
+          if (atomic)
+            atomicAdd(p, -acc[bj][bi][v]);
+          else
+            *p = cv[bj][bi][v] - acc[bj][bi][v];
+        }
+      }
+}
+
 // Update of narrow target tiles (at most 64 rows and 16 columns: the targets
 // in small supernodes), one wavefront per tile and four tiles per
 // workgroup: C -= sum over the tile's contributions of X * Y^T, the MFMA
@@ -2702,6 +2888,8 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
   else if (win)
     hipLaunchKernelGGL(k_update_win<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
                        (int)count, 0);
+  else if (variant == UPD_TILE_PACK)
+    hipLaunchKernelGGL(k_update_pack, g, b, 0, st, tiles, segs, L);
   else
     hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
                        (int)count, xcd);

@@ -104,6 +104,33 @@ double seg_exec_flops(int64_t ra, int64_t rb, int64_t ca, int64_t cb, int64_t k)
 
 }  // namespace
 
+int32_t tile_variant(const UpdTile* tiles, int64_t count, const UpdSeg* segs) {
+  // chunk rounds of the three ways of staging K: KCH-deep chunks of every
+  // contribution; chunks shaped to the contribution's rectangle (64-row
+  // windows KCH deep, 32- and 16-row windows 2 and 4 times deeper); the
+  // contributions of a tile end to end (each padded to a multiple of 4), KCH
+  // deep
+  int64_t rounds = 0, rounds_win = 0, rounds_pack = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const UpdTile& t = tiles[i];
+    int64_t kt = 0;
+    for (int32_t e = 0; e < t.nseg; ++e) {
+      const UpdSeg& g = segs[t.seg0 + e];
+      const bool r16 = (g.ra >> 4) == ((g.rb - 1) >> 4) && (g.ca >> 4) == ((g.cb - 1) >> 4);
+      const bool r32 = (g.ra >> 5) == ((g.rb - 1) >> 5) && (g.ca >> 5) == ((g.cb - 1) >> 5);
+      const int64_t kc = KCH * (r16 ? 4 : (r32 ? 2 : 1));
+      rounds += (g.k + KCH - 1) / KCH;
+      rounds_win += (g.k + kc - 1) / kc;
+      kt += (g.k + 3) & ~3;
+    }
+    rounds_pack += (kt + KCH - 1) / KCH;
+  }
+  // another staging only when it saves at least 30 % of the rounds
+  const int64_t best = std::min(rounds_win, rounds_pack);
+  if (10 * best > 7 * rounds) return UPD_TILE;
+  return rounds_pack < rounds_win ? UPD_TILE_PACK : UPD_TILE_WIN;
+}
+
 int build_plan(Symbolic& s, std::string& err) {
   Plan& p = s.plan;
   p = Plan();
@@ -347,25 +374,10 @@ int build_plan(Symbolic& s, std::string& err) {
       p.launches[fused_into].ucount = counts[0];
       p.launches[fused_into].ncount = counts[1];
     } else if (counts[0]) {
-      // K chunks shaped to the contributions' rectangles when that saves at
-      // least 30 % of the launch's chunk rounds (64-row windows: KCH deep;
-      // 32- and 16-row windows: 2 and 4 times deeper)
-      int64_t rounds = 0, rounds_win = 0;
-      for (int64_t i = start; i < start + counts[0]; ++i) {
-        const UpdTile& t = p.updates[i];
-        for (int32_t e = 0; e < t.nseg; ++e) {
-          const UpdSeg& g = p.segs[t.seg0 + e];
-          const bool r16 = (g.ra >> 4) == ((g.rb - 1) >> 4) && (g.ca >> 4) == ((g.cb - 1) >> 4);
-          const bool r32 = (g.ra >> 5) == ((g.rb - 1) >> 5) && (g.ca >> 5) == ((g.cb - 1) >> 5);
-          const int64_t kc = KCH * (r16 ? 4 : (r32 ? 2 : 1));
-          rounds += (g.k + KCH - 1) / KCH;
-          rounds_win += (g.k + kc - 1) / kc;
-        }
-      }
       const int32_t var = shortk ? UPD_SHORT
-                          : (s.opt.tile_order == 1 && counts[0] >= XCD_ORDER_MIN) ? UPD_TILE_XCD
-                          : (10 * rounds_win <= 7 * rounds)                       ? UPD_TILE_WIN
-                                                                                  : UPD_TILE;
+                          : (s.opt.tile_order == 1 && counts[0] >= XCD_ORDER_MIN)
+                              ? UPD_TILE_XCD
+                              : tile_variant(p.updates.data() + start, counts[0], p.segs.data());
       Launch lu{LAUNCH_UPDATE, u.level, u.step, var, start, counts[0], 0, (int32_t)nwave, 0, 0, 0};
       p.launches.push_back(lu);
     }

@@ -157,6 +157,8 @@ constexpr int32_t UPD_SHORT = 1;
 constexpr int32_t UPD_BIG = 2;
 constexpr int32_t UPD_TILE_WIN = 4;  // UPD_TILE with K chunks shaped to the contributions'
                                      // rectangles (tiles of many small contributions)
+constexpr int32_t UPD_TILE_PACK = 5;  // UPD_TILE with the contributions of a tile end to end
+                                      // along K (tiles of many contributions of small k)
 constexpr int32_t UPD_TILE_XCD = 3;  // UPD_TILE, workgroup b takes the tile at position
                                      // (b % 8) * (count / 8) + min(b % 8, count % 8) + b / 8
 
@@ -255,5 +257,8 @@ int analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
             const AnalyzeOptions& opt, Symbolic& out, std::string& err);
 
 int build_plan(Symbolic& s, std::string& err);
+// Kernel variant (UPD_TILE, UPD_TILE_WIN or UPD_TILE_PACK) of an update launch
+// over the given tiles, from the chunk rounds each way of staging K takes.
+int32_t tile_variant(const UpdTile* tiles, int64_t count, const UpdSeg* segs);
 
 }  // namespace rlb

@@ -339,3 +339,42 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     Af = A.to_scipy_full()
     be = np.abs(Af @ X - B).max(axis=0) / (abs(Af).sum(axis=1).max() * np.abs(X).max(axis=0))
     assert be.max() <= 1e-14, be
+
+
+@pytest.mark.parametrize("name,make,kw", [
+    ("lap2d9_45x38", lambda: W.small_grid("9pt", (45, 38, 1), seed=21), {}),
+    ("batch_member_7", lambda: W.batch_member(7), {}),
+    ("irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40), {"ordering": "graph"}),
+])
+def test_update_variant_follows_chunk_rounds(name, make, kw):
+    """Each update launch's kernel variant is the way of staging K with the
+    fewest chunk rounds, taken only when it saves at least 30 %: KCH = 16 deep
+    chunks of every contribution (dense), chunks shaped to the contribution's
+    rectangle (16- and 32-row windows 4 and 2 times deeper), or the tile's
+    contributions end to end, each padded to a multiple of 4 (packed). The
+    2D lower levels take the packed form."""
+    s = rlb.Symbolic.from_matrix(make(), **kw)
+    L = s.array("launches").reshape(-1, 12)
+    U = s.array("update_tiles").reshape(-1, 7)
+    G = s.array("update_segs").reshape(-1, 9)
+    seen = set()
+    for l in L:
+        kind, st, cnt, var = int(l[0]), int(l[3]), int(l[4]), int(l[5])
+        if kind != 1 or var not in (0, 4, 5):
+            continue
+        rounds = win = pack = 0
+        for t in U[st:st + cnt]:
+            g = G[t[5]:t[5] + t[6]]
+            k, ra, rb, ca, cb = g[:, 3], g[:, 4], g[:, 5], g[:, 6], g[:, 7]
+            r16 = ((ra >> 4) == ((rb - 1) >> 4)) & ((ca >> 4) == ((cb - 1) >> 4))
+            r32 = ((ra >> 5) == ((rb - 1) >> 5)) & ((ca >> 5) == ((cb - 1) >> 5))
+            kc = np.where(r16, 64, np.where(r32, 32, 16))
+            rounds += int(((k + 15) // 16).sum())
+            win += int(((k + kc - 1) // kc).sum())
+            pack += -(-int(((k + 3) & ~3).sum()) // 16)
+        best = min(win, pack)
+        want = 0 if 10 * best > 7 * rounds else (5 if pack < win else 4)
+        assert var == want, (name, var, rounds, win, pack)
+        seen.add(var)
+    if name != "irregular_3000":
+        assert 5 in seen, seen

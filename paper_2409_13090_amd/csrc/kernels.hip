@@ -273,6 +273,16 @@ __device__ __forceinline__ UpdSeg uniform_seg(const UpdSeg& g) {
   return u;
 }
 
+// One FP64 element per lane from a buffer of `bytes` bytes at p (a uniform
+// address): lanes whose byte offset lies outside it read zero (the buffer
+// unit's range check), so ragged rows and columns need no masking.
+constexpr int BUF_CONFIG = 0x00020000;  // raw buffer, 32-bit data format
+__device__ __forceinline__ double load_range(const double* p, int bytes, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, bytes, BUF_CONFIG);
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
 constexpr int KC = 16;  // K chunk staged per LDS buffer
 
 // Which of this thread's 16 accumulator elements of a 64x64 target tile lie in
@@ -1136,16 +1146,32 @@ __global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ t
   int fe = 0, fk = 0;
   UpdSeg gf = seg_at(0);
   auto fetch = [&](int set) {
-    xin[set] = lr >= gf.ra && lr < gf.rb;
-    yin[set] = lr >= gf.ca && lr < gf.cb;
-    kvalid[set] = gf.k - fk - lk;
-    const int64_t xo = gf.x + min(max(lr - gf.ra, 0), gf.rb - gf.ra - 1);
-    const int64_t yo = gf.y + min(max(lr - gf.ca, 0), gf.cb - gf.ca - 1);
+    if constexpr (sizeof(T) == 8) {
+      // FP64 operands through buffer loads whose range is the contribution's
+      // rows (columns) of one source column: rows outside it, and k past the
+      // contribution's, read as zero with no masking in the kernel
+      const int kw = uni32(fk + lk);
+      const uint32_t xoff = (uint32_t)(lr - gf.ra) << 3, yoff = (uint32_t)(lr - gf.ca) << 3;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int64_t kk = min(fk + lk + 4 * q, gf.k - 1);
-      xr[set][q] = S[xo + kk * gf.lds];
-      yr[set][q] = S[yo + kk * gf.lds];
+      for (int q = 0; q < NQ; ++q) {
+        const int kk = kw + 4 * q;
+        const bool kin = kk < gf.k;
+        const int64_t ko = (int64_t)kk * gf.lds;
+        xr[set][q] = load_range(S + gf.x + ko, kin ? (gf.rb - gf.ra) << 3 : 0, xoff);
+        yr[set][q] = load_range(S + gf.y + ko, kin ? (gf.cb - gf.ca) << 3 : 0, yoff);
+      }
+    } else {
+      xin[set] = lr >= gf.ra && lr < gf.rb;
+      yin[set] = lr >= gf.ca && lr < gf.cb;
+      kvalid[set] = gf.k - fk - lk;
+      const int64_t xo = gf.x + min(max(lr - gf.ra, 0), gf.rb - gf.ra - 1);
+      const int64_t yo = gf.y + min(max(lr - gf.ca, 0), gf.cb - gf.ca - 1);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int64_t kk = min(fk + lk + 4 * q, gf.k - 1);
+        xr[set][q] = S[xo + kk * gf.lds];
+        yr[set][q] = S[yo + kk * gf.lds];
+      }
     }
     fk += KC;
     if (fk >= gf.k) {
@@ -1156,9 +1182,14 @@ __global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ t
   auto stash = [&](int set, int buf) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const bool kin = 4 * q < kvalid[set];
-      sX[buf][lk + 4 * q][lr] = (kin && xin[set]) ? xr[set][q] : T(0);
-      sY[buf][lk + 4 * q][lr] = (kin && yin[set]) ? yr[set][q] : T(0);
+      if constexpr (sizeof(T) == 8) {
+        sX[buf][lk + 4 * q][lr] = xr[set][q];
+        sY[buf][lk + 4 * q][lr] = yr[set][q];
+      } else {
+        const bool kin = 4 * q < kvalid[set];
+        sX[buf][lk + 4 * q][lr] = (kin && xin[set]) ? xr[set][q] : T(0);
+        sY[buf][lk + 4 * q][lr] = (kin && yin[set]) ? yr[set][q] : T(0);
+      }
     }
   };
   // chunks 0 and 1 in flight first, then the target values

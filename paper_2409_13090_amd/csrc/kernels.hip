@@ -339,14 +339,30 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
   const bool diag = t.flags & 1;
   const bool assign = t.flags & 4;  // write -(sum) without reading the target
   const bool xin = lr >= g.ra && lr < g.rb, yin = lr >= g.ca && lr < g.cb;
-  const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
-  const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
   T xr[16], yr[16];
+  if constexpr (sizeof(T) == 8) {
+    // range-checked buffer loads: rows outside the rectangle and k past the
+    // contribution's read zero
+    const UpdSeg u = uniform_seg(g);
+    const int kw = uni32(lk);
+    const uint32_t xoff = (uint32_t)(lr - u.ra) << 3, yoff = (uint32_t)(lr - u.ca) << 3;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int64_t kk = min(lk + 4 * q, g.k - 1);
-    xr[q] = S[xo + kk * g.lds];
-    yr[q] = S[yo + kk * g.lds];
+    for (int q = 0; q < 16; ++q) {
+      const int kk = kw + 4 * q;
+      const bool kin = kk < u.k;
+      const int64_t ko = (int64_t)kk * u.lds;
+      xr[q] = load_range(S + u.x + ko, kin ? (u.rb - u.ra) << 3 : 0, xoff);
+      yr[q] = load_range(S + u.y + ko, kin ? (u.cb - u.ca) << 3 : 0, yoff);
+    }
+  } else {
+    const int64_t xo = g.x + min(max(lr - g.ra, 0), g.rb - g.ra - 1);
+    const int64_t yo = g.y + min(max(lr - g.ca, 0), g.cb - g.ca - 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t kk = min(lk + 4 * q, g.k - 1);
+      xr[q] = S[xo + kk * g.lds];
+      yr[q] = S[yo + kk * g.lds];
+    }
   }
   double cv[2][2][4];
 #pragma unroll
@@ -372,9 +388,14 @@ __device__ __forceinline__ void upd_short_tile(const UpdTile& t, const UpdSeg& g
 #pragma unroll
       for (int u = 0; u < KC / 4; ++u) {
         const int q = 4 * c + u;
-        const bool kin = lk + 4 * q < g.k;
-        sX[buf][lk + 4 * u][lr] = (kin && xin) ? xr[q] : T(0);
-        sY[buf][lk + 4 * u][lr] = (kin && yin) ? yr[q] : T(0);
+        if constexpr (sizeof(T) == 8) {
+          sX[buf][lk + 4 * u][lr] = xr[q];
+          sY[buf][lk + 4 * u][lr] = yr[q];
+        } else {
+          const bool kin = lk + 4 * q < g.k;
+          sX[buf][lk + 4 * u][lr] = (kin && xin) ? xr[q] : T(0);
+          sY[buf][lk + 4 * u][lr] = (kin && yin) ? yr[q] : T(0);
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -1359,6 +1380,23 @@ __global__ __launch_bounds__(256, 4) void k_update_win(const UpdTile* __restrict
   UpdSeg gf = seg_at(0);
   int fwl = window_log(gf);
   auto fetch_w = [&](int set, int wl) {
+    if constexpr (sizeof(T) == 8) {
+      if (wl == 6) {
+        // 64-row chunks: one k per wavefront and load, through range-checked
+        // buffer loads (ragged rows and k past the contribution read zero)
+        const int kw = uni32(fk + (tid >> 6));
+        const uint32_t xoff = (uint32_t)(lane - gf.ra) << 3, yoff = (uint32_t)(lane - gf.ca) << 3;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int kk = kw + 4 * q;
+          const bool kin = kk < gf.k;
+          const int64_t ko = (int64_t)kk * gf.lds;
+          xr[set][q] = load_range(S + gf.x + ko, kin ? (gf.rb - gf.ra) << 3 : 0, xoff);
+          yr[set][q] = load_range(S + gf.y + ko, kin ? (gf.cb - gf.ca) << 3 : 0, yoff);
+        }
+        return;
+      }
+    }
     const int win = 1 << wl;
     const int r = tid & (win - 1), kb = tid >> wl, kstep = 256 >> wl;
     const int xrow = (gf.ra & ~(win - 1)) + r, ycol = (gf.ca & ~(win - 1)) + r;
@@ -1393,8 +1431,13 @@ __global__ __launch_bounds__(256, 4) void k_update_win(const UpdTile* __restrict
     for (int q = 0; q < NQ; ++q) {
       const bool kin = kstep * q < kvalid[set];
       const int pos = ((kb + kstep * q) << wl) + r;
-      sX[buf][pos] = (kin && xin[set]) ? xr[set][q] : T(0);
-      sY[buf][pos] = (kin && yin[set]) ? yr[set][q] : T(0);
+      if (sizeof(T) == 8 && wl == 6) {
+        sX[buf][pos] = xr[set][q];
+        sY[buf][pos] = yr[set][q];
+      } else {
+        sX[buf][pos] = (kin && xin[set]) ? xr[set][q] : T(0);
+        sY[buf][pos] = (kin && yin[set]) ? yr[set][q] : T(0);
+      }
     }
   };
   auto stash = [&](int set, int buf) {
@@ -1529,10 +1572,6 @@ __global__ __launch_bounds__(256, 4) void k_update_win(const UpdTile* __restrict
 template __global__ void k_update_win<double>(const UpdTile*, const UpdSeg*, double*,
                                               const double*, int, int);
 
-// A zero word that masked loads read instead of an element (global memory,
-// never written).
-__device__ double k_zero_word[1];
-
 // k_update for launches whose tiles hold many contributions of a small k
 // (the small supernodes of a batch of 2D grids: k of a few columns): the
 // contributions of a tile are laid end to end along one K axis, each padded to
@@ -1578,13 +1617,12 @@ __global__ __launch_bounds__(256, 4) void k_update_pack(const UpdTile* __restric
   for (int i = 0; i < nseg; ++i) kt += (seg_at(i).k + 3) & ~3;
   const int nch = (kt + KC - 1) / KC;
 
-  // register sets of loaded values (a staged element outside its
-  // contribution's rectangle or k is read from a zero word) and the blocks
+  // register sets of loaded values (range-checked buffer loads: a staged
+  // element outside its contribution's rectangle or k reads zero) and the blocks
   // of this wavefront's quarter each MFMA step of the chunk meets (bit
   // 4 q + 2 bj + bi)
   double xr[2][NQ], yr[2][NQ];
   unsigned ub[2] = {0u, 0u};
-  const double* zp = k_zero_word;
   int fe = 0, fbase = 0, fc = 0;  // contribution fe starts at padded k fbase
   UpdSeg gf = seg_at(0);
   auto fetch = [&](int set) {
@@ -1599,10 +1637,10 @@ __global__ __launch_bounds__(256, 4) void k_update_pack(const UpdTile* __restric
       const int kk = v - fbase;
       const bool kin = kk < gf.k;
       const int64_t ko = (int64_t)kk * gf.lds;
-      const double* px = kin && lr >= gf.ra && lr < gf.rb ? L + gf.x + ko + (lr - gf.ra) : zp;
-      const double* py = kin && lr >= gf.ca && lr < gf.cb ? L + gf.y + ko + (lr - gf.ca) : zp;
-      xr[set][q] = *px;
-      yr[set][q] = *py;
+      xr[set][q] = load_range(L + gf.x + ko, kin ? (gf.rb - gf.ra) << 3 : 0,
+                              (uint32_t)(lr - gf.ra) << 3);
+      yr[set][q] = load_range(L + gf.y + ko, kin ? (gf.cb - gf.ca) << 3 : 0,
+                              (uint32_t)(lr - gf.ca) << 3);
       if (kk < ((gf.k + 3) & ~3)) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)

@@ -243,8 +243,8 @@ def main():
     # (the algorithmic flops of the tiles these launches run; the previous
     # block's update inside the panel launches is not part of them)
     ach = info["flops_upd_launch"] / upd_s / 1e12
-    roof = {"kernel": "update launches: k_update<double> / k_update_short<double> (SYRK/GEMM "
-                      "summed into 64x64 target tiles, MFMA f64 16x16x4)",
+    roof = {"kernel": "update launches: k_update / k_update_win / k_update_pack / k_update_short "
+                      "(SYRK/GEMM summed into 64x64 target tiles, MFMA f64 16x16x4)",
             "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(args.workload, args.side),

@@ -125,3 +125,25 @@ def test_solve_after_failed_factor_is_refused_without_status_call():
     with pytest.raises(rlb.RlbError) as e:
         num.solve(torch.zeros(A.n, dtype=torch.float64, device="cuda"))
     assert e.value.status == -6
+
+
+def test_batch_unfused_merged_launches_meet_oracle():
+    """Matrices analysed with deterministic = 0: the batch unfuses their panel
+    steps and merges every matrix's update launches of a step into one whose
+    kernel (dense, windowed or packed K staging) is chosen from the merged
+    tiles; each member's factor still meets the oracle."""
+    import torch
+    mats = [W.batch_member(i) for i in range(16)]
+    syms = [rlb.Symbolic.from_matrix(A, deterministic=False) for A in mats]
+    b = rlb.Batch(syms)
+    vals = [torch.from_numpy(A.values).cuda() for A in mats]
+    assert np.all(b.factor(vals) == 0)
+    ws_b = b.workspace.cpu().numpy()
+    elems = [s.info()["factor_bytes"] // 8 for s in syms]
+    base = np.concatenate([[0], np.cumsum(elems)])
+    worst = 0.0
+    for i in (0, 3, 7, 15):
+        part = ws_b[base[i]:base[i] + elems[i]]
+        o, f = oracle_factor(mats[i])
+        worst = max(worst, compare_factor(export_from_storage(syms[i], part), f, mats[i].n))
+    print(f"[case] unfused batch of 16, worst rel_err {worst:.3e}", flush=True)

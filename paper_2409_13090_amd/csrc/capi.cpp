@@ -414,7 +414,7 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
       return fail(RLB_ERR_ARG, "bad outer_block (a multiple of 64)");
     ao.outer_block = opt->outer_block ? opt->outer_block : 256;
     ao.big_tile_min = opt->big_tile_min;
-    if (opt->method < 0 || opt->method > 1) return fail(RLB_ERR_ARG, "bad method");
+    if (opt->method < 0 || opt->method > 2) return fail(RLB_ERR_ARG, "bad method");
     ao.method = opt->method;
     if (opt->tile_order < 0 || opt->tile_order > 1) return fail(RLB_ERR_ARG, "bad tile_order");
     ao.tile_order = opt->tile_order;

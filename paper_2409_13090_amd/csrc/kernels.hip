@@ -1853,18 +1853,48 @@ __global__ __launch_bounds__(256, 4) void k_update_w(const UpdTile* __restrict__
 }
 
 // RL (Algorithm 4) assembly: column j of an update matrix U_J added into the
-// ancestor column that owns it, at the rows its relative indices give; one
-// wavefront per column, four per workgroup. Update matrices of several
-// supernodes of a step may meet in one ancestor entry: the additions are
-// atomic (their order, and so the rounding, varies from run to run).
+// ancestor column that owns it, at the rows its relative indices give. The
+// columns of a launch that target one ancestor column (from several update
+// matrices of the step) are consecutive in the list, in source order; the
+// wavefront of the first of them adds them all, one after the other, so
+// every entry has one writer and the sums have a fixed order (no atomics).
+// The target entries are read and written at agent scope (past the CU's L1)
+// and each column's stores complete before the next column's reads.
 __global__ __launch_bounds__(256) void k_assemble(const AsmCol* __restrict__ cols,
                                                   const int32_t* __restrict__ rows,
                                                   double* __restrict__ L, int count) {
   const int lane = threadIdx.x & 63;
   const int ci = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
   if (ci >= count) return;
-  const AsmCol c = cols[ci];
-  for (int i = lane; i < c.len; i += 64) atomicAdd(L + c.dst + rows[c.rp + i], L[c.src + i]);
+  const int64_t dst = uni64(cols[ci].dst);
+  if (ci > 0 && uni64(cols[ci - 1].dst) == dst) return;  // not the first of its group
+  for (int c = ci; c < count; ++c) {
+    const AsmCol a = cols[c];
+    if (uni64(a.dst) != dst) break;
+    const int64_t src = uni64(a.src);
+    const int32_t rp = uni32(a.rp), len = uni32(a.len);
+    // 256 entries at a time: their row positions and values, then their
+    // targets, then the sums, so each pass waits for memory twice
+    for (int i0 = 0; i0 < len; i0 += 256) {
+      int ro[4];
+      double u[4], t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = min(i0 + 64 * q + lane, len - 1);
+        ro[q] = rows[rp + i];
+        u[q] = L[src + i];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        t[q] = __hip_atomic_load(L + dst + ro[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (i0 + 64 * q + lane < len)
+          __hip_atomic_store(L + dst + ro[q], t[q] + u[q], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this column's stores are done
+  }
 }
 
 // The trailing updates of a step as a launch of their own.

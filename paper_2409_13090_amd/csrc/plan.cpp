@@ -35,6 +35,7 @@ constexpr int FLAG_DIAG = 1;
 constexpr int FLAG_ATOMIC = 2;
 constexpr int FLAG_ASSIGN = 4;  // the tile is written with -(sum), not read (RL's U_J)
 constexpr int KCH = 16;        // K chunk of the update kernel
+constexpr double HYBRID_RATIO = 1.5;
 // panel launch cost model by width class (1, 2, 4 blocks of 16 columns):
 // microseconds per workgroup, resident workgroups on the device, and the
 // fixed cost of a launch (measured orders of magnitude on MI355X)
@@ -265,6 +266,22 @@ int build_plan(Symbolic& s, std::string& err) {
       return -1;
     }
   }
+  // hybrid method: a supernode's ancestor updates cost about one K pass per
+  // (rectangle, 64x64 target tile) pair they meet when written in place, and
+  // one per 64x64 tile of its update matrix (plus the assembly) through RL;
+  // the update matrix is taken when the first is HYBRID_RATIO times the second
+  auto rl_better = [&](int64_t J) {
+    const int64_t r = M(J) - W(J);
+    if (r <= 0) return false;
+    int64_t pieces = 0;
+    for (const Rect& q : rects[J]) {
+      const int64_t nr = (q.r0 + q.mr - 1) / TM - q.r0 / TM + 1;
+      const int64_t nc = (q.c0 + q.nc - 1) / TN - q.c0 / TN + 1;
+      pieces += nr * nc;
+    }
+    const int64_t t = (r + TM - 1) / TM;
+    return (double)pieces > HYBRID_RATIO * (double)(t * (t + 1) / 2);
+  };
 
   // Where a wide supernode switches from outer blocks to per-step trailing
   // updates: once its trailing region holds few enough 64x64 tiles to run
@@ -567,7 +584,18 @@ int build_plan(Symbolic& s, std::string& err) {
           }
         }
       }
-      if (s.opt.method == 1 && !finished.empty()) {
+      // the supernodes whose ancestor updates go through an update matrix:
+      // all finished ones in RL; in the hybrid method those whose rectangles
+      // would fill the MFMA blocks of the target tiles poorly
+      std::vector<int64_t> via_u;
+      if (s.opt.method == 1) {
+        via_u.swap(finished);
+      } else if (s.opt.method == 2) {
+        std::vector<int64_t> keep;
+        for (int64_t J : finished) (rl_better(J) ? via_u : keep).push_back(J);
+        finished.swap(keep);
+      }
+      if (!via_u.empty()) {
         // RL (Algorithm 4): for every supernode J whose cdiv ends at this
         // step, one SYRK forms its update matrix U_J = -L_{R,J} L_{R,J}^T
         // (R: the r_J rows below the diagonal block; lower triangle, r_J x r_J
@@ -582,7 +610,7 @@ int build_plan(Symbolic& s, std::string& err) {
         bool shortk = true;
         int64_t uo = 0;
         const int64_t ac0 = (int64_t)p.asmcols.size();
-        for (int64_t J : finished) {
+        for (int64_t J : via_u) {
           const int64_t w = W(J), m = M(J), r = m - w;
           if (r == 0) continue;
           const int64_t ub = p.l_elems + uo;
@@ -647,6 +675,9 @@ int build_plan(Symbolic& s, std::string& err) {
           err = "RL assembly lists too large";
           return -1;
         }
+        // the step's columns grouped by target column, in source order
+        std::stable_sort(p.asmcols.begin() + ac0, p.asmcols.end(),
+                         [](const AsmCol& x, const AsmCol& y) { return x.dst < y.dst; });
         p.u_elems = std::max(p.u_elems, uo);
         if (!ut.empty()) {
           const int64_t start = (int64_t)p.updates.size();
@@ -663,7 +694,6 @@ int build_plan(Symbolic& s, std::string& err) {
           p.flops_upd_alg += alg;
           p.flops_upd_launch += alg;
         }
-        finished.clear();
       }
       // the long part cut by a target tile grid of side T; every tile keeps
       // its contributions in ascending source order

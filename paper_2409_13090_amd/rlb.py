@@ -187,7 +187,7 @@ class Symbolic:
         o.deterministic = 1 if deterministic else 0
         o.outer_block = int(outer_block)
         o.big_tile_min = int(big_tile_min)
-        o.method = {"rlb": 0, "rl": 1}[method]
+        o.method = {"rlb": 0, "rl": 1, "hybrid": 2}[method]
         o.tile_order = {"weight": 0, "xcd": 1}[tile_order]
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)

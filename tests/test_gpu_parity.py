@@ -390,22 +390,28 @@ RL_CASES = [
 ]
 
 
+@pytest.mark.parametrize("method", ["rl", "hybrid"])
 @pytest.mark.parametrize("name,make", RL_CASES, ids=[c[0] for c in RL_CASES])
-def test_rl_method_matches_oracle(name, make):
+def test_rl_method_matches_oracle(name, make, method):
     """RL (Algorithm 4): update matrices in working storage, assembled into the
-    ancestors through relative indices; the same factor as the oracle's."""
+    ancestors through relative indices; the hybrid method takes that route for
+    the supernodes whose rectangles are small and writes the others' updates
+    in place; the same factor as the oracle's."""
     A = make()
     o, f = oracle_factor(A)
-    s, num, vals, info = gpu_factor(A, method="rl")
+    s, num, vals, info = gpu_factor(A, method=method)
     assert info == 0
     assert s.info()["u_bytes"] > 0
+    L = s.array("launches").reshape(-1, 12)
+    assert (L[:, 0] == 2).sum() >= 1
     err = compare_factor(num.export(), f, A.n)
-    print(f"[case] RL {name} rel_err={err:.3e} u_bytes={s.info()['u_bytes']}", flush=True)
+    print(f"[case] {method} {name} rel_err={err:.3e} u_bytes={s.info()['u_bytes']}", flush=True)
     if A.rhs is not None:
         solve_check(num, A)
 
 
-@pytest.mark.parametrize("n,method", [(3000, "rlb"), (6000, "rlb"), (3000, "rl")])
+@pytest.mark.parametrize("n,method", [(3000, "rlb"), (6000, "rlb"), (3000, "rl"),
+                                      (6000, "hybrid")])
 def test_irregular_graph_ordering_matches_oracle(n, method):
     """General sparse input: a k-nearest-neighbour graph Laplacian of random
     points (no grid) ordered by graph nested dissection, the oracle deriving

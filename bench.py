@@ -286,41 +286,51 @@ def main():
         "roofline": roof,
     }
 
-    if not args.no_rl:
-        # RL (Algorithm 4) on the same matrix and the same symbolic phase:
-        # update matrices in working storage, assembled into the ancestors
-        sym_rl = rlb.Symbolic.from_matrix(A, method="rl", **order_kw)
-        info_rl = sym_rl.info()
-        num_rl = rlb.Numeric(sym_rl, rlb.RLB_PREC_FP64)
-        num_rl.set_graph_mode(graph)
-        ws_rl = torch.empty(info_rl["factor_bytes"] // 8 + 1, dtype=torch.float64, device=dev)
-        assert num_rl.factor(vals, ws_rl) == 0
-        ms_rl = []
+    def time_method(method):
+        """FP64 factor of the same matrix with another update method, on the
+        same symbolic phase settings (median of the timed steps)."""
+        sym_m = rlb.Symbolic.from_matrix(A, method=method, **order_kw)
+        info_m = sym_m.info()
+        num_m = rlb.Numeric(sym_m, rlb.RLB_PREC_FP64)
+        num_m.set_graph_mode(graph)
+        ws_m = torch.empty(info_m["factor_bytes"] // 8 + 1, dtype=torch.float64, device=dev)
+        assert num_m.factor(vals, ws_m) == 0
+        ms_m = []
         for _ in range(args.steps):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            num_rl.factor(vals, ws_rl, check=False)
+            num_m.factor(vals, ws_m, check=False)
             e1.record(stream)
             e1.synchronize()
-            ms_rl.append(e0.elapsed_time(e1))
-        assert num_rl.status() == 0
+            ms_m.append(e0.elapsed_time(e1))
+        assert num_m.status() == 0
         X.copy_(B)
-        num_rl.solve(X)
-        be_rl = num_rl.backward_error(B, X)
-        t_rl = statistics.median(ms_rl) / 1e3
+        num_m.solve(X)
+        be_m = num_m.backward_error(B, X)
+        t_m = statistics.median(ms_m) / 1e3
+        n_asm = int((sym_m.array("launches").reshape(-1, 12)[:, 0] == 2).sum())
+        return {"factor_ms": round(t_m * 1e3, 3), "gflops": round(F / t_m / 1e9, 2),
+                "rlb_factor_ms": round(t_fac * 1e3, 3),
+                "over_rlb_time": round(t_m / t_fac, 3),
+                "fp_storage_bytes": info_m["factor_bytes"],
+                "update_matrix_bytes": info_m["u_bytes"],
+                "rlb_fp_storage_bytes": info["factor_bytes"],
+                "assembly_launches": n_asm,
+                "backward_error_max": float(f"{max(be_m):.3e}")}
+
+    if not args.no_rl:
+        # RL (Algorithm 4) on the same matrix and the same symbolic phase:
+        # update matrices in working storage, assembled into the ancestors
         out["rl"] = {"method": "RL (Algorithm 4): SYRK into an update matrix per supernode, "
                                "assembled into the ancestors through relative indices "
-                               "(atomic additions)",
-                     "factor_ms": round(t_rl * 1e3, 3), "gflops": round(F / t_rl / 1e9, 2),
-                     "rlb_factor_ms": round(t_fac * 1e3, 3),
-                     "rl_over_rlb_time": round(t_rl / t_fac, 3),
-                     "fp_storage_bytes": info_rl["factor_bytes"],
-                     "update_matrix_bytes": info_rl["u_bytes"],
-                     "rlb_fp_storage_bytes": info["factor_bytes"],
-                     "backward_error_max": float(f"{max(be_rl):.3e}")}
-        del num_rl, ws_rl
-
+                               "(one writer per target column, no atomics)",
+                     **time_method("rl")}
+        # per supernode the cheaper of the two routes by the planner's model
+        out["hybrid"] = {"method": "RLB for most supernodes, RL's update matrix for those "
+                                   "whose rectangles meet many target tiles (planner's "
+                                   "cost model; not the paper's method)",
+                         **time_method("hybrid")}
     if not args.no_mixed:
         mixed = args.mixed or ("bf16" if args.workload == "elast3_40" else "fp32")
         prec = {"fp32": rlb.RLB_PREC_FP32_UPDATES, "bf16": rlb.RLB_PREC_BF16_UPDATES,
@@ -391,6 +401,7 @@ ABLATIONS = [
     ("atomic_split", {"deterministic": False}),
     ("big_tiles_128", {"big_tile_min": 256}),
     ("method_rl", {"method": "rl"}),
+    ("method_hybrid", {"method": "hybrid"}),
     ("tile_order_xcd", {"tile_order": "xcd"}),
 ]
 

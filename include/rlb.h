@@ -93,14 +93,22 @@ typedef struct rlb_options {
                                Algorithm 4 (Section 2.2.1), each supernode's updates
                                formed in an update matrix U_J (working storage after the
                                factor in the workspace) and assembled into the ancestors
-                               through relative indices, with atomic additions; FP64
-                               only, not batched */
+                               through relative indices (one writer per target column,
+                               a fixed order); RLB_METHOD_HYBRID: per step, the RL route
+                               for the supernodes whose rectangles meet many more 64x64
+                               target tiles than U_J has (a cost model of the planner),
+                               Algorithm 5 for the rest. The two others are FP64 only
+                               and not batched */
   int32_t tile_order;       /* target tiles of an update launch of its own:
                                RLB_TILE_ORDER_WEIGHT (0): heaviest first, dealt round-robin
                                to the XCDs as dispatched; RLB_TILE_ORDER_XCD (1): in 8x8
                                blocks of neighbouring tiles of each target supernode, and
                                each XCD takes a contiguous eighth of that order, so the
                                tiles running on one XCD (one L2) share their source rows */
+  double hybrid_step_us;    /* RLB_METHOD_HYBRID: the time (microseconds, by the planner's
+                               model) the update-matrix route must save in a step to be
+                               taken there; 0 (default): 30, about the step's two extra
+                               launches; < 0: any saving */
 } rlb_options;
 
 #define RLB_TILE_ORDER_WEIGHT 0
@@ -108,6 +116,7 @@ typedef struct rlb_options {
 
 #define RLB_METHOD_RLB 0
 #define RLB_METHOD_RL 1
+#define RLB_METHOD_HYBRID 2
 
 typedef struct rlb_info {
   int64_t n, nnz_a;

@@ -22,9 +22,12 @@ namespace {
 
 thread_local std::string g_err;
 
-// update variants that differ only in how K is staged
-int32_t tile_class(int32_t v) {
-  return v == UPD_TILE_WIN || v == UPD_TILE_PACK ? UPD_TILE : v;
+// the merge key of a launch's variant: update variants that differ only in
+// how K is staged are one class (a panel launch's variant is its width class)
+int32_t merge_class(const Launch& l) {
+  return l.kind == LAUNCH_UPDATE && (l.variant == UPD_TILE_WIN || l.variant == UPD_TILE_PACK)
+             ? UPD_TILE
+             : l.variant;
 }
 
 rlb_status fail(rlb_status s, const std::string& msg) {
@@ -418,6 +421,8 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     ao.method = opt->method;
     if (opt->tile_order < 0 || opt->tile_order > 1) return fail(RLB_ERR_ARG, "bad tile_order");
     ao.tile_order = opt->tile_order;
+    if (!(opt->hybrid_step_us == opt->hybrid_step_us)) return fail(RLB_ERR_ARG, "bad hybrid_step_us");
+    ao.hybrid_step_us = opt->hybrid_step_us == 0 ? 30.0 : std::max(0.0, opt->hybrid_step_us);
   } else {
     ao.ordering = 0;
   }
@@ -1056,7 +1061,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       // the dense, windowed and packed staging of one step are one class,
       // the variant of the merged launch is chosen from its merged tiles
       // (deterministic: each matrix's tiles keep the kernel of its own plan)
-      const int32_t vv = keep_fused ? l.variant : tile_class(l.variant);
+      const int32_t vv = keep_fused ? l.variant : merge_class(l);
       const int32_t pp = l.kind == LAUNCH_PANEL ? l.pre : 0;
       if (!any ||
           std::make_tuple(lv, l.step, l.kind, vv, pp) < std::make_tuple(bl, bs, bk, bv, bp)) {
@@ -1079,7 +1084,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       if (cur[i] >= lists[i].size()) continue;
       const Launch& l = lists[i][cur[i]];
       if (l.level + shift[i] != bl || l.step != bs || l.kind != bk ||
-          (keep_fused ? l.variant : tile_class(l.variant)) != bv)
+          (keep_fused ? l.variant : merge_class(l)) != bv)
         continue;
       if (bk == LAUNCH_PANEL && l.pre != bp) continue;
       if (bk != LAUNCH_UPDATE) {

@@ -35,7 +35,8 @@ constexpr int FLAG_DIAG = 1;
 constexpr int FLAG_ATOMIC = 2;
 constexpr int FLAG_ASSIGN = 4;  // the tile is written with -(sum), not read (RL's U_J)
 constexpr int KCH = 16;        // K chunk of the update kernel
-constexpr double HYBRID_RATIO = 1.5;
+constexpr double HYB_PASSES_PER_US = 1024 / 2.3;  // hybrid method's cost model
+constexpr double HYB_BYTES_PER_US = 2.0e6;
 // panel launch cost model by width class (1, 2, 4 blocks of 16 columns):
 // microseconds per workgroup, resident workgroups on the device, and the
 // fixed cost of a launch (measured orders of magnitude on MI355X)
@@ -266,13 +267,16 @@ int build_plan(Symbolic& s, std::string& err) {
       return -1;
     }
   }
-  // hybrid method: a supernode's ancestor updates cost about one K pass per
-  // (rectangle, 64x64 target tile) pair they meet when written in place, and
-  // one per 64x64 tile of its update matrix (plus the assembly) through RL;
-  // the update matrix is taken when the first is HYBRID_RATIO times the second
-  auto rl_better = [&](int64_t J) {
+  // hybrid method, a model of the time (us) the update-matrix route saves for
+  // supernode J: written in place its ancestor updates take one K pass per
+  // (rectangle, 64x64 target tile) pair they meet, through RL one per 64x64
+  // tile of U_J, and the assembly moves 32 bytes per entry of U_J (written,
+  // read, target read and written); K passes run at about 1024 resident tiles
+  // per 2.3 us round, the assembly at about 2 TB/s (half the rate it moves
+  // its bytes at: a margin for what the model leaves out)
+  auto rl_gain_us = [&](int64_t J) {
     const int64_t r = M(J) - W(J);
-    if (r <= 0) return false;
+    if (r <= 0) return 0.0;
     int64_t pieces = 0;
     for (const Rect& q : rects[J]) {
       const int64_t nr = (q.r0 + q.mr - 1) / TM - q.r0 / TM + 1;
@@ -280,9 +284,9 @@ int build_plan(Symbolic& s, std::string& err) {
       pieces += nr * nc;
     }
     const int64_t t = (r + TM - 1) / TM;
-    return (double)pieces > HYBRID_RATIO * (double)(t * (t + 1) / 2);
+    const double passes = (double)(pieces - t * (t + 1) / 2) * (double)((W(J) + KCH - 1) / KCH);
+    return passes / HYB_PASSES_PER_US - 32.0 * 0.5 * (double)r * (double)(r + 1) / HYB_BYTES_PER_US;
   };
-
   // Where a wide supernode switches from outer blocks to per-step trailing
   // updates: once its trailing region holds few enough 64x64 tiles to run
   // beside the next panel launch (the fused form), every step updates all of
@@ -591,9 +595,23 @@ int build_plan(Symbolic& s, std::string& err) {
       if (s.opt.method == 1) {
         via_u.swap(finished);
       } else if (s.opt.method == 2) {
+        // the supernodes the route saves time for, when together they save
+        // more than the step's two extra launches (SYRK and assembly) cost
         std::vector<int64_t> keep;
-        for (int64_t J : finished) (rl_better(J) ? via_u : keep).push_back(J);
-        finished.swap(keep);
+        double saved = 0;
+        for (int64_t J : finished) {
+          const double g = rl_gain_us(J);
+          if (g > 0) {
+            via_u.push_back(J);
+            saved += g;
+          } else {
+            keep.push_back(J);
+          }
+        }
+        if (saved > s.opt.hybrid_step_us)
+          finished.swap(keep);
+        else
+          via_u.clear();
       }
       if (!via_u.empty()) {
         // RL (Algorithm 4): for every supernode J whose cdiv ends at this

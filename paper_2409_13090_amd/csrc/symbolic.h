@@ -26,6 +26,7 @@ struct AnalyzeOptions {
                            // there are at least this many (<= 0: never)
   int method = 0;          // 0: RLB (Algorithm 5); 1: RL (Algorithm 4), the updates of a
                            // supernode into its ancestors through an update matrix
+  double hybrid_step_us = 30.0;  // hybrid method: least modelled saving of a step (us)
   int tile_order = 0;      // 0: heaviest tiles first; 1: 8x8 blocks of neighbouring
                            // tiles, a contiguous eighth of the order per XCD
 };

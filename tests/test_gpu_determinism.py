@@ -156,7 +156,9 @@ def test_update_matrix_assembly_is_bitwise_repeatable(method):
     bits, in eager launches and graph replays."""
     import torch
     A = W.small_grid("27pt", (18, 18, 18), seed=62, lo=0.1, hi=1.0, shift=1e-4)
-    s = rlb.Symbolic.from_matrix(A, method=method)
+    s = rlb.Symbolic.from_matrix(A, method=method,
+                                 **({"hybrid_step_us": -1} if method == "hybrid" else {}))
+    assert (s.array("launches").reshape(-1, 12)[:, 0] == 2).sum() >= 1
     num = rlb.Numeric(s)
     vals = torch.from_numpy(A.values).cuda()
     assert num.factor(vals) == 0

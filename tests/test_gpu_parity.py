@@ -399,7 +399,9 @@ def test_rl_method_matches_oracle(name, make, method):
     in place; the same factor as the oracle's."""
     A = make()
     o, f = oracle_factor(A)
-    s, num, vals, info = gpu_factor(A, method=method)
+    # hybrid: no least saving per step, so that these small matrices take both routes
+    s, num, vals, info = gpu_factor(A, method=method,
+                                    **({"hybrid_step_us": -1} if method == "hybrid" else {}))
     assert info == 0
     assert s.info()["u_bytes"] > 0
     L = s.array("launches").reshape(-1, 12)
@@ -418,8 +420,12 @@ def test_irregular_graph_ordering_matches_oracle(n, method):
     the same ordering on its own."""
     A = W.irregular3d(n, k=10, seed=40 + n % 7)
     o, f = oracle_factor(A, ordering="graph")
-    s, num, vals, info = gpu_factor(A, ordering="graph", method=method)
+    s, num, vals, info = gpu_factor(A, ordering="graph", method=method,
+                                    **({"hybrid_step_us": -1} if method == "hybrid" else {}))
     assert info == 0
+    if method == "hybrid":
+        L = s.array("launches").reshape(-1, 12)
+        assert (L[:, 0] == 2).sum() >= 1
     if method == "rlb":
         # most update launches take the K chunks shaped to small rectangles
         L = s.array("launches").reshape(-1, 12)

@@ -291,6 +291,12 @@ CASES = [
     ("rl_lap3d27_13", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
                                            shift=1e-4), {"method": "rl"}),
     ("rl_lap2d9_45x38", lambda: W.small_grid("9pt", (45, 38, 1), seed=21), {"method": "rl"}),
+    # hybrid: RL's update matrices for some supernodes, in-place updates for the rest
+    ("hybrid_lap3d27_13", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                               shift=1e-4),
+     {"method": "hybrid", "hybrid_step_us": -1}),
+    ("hybrid_irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"method": "hybrid", "hybrid_step_us": -1, "ordering": "graph"}),
     # several wide supernodes in one level, outer blocks of 64 columns
     ("lap3d27_16_outer64", lambda: W.small_grid("27pt", (16, 16, 16), seed=27, lo=0.1, hi=1.0,
                                                 shift=1e-4),
@@ -306,7 +312,7 @@ CASES = [
 def test_work_lists_replayed_match_oracle(name, make, kw):
     A = make()
     s, Lb = replay_factor(A, **kw)
-    o, f = oracle_factor(A)
+    o, f = oracle_factor(A, **({"ordering": kw["ordering"]} if "ordering" in kw else {}))
     err = compare_factor(export(s, Lb), f, A.n)
     assert err <= 1e-12
     # the unfused form (the batch's) reaches the same factor

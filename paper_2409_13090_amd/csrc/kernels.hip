@@ -444,10 +444,21 @@ __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, in
   for (int j = 0; j < 16; ++j) v[j] = T[lr * tp + o + j];
   double dg = 1.0;  // the pivot of this lane's row, for its diagonal entry
   double dn = lane_bcast(v[0], o);  // the next pivot, before any patching
+  // Column c's update of the columns j >= c + 2 needs the multipliers of rows
+  // o + j (through LDS); it is applied one pivot later, its LDS reads issued
+  // before that pivot's square root, so the LDS round trip overlaps the
+  // pivot chain. Every entry still takes the updates in pivot order, with the
+  // same operands.
+  double lp = 0.0;  // the previous column's multiplier of this lane's row
+  double r[16];     // the previous column's multipliers of rows o + j
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     // NC < 16 (callers with nb <= o + NC): columns from nb on are the
     // identity with zeros below, they change nothing and are not visited
+    if (c >= 1) {
+#pragma unroll
+      for (int j = c + 1; j < 16; ++j) r[j] = Lc[(c - 1) * 64 + o + j];
+    }
     double d = dn;
     if (FIX) {
       if (d <= lane_bcast(thr, o + c) && o + c < nb) {
@@ -461,16 +472,25 @@ __device__ __forceinline__ int panel16(double* T, int tp, int tr, double* Lc, in
     y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
     const double l = v[c] * y;
     v[c] = l;
+    if (c >= 1 && c < 15) v[c + 1] = fma(-lp, r[c + 1], v[c + 1]);
     if (c < 15) {
       // the pivot row's own entries give the next pivot without waiting for
       // the broadcast of its multiplier
       dn = lane_bcast(fma(-l, l, v[c + 1]), o + c + 1);
+    }
+    if (c >= 1) {
+#pragma unroll
+      for (int j = c + 2; j < 16; ++j) v[j] = fma(-lp, r[j], v[j]);
+    }
+    if (c < 15) {
       Lc[c * 64 + lane] = l;
       v[c + 1] = fma(-l, lane_bcast(l, o + c + 1), v[c + 1]);
-#pragma unroll
-      for (int j = c + 2; j < 16; ++j) v[j] = fma(-l, Lc[c * 64 + o + j], v[j]);
     }
+    lp = l;
   }
+  // the last column's update of the columns past it (NC < 16)
+#pragma unroll
+  for (int j = NC + 1; j < 16; ++j) v[j] = fma(-lp, Lc[(NC - 1) * 64 + o + j], v[j]);
   const double sq = sqrt(dg);
   // rows from the diagonal block down; the rows above it lie in the tile's
   // unused upper part, which may hold other data (the 16x16 inverses)

@@ -1800,45 +1800,66 @@ __device__ __forceinline__ void update_w_tile(const UpdTile& t, const UpdSeg* __
   v4d acc[NBI];
 #pragma unroll
   for (int bi = 0; bi < NBI; ++bi) acc[bi] = v4d{0, 0, 0, 0};
-  UpdSeg gn = segs[t.seg0];
-  for (int e = 0; e < t.nseg; ++e) {
-    const UpdSeg g = gn;
-    if (e + 1 < t.nseg) gn = segs[t.seg0 + e + 1];  // the next record, read ahead
-    const bool yin = il >= g.ca && il < g.cb;
+  // K in steps of 8 (two 4-deep MFMA steps) over the contributions in order;
+  // the loads of a step are issued before the products of the one before
+  // (two register sets), so a tile of many short contributions waits for
+  // memory about once instead of once per contribution
+  constexpr int KW = 8, NQW = KW / 4;
+  double ya[2][NQW], xb[2][NQW][NBI];
+  bool yin[2], xin[2][NBI];
+  int kv[2], nq[2];
+  int e = 0, k0 = 0;  // load cursor
+  UpdSeg g = uniform_seg(segs[t.seg0]);
+  auto load = [&](const int st) {
+    yin[st] = il >= g.ca && il < g.cb;
     const int64_t yo = g.y + min(max(il - g.ca, 0), g.cb - g.ca - 1);
-    bool xin[NBI];
     int64_t xo[NBI];
 #pragma unroll
     for (int bi = 0; bi < NBI; ++bi) {
       const int r = 16 * bi + il;
-      xin[bi] = r >= g.ra && r < g.rb;
+      xin[st][bi] = r >= g.ra && r < g.rb;
       xo[bi] = g.x + min(max(r - g.ra, 0), g.rb - g.ra - 1);
     }
-#pragma unroll 1
-    for (int k0 = 0; k0 < g.k; k0 += 16) {
-      // all loads of the 16-deep chunk in flight before its products; the
-      // 4-deep steps past the contribution's k (uniform) are skipped
-      const int nq = min(4, (g.k - k0 + 3) >> 2);
-      double ya[4], xb[4][NBI];
+    kv[st] = g.k - k0;
+    nq[st] = min(NQW, (g.k - k0 + 3) >> 2);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < nq) {
-          const int64_t kc = min(k0 + 4 * q + kl, g.k - 1);
-          ya[q] = L[yo + kc * g.lds];
+    for (int q = 0; q < NQW; ++q) {
+      if (q < nq[st]) {
+        const int64_t kc = min(k0 + 4 * q + kl, g.k - 1);
+        ya[st][q] = L[yo + kc * g.lds];
 #pragma unroll
-          for (int bi = 0; bi < NBI; ++bi) xb[q][bi] = L[xo[bi] + kc * g.lds];
-        }
+        for (int bi = 0; bi < NBI; ++bi) xb[st][q][bi] = L[xo[bi] + kc * g.lds];
       }
+    }
+    k0 += KW;
+    if (k0 >= g.k) {
+      k0 = 0;
+      if (++e < t.nseg) g = uniform_seg(segs[t.seg0 + e]);
+    }
+  };
+  auto compute = [&](const int st) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < nq) {
-          const bool kin = k0 + 4 * q + kl < g.k;
-          const double a = (kin && yin) ? ya[q] : 0.0;
+    for (int q = 0; q < NQW; ++q) {
+      if (q < nq[st]) {
+        const bool kin = 4 * q + kl < kv[st];
+        const double a = (kin && yin[st]) ? ya[st][q] : 0.0;
 #pragma unroll
-          for (int bi = 0; bi < NBI; ++bi)
-            acc[bi] = mfma64(a, (kin && xin[bi]) ? xb[q][bi] : 0.0, acc[bi]);
-        }
+        for (int bi = 0; bi < NBI; ++bi)
+          acc[bi] = mfma64(a, (kin && xin[st][bi]) ? xb[st][q][bi] : 0.0, acc[bi]);
       }
+    }
+  };
+  if (t.nseg > 0) {
+    load(0);
+    for (;;) {
+      const bool m1 = e < t.nseg;
+      if (m1) load(1);
+      compute(0);
+      if (!m1) break;
+      const bool m0 = e < t.nseg;
+      if (m0) load(0);
+      compute(1);
+      if (!m0) break;
     }
   }
   // acc[bi][v] is the update of target row 16*bi + il, column 4*v + kl

@@ -400,6 +400,7 @@ ABLATIONS = [
     ("outer_block_512", {"outer_block": 512}),
     ("atomic_split", {"deterministic": False}),
     ("big_tiles_128", {"big_tile_min": 256}),
+    ("tall_tiles_128x64", {"tall_tile_min": 256}),
     ("method_rl", {"method": "rl"}),
     ("method_hybrid", {"method": "hybrid"}),
     ("tile_order_xcd", {"tile_order": "xcd"}),

@@ -105,6 +105,11 @@ typedef struct rlb_options {
                                blocks of neighbouring tiles of each target supernode, and
                                each XCD takes a contiguous eighth of that order, so the
                                tiles running on one XCD (one L2) share their source rows */
+  int32_t tall_tile_min;    /* the long updates of a step (updates into ancestors, and the
+                               trailing update after an outer block) take 128x64 target
+                               tiles in the FP64 form when there are at least this many;
+                               <= 0: never (the other forms run the same work in 64x64
+                               tiles) */
   double hybrid_step_us;    /* RLB_METHOD_HYBRID: the time (microseconds, by the planner's
                                model) the update-matrix route must save in a step to be
                                taken there; 0 (default): 30, about the step's two extra

@@ -421,6 +421,7 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     ao.method = opt->method;
     if (opt->tile_order < 0 || opt->tile_order > 1) return fail(RLB_ERR_ARG, "bad tile_order");
     ao.tile_order = opt->tile_order;
+    ao.tall_tile_min = opt->tall_tile_min;
     if (!(opt->hybrid_step_us == opt->hybrid_step_us)) return fail(RLB_ERR_ARG, "bad hybrid_step_us");
     ao.hybrid_step_us = opt->hybrid_step_us == 0 ? 30.0 : std::max(0.0, opt->hybrid_step_us);
   } else {
@@ -630,9 +631,10 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
     if (l.kind == LAUNCH_ASSEMBLE) {
       launch_assemble(h->d.asmcols + l.start, l.count, h->d.asm_rows, L, ls);
     } else if (l.kind == LAUNCH_UPDATE) {
-      if (l.variant == UPD_BIG && h->precision >= RLB_PREC_BF16_UPDATES)
+      if ((l.variant == UPD_BIG && h->precision >= RLB_PREC_BF16_UPDATES) ||
+          (l.variant == UPD_TALL && h->precision != RLB_PREC_FP64))
         launch_update(h->d.updates + l.alt_start, h->d.segs, l.alt_count, L, h->precision,
-                      h->smax, UPD_TILE, ls, 0);
+                      h->smax, UPD_TILE, ls, 0, h->Ls);
       else
         launch_update(h->d.updates + l.start, h->d.segs, l.count, L, h->precision, h->smax,
                       l.variant, ls, l.nwave, h->Ls);
@@ -1112,7 +1114,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
           UpdTile ut = p.updates[l.start + t];
           ut.c += b->base[i];
           ut.seg0 += (int32_t)segbase[i];
-          if (ut.n <= NARROW_COLS && bv != UPD_BIG)
+          if (ut.n <= NARROW_COLS && bv != UPD_BIG && bv != UPD_TALL)
             narrow.push_back(ut);
           else
             b->updates.push_back(ut);

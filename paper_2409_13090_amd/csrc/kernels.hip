@@ -1339,6 +1339,147 @@ __global__ __launch_bounds__(256, 4) void k_update(const UpdTile* __restrict__ t
 
 template __global__ void k_update<double>(const UpdTile*, const UpdSeg*, double*, const double*,
                                           int, int);
+
+// k_update on target tiles of up to 128 rows and 64 columns (the long
+// updates of the upper levels): eight wavefronts, wavefront w holding the
+// 32x32 quarter at rows 32 (w & 3), columns 32 (w >> 2); each K chunk stages
+// 128 rows of X and 64 of Y, 1.5 times the bytes of a 64x64 tile's chunk for
+// twice its products. X row (w & 1) * 64 + lane of k (w >> 1) + 4q and Y row
+// lane of k w + 8q are one wavefront's loads; FP64, range-checked buffer
+// loads as in k_update.
+__global__ __launch_bounds__(512, 2) void k_update_tall(const UpdTile* __restrict__ tiles,
+                                                        const UpdSeg* __restrict__ segs,
+                                                        double* __restrict__ L) {
+  constexpr int KC = 16, NQX = 4, NQY = 2;
+  const UpdTile t = tiles[blockIdx.x];
+  __shared__ double sX[2][KC][128];
+  __shared__ double sY[2][KC][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = (wave & 3) * 32, wc = (wave >> 2) * 32;
+  const int xrow = (wave & 1) * 64 + lane, xk = wave >> 1;
+  double* __restrict__ C = L + t.c;
+  const int64_t ldc = t.ldc;
+  const bool diag = t.flags & 1;
+  const bool atomic = t.flags & 2;
+  auto seg_at = [&](int i) { return uniform_seg(segs[t.seg0 + i]); };
+
+  double xr[2][NQX], yr[2][NQY];
+  int fe = 0, fk = 0;  // fetch cursor
+  UpdSeg gf = seg_at(0);
+  auto fetch = [&](int set) {
+    const uint32_t xoff = (uint32_t)(xrow - gf.ra) << 3, yoff = (uint32_t)(lane - gf.ca) << 3;
+    const int xrec = (gf.rb - gf.ra) << 3, yrec = (gf.cb - gf.ca) << 3;
+#pragma unroll
+    for (int q = 0; q < NQX; ++q) {
+      const int kk = fk + xk + 4 * q;
+      xr[set][q] = load_range(L + gf.x + (int64_t)kk * gf.lds, kk < gf.k ? xrec : 0, xoff);
+    }
+#pragma unroll
+    for (int q = 0; q < NQY; ++q) {
+      const int kk = fk + wave + 8 * q;
+      yr[set][q] = load_range(L + gf.y + (int64_t)kk * gf.lds, kk < gf.k ? yrec : 0, yoff);
+    }
+    fk += KC;
+    if (fk >= gf.k) {
+      fk = 0;
+      if (++fe < t.nseg) gf = seg_at(fe);
+    }
+  };
+  auto stash = [&](int set, int buf) {
+#pragma unroll
+    for (int q = 0; q < NQX; ++q) sX[buf][xk + 4 * q][xrow] = xr[set][q];
+#pragma unroll
+    for (int q = 0; q < NQY; ++q) sY[buf][wave + 8 * q][lane] = yr[set][q];
+  };
+  // chunks 0 and 1 in flight first, then the target values
+  fetch(0);
+  if (fe < t.nseg) fetch(1);
+  const unsigned cover = cover_bits<Mfma<double>>(t, segs, wr, wc, lane);
+  double cv[2][2][4] = {};
+  if (!atomic) {
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(wr + 16 * bi + (lane & 15), t.m - 1);
+          const int col = min(wc + 16 * bj + Mfma<double>::drow(lane, v), t.n - 1);
+          if ((cover >> (bj * 8 + bi * 4 + v)) & 1u) cv[bj][bi][v] = C[(int64_t)col * ldc + row];
+        }
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  stash(0, 0);
+  if (fe < t.nseg) fetch(0);  // chunk 2
+  __syncthreads();
+
+  int e = 0, k0 = 0;  // compute cursor
+  UpdSeg g = seg_at(0);
+  auto multiply = [&](int buf) {
+    bool use[2][2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        use[bj][bi] = wr + 16 * bi < g.rb && wr + 16 * bi + 16 > g.ra &&
+                      wc + 16 * bj < g.cb && wc + 16 * bj + 16 > g.ca;
+    if (use[0][0] || use[0][1] || use[1][0] || use[1][1]) {
+      const bool all4 = use[0][0] && use[0][1] && use[1][0] && use[1][1];
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        const int kk = kq * 4 + (lane >> 4);
+        const double a0 = sY[buf][kk][wc + (lane & 15)];
+        const double a1 = sY[buf][kk][wc + 16 + (lane & 15)];
+        const double b0 = sX[buf][kk][wr + (lane & 15)];
+        const double b1 = sX[buf][kk][wr + 16 + (lane & 15)];
+        if (all4 || use[0][0]) acc[0][0] = mfma64(a0, b0, acc[0][0]);
+        if (all4 || use[0][1]) acc[0][1] = mfma64(a0, b1, acc[0][1]);
+        if (all4 || use[1][0]) acc[1][0] = mfma64(a1, b0, acc[1][0]);
+        if (all4 || use[1][1]) acc[1][1] = mfma64(a1, b1, acc[1][1]);
+      }
+    }
+    k0 += KC;
+    if (k0 >= g.k) {
+      k0 = 0;
+      if (++e < t.nseg) g = seg_at(e);
+    }
+  };
+  // chunk i (even) is in LDS buffer 0, its successor in register set 1
+  for (;;) {
+    multiply(0);
+    if (e >= t.nseg) break;
+    stash(1, 1);
+    if (fe < t.nseg) fetch(1);
+    __syncthreads();
+    multiply(1);
+    if (e >= t.nseg) break;
+    stash(0, 0);
+    if (fe < t.nseg) fetch(0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + 16 * bi + (lane & 15);
+        const int col = wc + 16 * bj + Mfma<double>::drow(lane, v);
+        if (((cover >> (bj * 8 + bi * 4 + v)) & 1u) && row < t.m && col < t.n &&
+            (!diag || row >= col)) {
+          double* p = C + (int64_t)col * ldc + row;
+          if (atomic)
+            atomicAdd(p, -acc[bj][bi][v]);
+          else
+            *p = cv[bj][bi][v] - acc[bj][bi][v];
+        }
+      }
+}
 template __global__ void k_update<float>(const UpdTile*, const UpdSeg*, double*, const float*,
                                          int, int);
 
@@ -2988,6 +3129,12 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
                    int precision, const unsigned long long* smax, int variant, hipStream_t st,
                    int64_t nwave, const float* Ls, int64_t wave_min) {
   if (count <= 0) return;
+  if (variant == UPD_TALL) {
+    // 128x64 target tiles, FP64 (the other forms run the same work from its
+    // 64x64 tiling)
+    hipLaunchKernelGGL(k_update_tall, dim3((unsigned)count), dim3(512), 0, st, tiles, segs, L);
+    return;
+  }
   if (variant == UPD_BIG) {
     // 128x128 target tiles: FP64 or FP32 operands (the 16-bit forms run the
     // same work from its 64x64 tiling)

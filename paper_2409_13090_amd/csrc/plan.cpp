@@ -143,6 +143,8 @@ int build_plan(Symbolic& s, std::string& err) {
   const int64_t NBO = s.opt.outer_block;
   const int64_t MIN_BIG_TILES =
       s.opt.big_tile_min > 0 ? s.opt.big_tile_min : std::numeric_limits<int64_t>::max();
+  const int64_t MIN_TALL_TILES =
+      s.opt.tall_tile_min > 0 ? s.opt.tall_tile_min : std::numeric_limits<int64_t>::max();
   const int64_t n = s.n;
   const int64_t S = (int64_t)s.sn_ptr.size() - 1;
   auto W = [&](int64_t J) { return s.sn_ptr[J + 1] - s.sn_ptr[J]; };
@@ -722,7 +724,10 @@ int build_plan(Symbolic& s, std::string& err) {
         double exec = 0, alg_total = 0;
         int64_t merged = 0, split = 0, whole = 0;
       };
-      auto build_long = [&](int64_t T) {
+      // (target tiles of TR rows and TC columns; in column block TJ of a
+      // target the row tiles start at its diagonal row TJ * TC, so the first
+      // holds the diagonal block and the rows below it)
+      auto build_long = [&](int64_t TR, int64_t TC) {
         LongPart lp;
         auto put = [&](UpdTile t, const std::vector<UpdSeg>& gs) {
           const bool diag = (t.flags & FLAG_DIAG) != 0;
@@ -784,10 +789,10 @@ int build_plan(Symbolic& s, std::string& err) {
         // forms), tiles anchored at the first column right of the block
         for (const Outer& o : outer) {
           const int64_t J = o.J, w = W(J), m = M(J);
-          for (int64_t tj0 = o.c1; tj0 < w; tj0 += T) {
-            const int64_t tn = std::min<int64_t>(T, w - tj0);
-            for (int64_t ti0 = tj0; ti0 < m; ti0 += T) {
-              const int64_t tm = std::min<int64_t>(T, m - ti0);
+          for (int64_t tj0 = o.c1; tj0 < w; tj0 += TC) {
+            const int64_t tn = std::min<int64_t>(TC, w - tj0);
+            for (int64_t ti0 = tj0; ti0 < m; ti0 += TR) {
+              const int64_t tm = std::min<int64_t>(TR, m - ti0);
               UpdTile t;
               t.c = p.off[J] + tj0 * m + ti0;
               t.ldc = (int32_t)m;
@@ -822,36 +827,40 @@ int build_plan(Symbolic& s, std::string& err) {
           int64_t mJ = M(J), wJ = W(J);
           for (const Rect& r : rects[J]) {
             int64_t mP = M(r.P), wP = W(r.P);
-            for (int64_t TJ = r.c0 / T; TJ * T < r.c0 + r.nc; ++TJ)
-              for (int64_t TI = std::max(TJ, r.r0 / T); TI * T < r.r0 + r.mr; ++TI) {
-                int64_t rlo = std::max(r.r0, TI * T), rhi = std::min({r.r0 + r.mr, TI * T + T, mP});
-                int64_t clo = std::max(r.c0, TJ * T), chi = std::min({r.c0 + r.nc, TJ * T + T, wP});
+            for (int64_t TJ = r.c0 / TC; TJ * TC < r.c0 + r.nc; ++TJ) {
+              const int64_t cs = TJ * TC;
+              for (int64_t TI = r.r0 > cs ? (r.r0 - cs) / TR : 0; cs + TI * TR < r.r0 + r.mr; ++TI) {
+                const int64_t rs = cs + TI * TR;
+                int64_t rlo = std::max(r.r0, rs), rhi = std::min({r.r0 + r.mr, rs + TR, mP});
+                int64_t clo = std::max(r.c0, cs), chi = std::min({r.c0 + r.nc, cs + TC, wP});
                 if (rlo >= rhi || clo >= chi) continue;
-                if (TI == TJ && rhi - 1 < clo) continue;  // entirely above the diagonal
+                if (TI == 0 && rhi - 1 < clo) continue;  // entirely above the diagonal
                 UpdSeg g;
                 g.x = p.off[J] + r.sx + (rlo - r.r0);
                 g.y = p.off[J] + r.sy + (clo - r.c0);
                 g.lds = (int32_t)mJ;
                 g.k = (int32_t)wJ;
-                g.ra = (int32_t)(rlo - TI * T);
-                g.rb = (int32_t)(rhi - TI * T);
-                g.ca = (int32_t)(clo - TJ * T);
-                g.cb = (int32_t)(chi - TJ * T);
+                g.ra = (int32_t)(rlo - rs);
+                g.rb = (int32_t)(rhi - rs);
+                g.ca = (int32_t)(clo - cs);
+                g.cb = (int32_t)(chi - cs);
                 g.src = (int32_t)J;
                 g.sslot = anc_slot(J);
                 by_tile[std::make_tuple(r.P, TJ, TI)].push_back(g);
               }
+            }
           }
         }
         for (auto& kv : by_tile) {
           int64_t P = std::get<0>(kv.first), TJ = std::get<1>(kv.first), TI = std::get<2>(kv.first);
           int64_t mP = M(P), wP = W(P);
           UpdTile t;
-          t.c = p.off[P] + TJ * T * mP + TI * T;
+          const int64_t cs = TJ * TC, rs = cs + TI * TR;
+          t.c = p.off[P] + cs * mP + rs;
           t.ldc = (int32_t)mP;
-          t.m = (int32_t)std::min<int64_t>(T, mP - TI * T);
-          t.n = (int32_t)std::min<int64_t>(T, wP - TJ * T);
-          t.flags = TI == TJ ? FLAG_DIAG : 0;
+          t.m = (int32_t)std::min<int64_t>(TR, mP - rs);
+          t.n = (int32_t)std::min<int64_t>(TC, wP - cs);
+          t.flags = TI == 0 ? FLAG_DIAG : 0;
           t.seg0 = t.nseg = 0;
           if (kv.second.size() > 1) lp.merged++;
           put(t, kv.second);
@@ -883,9 +892,9 @@ int build_plan(Symbolic& s, std::string& err) {
         }
         return start;
       };
-      LongPart lp = build_long(BIG);
+      LongPart lp = build_long(BIG, BIG);
       if (lp.whole >= MIN_BIG_TILES) {
-        LongPart alt = build_long(TM);
+        LongPart alt = build_long(TM, TN);
         Launch lb{LAUNCH_UPDATE, h, (int32_t)k, UPD_BIG, place(lp), (int64_t)lp.tiles.size(),
                   0, 0, 0, 0, 0};
         lb.alt_start = place(alt);
@@ -897,15 +906,33 @@ int build_plan(Symbolic& s, std::string& err) {
         p.n_merged_tiles += lp.merged;
         p.n_split_tiles += lp.split;
       } else {
-        LongPart sp = build_long(TM);
-        for (size_t i = 0; i < sp.tiles.size(); ++i) {
-          const UpdTile& t = sp.tiles[i];
-          add_tile(t, sp.segs, t.seg0, t.seg0 + t.nseg, false);
+        // 128x64 target tiles for a long part of enough of them (the same work
+        // in 64x64 tiles kept for the forms other than FP64)
+        LongPart tp;
+        if (MIN_TALL_TILES < std::numeric_limits<int64_t>::max()) tp = build_long(2 * TM, TN);
+        if (tp.whole >= MIN_TALL_TILES) {
+          LongPart alt = build_long(TM, TN);
+          Launch lt{LAUNCH_UPDATE, h, (int32_t)k, UPD_TALL, place(tp), (int64_t)tp.tiles.size(),
+                    0, 0, 0, 0, 0};
+          lt.alt_start = place(alt);
+          lt.alt_count = (int64_t)alt.tiles.size();
+          p.launches.push_back(lt);
+          p.flops_tiles += tp.exec;
+          p.flops_upd_alg += tp.alg_total;
+          p.flops_upd_launch += tp.alg_total;
+          p.n_merged_tiles += tp.merged;
+          p.n_split_tiles += tp.split;
+        } else {
+          LongPart sp = build_long(TM, TN);
+          for (size_t i = 0; i < sp.tiles.size(); ++i) {
+            const UpdTile& t = sp.tiles[i];
+            add_tile(t, sp.segs, t.seg0, t.seg0 + t.nseg, false);
+          }
+          p.flops_tiles += sp.exec;
+          p.flops_upd_alg += sp.alg_total;
+          p.n_merged_tiles += sp.merged;
+          p.n_split_tiles += sp.split;
         }
-        p.flops_tiles += sp.exec;
-        p.flops_upd_alg += sp.alg_total;
-        p.n_merged_tiles += sp.merged;
-        p.n_split_tiles += sp.split;
       }
     }
     if (pend.valid) commit(pend, -1);

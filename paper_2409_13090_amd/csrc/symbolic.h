@@ -27,6 +27,8 @@ struct AnalyzeOptions {
   int method = 0;          // 0: RLB (Algorithm 5); 1: RL (Algorithm 4), the updates of a
                            // supernode into its ancestors through an update matrix
   double hybrid_step_us = 30.0;  // hybrid method: least modelled saving of a step (us)
+  int tall_tile_min = 0;   // the long updates of a step take 128x64 target tiles (FP64)
+                           // when there are at least this many (<= 0: never)
   int tile_order = 0;      // 0: heaviest tiles first; 1: 8x8 blocks of neighbouring
                            // tiles, a contiguous eighth of the order per XCD
 };
@@ -158,6 +160,8 @@ constexpr int32_t UPD_SHORT = 1;
 constexpr int32_t UPD_BIG = 2;
 constexpr int32_t UPD_TILE_WIN = 4;  // UPD_TILE with K chunks shaped to the contributions'
                                      // rectangles (tiles of many small contributions)
+constexpr int32_t UPD_TALL = 6;  // 128x64 target tiles (the long updates), FP64; the
+                                 // launch's alt list holds the same work in 64x64 tiles
 constexpr int32_t UPD_TILE_PACK = 5;  // UPD_TILE with the contributions of a tile end to end
                                       // along K (tiles of many contributions of small k)
 constexpr int32_t UPD_TILE_XCD = 3;  // UPD_TILE, workgroup b takes the tile at position

@@ -449,3 +449,35 @@ def test_xcd_tile_order_matches_oracle():
     err = compare_factor(num.export(), f, A.n)
     print(f"[case] lap3d7_30 xcd order rel_err={err:.3e}", flush=True)
     solve_check(num, A)
+
+
+@pytest.mark.parametrize("name,make,kw", [
+    ("lap3d27_13_outer128", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                                 shift=1e-4), {"outer_block": 128}),
+    ("lap3d7_23x19x15", lambda: W.small_grid("7pt", (23, 19, 15), seed=23), {}),
+    ("irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40), {"ordering": "graph"}),
+])
+def test_tall_target_tiles_match_oracle(name, make, kw):
+    """The long updates on 128x64 target tiles (eight wavefronts, 128 rows of X
+    and 64 of Y staged per K chunk): the same factor as the oracle's; the FP32
+    form runs the same work from its 64x64 tiling and refines to 1e-14."""
+    A = make()
+    o, f = oracle_factor(A, **({"ordering": kw["ordering"]} if "ordering" in kw else {}))
+    s, num, vals, info = gpu_factor(A, tall_tile_min=1, **kw)
+    assert info == 0
+    L = s.array("launches").reshape(-1, 12)
+    assert ((L[:, 0] == 1) & (L[:, 5] == 6)).sum() >= 1
+    err = compare_factor(num.export(), f, A.n)
+    print(f"[case] tall {name} rel_err={err:.3e}", flush=True)
+    if A.rhs is not None:
+        solve_check(num, A)
+    s32, num32, vals32, info32 = gpu_factor(A, precision=rlb.RLB_PREC_FP32_UPDATES,
+                                            tall_tile_min=1, **kw)
+    assert info32 == 0
+    torch = _torch()
+    rhs = A.rhs if A.rhs is not None else np.ones((A.n, 1))
+    B = torch.from_numpy(np.asfortranarray(rhs)).cuda().T.contiguous().T
+    X = torch.zeros_like(B).T.contiguous().T
+    rep = num32.refine(B, X, tol=1e-14, max_iter=30)
+    assert rep["converged"], rep
+    assert max(rep["backward_error"]) <= 1e-14

@@ -40,12 +40,12 @@ def unfused(launches):
 
 
 def with_alt(launches):
-    """Launches of 128x128 target tiles replaced by the same work in 64x64
-    tiles, as the 16-bit update forms run them."""
+    """Launches of 128x128 or 128x64 target tiles replaced by the same work in
+    64x64 tiles, as the reduced-precision update forms run them."""
     out = []
     for l in launches:
         l = [int(v) for v in l]
-        if l[0] == 1 and l[5] == 2:
+        if l[0] == 1 and l[5] in (2, 6):
             assert l[11] > 0
             l[3], l[4], l[5] = l[10], l[11], 0
         out.append(tuple(l))
@@ -156,8 +156,9 @@ def replay_factor(A, expand=False, alt=False, **kw):
                            for i in range(ust, ust + ucnt))
         else:
             tiles = U[st:st + cnt]
-            side = 128 if variant == 2 else 64
-            assert all(m <= side and n <= side for _, _, m, n, _, _, _ in tiles)
+            rows = 128 if variant in (2, 6) else 64
+            cols = 128 if variant == 2 else 64
+            assert all(m <= rows and n <= cols for _, _, m, n, _, _, _ in tiles)
             updates(tiles)
     for diag, ld, nb in s.array("diag_tiles").reshape(-1, 3):
         Lt = np.array([[Lb[diag + j * ld + i] if i >= j else 0.0 for j in range(nb)]
@@ -297,6 +298,14 @@ CASES = [
      {"method": "hybrid", "hybrid_step_us": -1}),
     ("hybrid_irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40),
      {"method": "hybrid", "hybrid_step_us": -1, "ordering": "graph"}),
+    # 128x64 target tiles for the long updates (outer blocks and ancestors)
+    ("lap3d27_13_outer128_tall", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1,
+                                                      hi=1.0, shift=1e-4),
+     {"outer_block": 128, "tall_tile_min": 1}),
+    ("lap3d7_17_tall", lambda: W.small_grid("7pt", (17, 17, 17), seed=22, shift=1e-4),
+     {"tall_tile_min": 1}),
+    ("irregular_3000_tall", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"tall_tile_min": 1, "ordering": "graph"}),
     # several wide supernodes in one level, outer blocks of 64 columns
     ("lap3d27_16_outer64", lambda: W.small_grid("27pt", (16, 16, 16), seed=27, lo=0.1, hi=1.0,
                                                 shift=1e-4),
@@ -319,6 +328,11 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     s2, Lb2 = replay_factor(A, expand=True, **kw)
     assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
     L12 = s.array("launches").reshape(-1, 12)
+    if kw.get("tall_tile_min") == 1:
+        # the long parts went to 128x64 tiles; their 64x64 form (FP32, 16-bit) too
+        assert np.any((L12[:, 0] == 1) & (L12[:, 5] == 6))
+        s5, Lb5 = replay_factor(A, alt=True, **kw)
+        assert compare_factor(export(s5, Lb5), f, A.n) <= 1e-12
     if kw.get("big_tile_min") == 1:
         # the long parts went to 128x128 tiles; their 64x64 form (16-bit) too
         assert np.any((L12[:, 0] == 1) & (L12[:, 5] == 2))

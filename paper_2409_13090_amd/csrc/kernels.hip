@@ -764,11 +764,16 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     __syncthreads();
   }
   // row-tile work of the previous block's update: 2x2 groups of 16x16 blocks,
-  // g = (row blocks 2(g&1).., column blocks 2(g>>1)..); waves 1 and 2 take one
-  // each per pivot round from the second round on, the rest after the rounds
-  // (a 16-column tile image holds one column block)
+  // g = (row blocks 2(g&1).., column blocks 2(g>>1)..) for the later row
+  // tiles (a 16-column tile image holds one column block); for the first row
+  // tile halves of them, h = (row blocks 2(h&1).., column block h>>1), dealt
+  // to waves 1-3 in the pivot rounds from the second on (slot 3(r-1) + w - 1
+  // takes half h) so that no round's work outlasts its pivot chain, the rest
+  // after the rounds
   const int ngrp = (PRE && t.nrt > 0) ? 2 * ((nbb + 1) >> 1) : 0;
   auto grp = [&](int g) { pre_gemm2x2<(NBB > 1)>(sA, sX, sY, 2 * (g & 1), 2 * (g >> 1), lane); };
+  const int nhalf = (PRE && t.nrt > 0) ? 2 * nbb : 0;
+  auto half = [&](int h) { pre_gemm2x2<false>(sA, sX, sY, 2 * (h & 1), h >> 1, lane); };
   for (int r = 0; r < nbb; ++r) {
     if (wave == 0) {
       bad = min(bad, panel16<(MODE >= 1)>(T, TPn, TR, Lc, 16 * r, nb, t.col, lane, cthr, crep,
@@ -801,9 +806,9 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
           if (last) atomicExch(&counters[t.grp], 0);
           s_last = last;
         }
-      } else if (PRE && wave <= 2) {
-        const int g = 2 * (r - 1) + wave - 1;
-        if (g < ngrp) grp(g);
+      } else if (PRE) {
+        const int h = 3 * (r - 1) + wave - 1;
+        if (h < nhalf) half(h);
       }
     }
     __syncthreads();
@@ -811,10 +816,10 @@ __global__ __launch_bounds__(256, panel_occupancy(NBB, PRE)) void k_panel(
     if (r + 1 < nbb && r + 1 + wave < nbb) syrk16(T, TPn, r + 1 + wave, r + 1, r, lane);
     __syncthreads();
   }
-  if (PRE && 2 * (nbb - 1) < ngrp) {
-    // groups the rounds had no room for (single-round tiles)
-    if (wave == 1 || wave == 2)
-      for (int g = 2 * (nbb - 1) + wave - 1; g < ngrp; g += 2) grp(g);
+  if (PRE && 3 * (nbb - 1) < nhalf) {
+    // halves the rounds had no room for
+    if (wave >= 1)
+      for (int h = 3 * (nbb - 1) + wave - 1; h < nhalf; h += 3) half(h);
     __syncthreads();
   }
   // the last base inverse (wave 3) alongside the first column blocks of the

@@ -297,7 +297,8 @@ void rlb_numeric_free(rlb_numeric num);
 /* Batched form: factor many independent matrices with one merged level
  * schedule (level h of every matrix in the same launches).
  *   count           : number of matrices
- *   syms[count]     : (host) analysed patterns
+ *   syms[count]     : (host) analysed patterns, borrowed: each must outlive
+ *                     the batch (its schedules and solves read them)
  *   values[count]   : (host array of device pointers) FP64 values of each
  *   workspace       : (device) >= rlb_batch_bytes() bytes, caller-owned
  * rlb_batch_create builds the merged plan once; rlb_batch_factor runs it and

@@ -18,7 +18,9 @@
  *    diagonal present in every column, no duplicates. Values are FP64.
  *  - Host pointers are marked (host); device pointers (device). Device work is
  *    enqueued on the caller's HIP stream (a hipStream_t passed as void*); no
- *    call synchronizes except where stated.
+ *    call synchronizes except where stated. A device pointer may be NULL
+ *    when its buffer holds no element (n = 0, nrhs = 0 or no entries); the
+ *    matrix of order 0 goes through every call.
  *  - Handles are not thread-safe; one handle must not be used from two host
  *    threads at once.
  *  - Errors leave outputs unspecified; rlb_last_error() returns a message.

@@ -764,8 +764,9 @@ rlb_status rlb_factor_pivots_patched(rlb_numeric h, int64_t* count) {
 }
 
 rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* stream) {
-  if (!h || nrhs < 0 || (nrhs > 0 && !B)) return fail(RLB_ERR_ARG, "bad argument");
+  if (!h || nrhs < 0) return fail(RLB_ERR_ARG, "bad argument");
   const Symbolic& s = h->sym->s;
+  if (nrhs > 0 && s.n > 0 && !B) return fail(RLB_ERR_ARG, "null B");
   if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
   rlb_status e = require_factor(h);
   if (e) return e;
@@ -774,9 +775,10 @@ rlb_status rlb_solve(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* 
 }
 
 rlb_status rlb_solve_noalloc(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb, void* stream) {
-  if (!h || nrhs < 0 || nrhs > SOLVE_MAXRHS || (nrhs > 0 && !B))
+  if (!h || nrhs < 0 || nrhs > SOLVE_MAXRHS)
     return fail(RLB_ERR_ARG, "bad argument (0 <= nrhs <= 16)");
   const Symbolic& s = h->sym->s;
+  if (nrhs > 0 && s.n > 0 && !B) return fail(RLB_ERR_ARG, "null B");
   if (ldb < s.n) return fail(RLB_ERR_ARG, "ldb < n");
   if (s.n * nrhs > NOALLOC_SOLVE_ELEMS)
     return fail(RLB_ERR_ARG, "n * nrhs exceeds the allocation-free solve's capacity (2^21)");
@@ -804,8 +806,11 @@ rlb_status rlb_solve_noalloc(rlb_numeric h, int64_t nrhs, double* B, int64_t ldb
 
 rlb_status rlb_backward_error(rlb_numeric h, const double* values, int64_t nrhs, const double* B,
                               const double* X, int64_t ld, void* stream, double* out) {
-  if (!h || !values || !B || !X || !out || nrhs < 0) return fail(RLB_ERR_ARG, "bad argument");
+  if (!h || nrhs < 0 || (nrhs > 0 && !out)) return fail(RLB_ERR_ARG, "bad argument");
   const Symbolic& s = h->sym->s;
+  // (null buffers are accepted where they would hold no element)
+  if ((s.nnz_a > 0 && !values) || (nrhs > 0 && s.n > 0 && (!B || !X)))
+    return fail(RLB_ERR_ARG, "null values, B or X");
   if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
   // ||A||_inf is recomputed from `values` on every call (the caller may have
   // changed them in place since the last one)
@@ -822,9 +827,11 @@ rlb_status rlb_backward_error(rlb_numeric h, const double* values, int64_t nrhs,
 rlb_status rlb_refine(rlb_numeric h, const double* values, int64_t nrhs, const double* B,
                       double* X, int64_t ld, double tol, int32_t max_iter, void* stream,
                       rlb_refine_report* rep) {
-  if (!h || !values || !B || !X || nrhs < 1 || nrhs > SOLVE_MAXRHS || max_iter < 0)
+  if (!h || nrhs < 1 || nrhs > SOLVE_MAXRHS || max_iter < 0)
     return fail(RLB_ERR_ARG, "bad argument (1 <= nrhs <= 16)");
   const Symbolic& s = h->sym->s;
+  if ((s.nnz_a > 0 && !values) || (s.n > 0 && (!B || !X)))
+    return fail(RLB_ERR_ARG, "null values, B or X");
   if (ld < s.n) return fail(RLB_ERR_ARG, "ld < n");
   rlb_status e = require_factor(h);
   if (e) return e;
@@ -945,7 +952,8 @@ rlb_status rlb_factor_export(rlb_numeric h, int64_t* colptr, int64_t* rowidx, do
   const Symbolic& s = h->sym->s;
   std::vector<double> hl(s.plan.l_elems);
   HIP_OK(hipStreamSynchronize(h->stream));
-  HIP_OK(hipMemcpy(hl.data(), h->L, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (!hl.empty())
+    HIP_OK(hipMemcpy(hl.data(), h->L, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
   int64_t S = (int64_t)s.sn_ptr.size() - 1, q = 0;
   colptr[0] = 0;
   for (int64_t J = 0; J < S; ++J) {
@@ -1327,8 +1335,9 @@ rlb_status rlb_batch_status(rlb_batch b, int64_t* info) {
 
 rlb_status rlb_batch_solve(rlb_batch b, int32_t i, int64_t nrhs, double* B, int64_t ldb,
                            void* stream) {
-  if (!b || i < 0 || i >= (int32_t)b->syms.size() || nrhs < 0 || (nrhs && !B))
+  if (!b || i < 0 || i >= (int32_t)b->syms.size() || nrhs < 0)
     return fail(RLB_ERR_ARG, "bad argument");
+  if (nrhs > 0 && b->syms[i]->s.n > 0 && !B) return fail(RLB_ERR_ARG, "null B");
   if (!b->factored) return fail(RLB_ERR_STATE, "no factorization");
   if (b->h_info.empty()) {  // the statuses of the last factorization, read once
     std::vector<int64_t> info(b->syms.size());

@@ -172,6 +172,46 @@ def test_edge_cases_tiny_diagonal_chain():
     compare_factor(num.export(), f, A.n)
 
 
+def test_empty_matrix_through_every_call():
+    """Order 0: factor, status, export, both solves, backward error and
+    refinement accept the empty buffers (null device pointers), and a batch
+    with an empty member between two others gives those two the bits of
+    their own single factorizations."""
+    torch = _torch()
+    E = W.from_dense_lower(np.zeros((0, 0)))
+    s, num, vals, info = gpu_factor(E)
+    assert info == 0
+    cp, ri, vx = num.export()
+    assert cp.tolist() == [0] and ri.size == 0 and vx.size == 0
+    X = torch.zeros(0, dtype=torch.float64, device="cuda")
+    num.solve(X)
+    num.solve_noalloc(X)
+    assert num.backward_error(X, X).tolist() == [0.0]
+    rep = num.refine(X, X.clone())
+    assert rep["converged"] and rep["iterations"] == 0
+    mats = [W.batch_member(0), E, W.batch_member(1)]
+    syms = [rlb.Symbolic.from_matrix(A) for A in mats]
+    b = rlb.Batch(syms)
+    bv = [torch.from_numpy(A.values).cuda() for A in mats]
+    assert np.all(b.factor(bv) == 0)
+    ws_b = b.workspace.cpu().numpy()
+    elems = [sy.info()["factor_bytes"] // 8 for sy in syms]
+    assert elems[1] == 0
+    base = np.concatenate([[0], np.cumsum(elems)])
+    for i in (0, 2):
+        single = rlb.Numeric(syms[i])
+        assert single.factor(bv[i]) == 0
+        assert np.array_equal(ws_b[base[i]:base[i] + elems[i]],
+                              single.workspace[:elems[i]].cpu().numpy()), i
+    b.solve(1, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    B = torch.from_numpy(mats[2].rhs[:, 0].copy()).cuda()
+    Xb = B.clone()
+    b.solve(2, Xb)
+    single = rlb.Numeric(syms[2])
+    single.factor(bv[2])
+    assert single.backward_error(B, Xb)[0] <= 1e-14
+
+
 def test_not_positive_definite_reports_oracle_column():
     A = W.small_grid("7pt", (10, 10, 10), seed=28)
     # make it indefinite: a large negative shift on a set of late diagonals

@@ -116,6 +116,17 @@ typedef struct rlb_options {
                                model) the update-matrix route must save in a step to be
                                taken there; 0 (default): 30, about the step's two extra
                                launches; < 0: any saving */
+  int32_t split_chunks;     /* deterministic form: an update launch lasts at least as long
+                               as its heaviest target tile, which one workgroup sums. 0
+                               (default): tiles of more 16-deep K chunks than the launch's
+                               balanced share (its chunks over min(tiles, 1024 resident
+                               workgroups)) are cut along their contribution list into
+                               parts of about half that share; each part writes its sum
+                               into a 64x64 block of the workspace (factor_bytes counts
+                               them) and a reduce launch adds the parts into the tile in
+                               part order, so repeated factorizations stay bitwise equal;
+                               > 0: every tile of more chunks than this, in parts of this
+                               many; < 0: never */
 } rlb_options;
 
 #define RLB_TILE_ORDER_WEIGHT 0
@@ -141,7 +152,8 @@ typedef struct rlb_info {
   int64_t n_panel_tiles;  /* workgroups of all panel launches */
   int64_t n_update_tiles; /* target tiles of all update launches */
   int64_t n_merged_tiles; /* target tiles that sum contributions of several supernodes */
-  int64_t n_split_tiles;  /* update workgroups of tiles cut for load balance (atomic adds) */
+  int64_t n_split_tiles;  /* update workgroups of tiles cut for load balance (atomic adds,
+                             or deterministic parts summed by a reduce launch) */
   int64_t n_launches;
   double flops_tiles;    /* flops the update kernels execute (16x16 MFMA blocks touched) */
   double flops_upd_alg;  /* algorithmic flops of the updates: 2 * inner dimension *

@@ -73,6 +73,7 @@ struct DevPlan {
   int64_t* a_src = nullptr;
   AsmCol* asmcols = nullptr;    // RL assembly
   int32_t* asm_rows = nullptr;
+  PartReduce* reduces = nullptr;  // the parts of split target tiles
   // chained solve launches: signals each step counter waits for, and the
   // counters (step counters, one ticket counter per chained launch, the
   // timeout word), cleared at the start of every solve
@@ -98,6 +99,7 @@ struct DevPlan {
     dfree(a_src);
     dfree(asmcols);
     dfree(asm_rows);
+    dfree(reduces);
     dfree(sneed);
     dfree(chain);
   }
@@ -308,6 +310,8 @@ struct rlb_batch_s {
   std::vector<PanelTile> panels;
   std::vector<UpdTile> updates;
   std::vector<UpdSeg> segs;
+  std::vector<PartReduce> reduces;  // the parts of split target tiles
+  PartReduce* d_reduces = nullptr;
   std::vector<DiagTile> dtiles;  // by width class, as in a plan
   int64_t dt_ptr[4] = {0, 0, 0, 0};
   DiagTile* d_dtiles = nullptr;
@@ -343,6 +347,7 @@ struct rlb_batch_s {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     dfree(d_panels);
     dfree(d_updates);
+    dfree(d_reduces);
     dfree(d_segs);
     dfree(d_dtiles);
     dfree(d_ptiles);
@@ -422,6 +427,7 @@ rlb_status rlb_analyze(int64_t n, const int64_t* colptr, const int64_t* rowidx,
     if (opt->tile_order < 0 || opt->tile_order > 1) return fail(RLB_ERR_ARG, "bad tile_order");
     ao.tile_order = opt->tile_order;
     ao.tall_tile_min = opt->tall_tile_min;
+    ao.split_chunks = opt->split_chunks;
     if (!(opt->hybrid_step_us == opt->hybrid_step_us)) return fail(RLB_ERR_ARG, "bad hybrid_step_us");
     ao.hybrid_step_us = opt->hybrid_step_us == 0 ? 30.0 : std::max(0.0, opt->hybrid_step_us);
   } else {
@@ -537,6 +543,11 @@ rlb_status rlb_symbolic_array(rlb_symbolic sym, const char* which, int64_t* out,
       int64_t v[9] = {g.x, g.y, g.lds, g.k, g.ra, g.rb, g.ca, g.cb, g.src};
       tmp.insert(tmp.end(), v, v + 9);
     }
+  } else if (w == "part_reduces") {  // c, pbase, ldc, m, n, flags, nparts per split tile
+    for (const PartReduce& r : s.plan.reduces) {
+      int64_t v[7] = {r.c, r.pbase, r.ldc, r.m, r.n, r.flags, r.nparts};
+      tmp.insert(tmp.end(), v, v + 7);
+    }
   } else if (w == "panel_tiles") {  // diag, ld, nb, nrows, row0, col, slot, grp, gcnt, rw, nrt
     for (const PanelTile& t : s.plan.panels) {
       int64_t v[11] = {t.diag, t.ld, t.nb, t.nrows, t.row0, t.col, t.slot, t.grp, t.gcnt, t.rw,
@@ -591,6 +602,7 @@ rlb_status rlb_numeric_create(rlb_symbolic sym, int32_t precision, rlb_numeric* 
   if ((st = upload(&h->d.amap, s.plan.amap))) return st;
   if ((st = upload(&h->d.asmcols, s.plan.asmcols))) return st;
   if ((st = upload(&h->d.asm_rows, s.plan.asm_rows))) return st;
+  if ((st = upload(&h->d.reduces, s.plan.reduces))) return st;
   if ((st = upload_solve(s, 0, h->d))) return st;
   HIP_OK(hipMalloc((void**)&h->status, sizeof(int)));
   h->ncounters = std::max<int32_t>(1, s.plan.max_groups);
@@ -630,6 +642,8 @@ static void enqueue_factor(rlb_numeric_s* h, const double* values, double* L, hi
     hipStream_t ls = st;
     if (l.kind == LAUNCH_ASSEMBLE) {
       launch_assemble(h->d.asmcols + l.start, l.count, h->d.asm_rows, L, ls);
+    } else if (l.kind == LAUNCH_REDUCE) {
+      launch_part_reduce(h->d.reduces + l.start, l.count, L, ls);
     } else if (l.kind == LAUNCH_UPDATE) {
       if ((l.variant == UPD_BIG && h->precision >= RLB_PREC_BF16_UPDATES) ||
           (l.variant == UPD_TALL && h->precision != RLB_PREC_FP64))
@@ -1056,6 +1070,7 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
   b->launches.clear();
   b->panels.clear();
   b->updates.clear();
+  b->reduces.clear();
   b->ncounters = 0;
   // merge: for each (level, step, kind) the tiles of every matrix, in matrix order
   std::vector<size_t> cur(count, 0);
@@ -1087,7 +1102,9 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
     Launch m{bk, bl, bs, bv, 0, 0, bp, 0, 0, 0, 0};
     int32_t gbase = 0;  // group counters are numbered across the merged matrices
     std::vector<UpdTile> narrow;  // update launch: the narrow tiles, placed last
-    m.start = bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size();
+    m.start = bk == LAUNCH_REDUCE   ? (int64_t)b->reduces.size()
+              : bk != LAUNCH_UPDATE ? (int64_t)b->panels.size()
+                                    : (int64_t)b->updates.size();
     m.ustart = (int64_t)b->updates.size();
     for (int32_t i = 0; i < count; ++i) {
       const Plan& p = syms[i]->s.plan;
@@ -1097,7 +1114,14 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
           (keep_fused ? l.variant : merge_class(l)) != bv)
         continue;
       if (bk == LAUNCH_PANEL && l.pre != bp) continue;
-      if (bk != LAUNCH_UPDATE) {
+      if (bk == LAUNCH_REDUCE) {
+        for (int64_t t = 0; t < l.count; ++t) {
+          PartReduce r = p.reduces[l.start + t];
+          r.c += b->base[i];
+          r.pbase += b->base[i];
+          b->reduces.push_back(r);
+        }
+      } else if (bk != LAUNCH_UPDATE) {
         int32_t g_hi = 0;
         for (int64_t t = 0; t < l.count; ++t) {
           PanelTile pt = p.panels[l.start + t];
@@ -1137,17 +1161,21 @@ static rlb_status batch_schedule(rlb_batch_s* b, int32_t schedule) {
       b->updates.insert(b->updates.end(), narrow.begin(), narrow.end());
       m.nwave = (int32_t)narrow.size();
     }
-    m.count = (bk != LAUNCH_UPDATE ? (int64_t)b->panels.size() : (int64_t)b->updates.size()) -
+    m.count = (bk == LAUNCH_REDUCE   ? (int64_t)b->reduces.size()
+               : bk != LAUNCH_UPDATE ? (int64_t)b->panels.size()
+                                     : (int64_t)b->updates.size()) -
               m.start;
     b->launches.push_back(m);
     b->ncounters = std::max(b->ncounters, (int)gbase);
   }
   dfree(b->d_panels);
   dfree(b->d_updates);
+  dfree(b->d_reduces);
   dfree(b->counters);
   rlb_status st;
   if ((st = upload(&b->d_panels, b->panels))) return st;
   if ((st = upload(&b->d_updates, b->updates))) return st;
+  if ((st = upload(&b->d_reduces, b->reduces))) return st;
   b->ncounters = std::max(1, b->ncounters);
   HIP_OK(hipMalloc((void**)&b->counters, sizeof(int) * b->ncounters));
   HIP_OK(hipMemset(b->counters, 0, sizeof(int) * b->ncounters));
@@ -1179,7 +1207,8 @@ rlb_status rlb_batch_create(int32_t count, const rlb_symbolic* syms, int32_t pre
     if (syms[i]->s.opt.method != 0)
       return fail(RLB_ERR_UNSUPPORTED, "the batched form runs RLB plans only");
     b->base[i] = run;
-    run += syms[i]->s.plan.l_elems;
+    // the matrix's factor storage and the part blocks of its split tiles
+    run += syms[i]->s.plan.ws_elems;
     b->nnz_ptr[i + 1] = b->nnz_ptr[i] + syms[i]->s.nnz_a;
     maxlev = std::max(maxlev, syms[i]->s.plan.nlevels);
   }
@@ -1244,6 +1273,8 @@ static void enqueue_batch(rlb_batch_s* b, double* L, hipStream_t st) {
     if (l.kind == LAUNCH_UPDATE)
       launch_update(b->d_updates + l.start, b->d_segs, l.count, L, b->precision, nullptr,
                     l.variant, st, l.nwave, nullptr, b->narrow_min);
+    else if (l.kind == LAUNCH_REDUCE)
+      launch_part_reduce(b->d_reduces + l.start, l.count, L, st);
     else {
       // the batch factors with the FP64 panel kernel; its fused update tiles
       // run inside it in the FP64 form and as a short launch of their own in

@@ -60,6 +60,7 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
 void launch_tile_inverse(const DiagTile* tiles, int64_t count, int nbb, double* L,
                          hipStream_t st);
 // RL: update-matrix columns added into their ancestors (atomic adds)
+void launch_part_reduce(const PartReduce* recs, int64_t count, double* L, hipStream_t st);
 void launch_assemble(const AsmCol* cols, int64_t count, const int32_t* rows, double* L,
                      hipStream_t st);
 // the off-diagonal inverse blocks of the two-chunk solve steps (after

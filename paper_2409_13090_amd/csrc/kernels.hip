@@ -2084,6 +2084,24 @@ __global__ __launch_bounds__(256) void k_assemble(const AsmCol* __restrict__ col
   }
 }
 
+// The parts of split target tiles added into them, one workgroup per tile:
+// part p holds -(its sum) in the 64x64 block at pbase + 4096 p (column major,
+// ld 64), and every entry of the tile receives the parts' values summed in
+// part order, so the result does not depend on which part finished first.
+__global__ __launch_bounds__(256) void k_part_reduce(const PartReduce* __restrict__ recs,
+                                                     double* __restrict__ L) {
+  const PartReduce r = recs[blockIdx.x];
+  const bool diag = r.flags & 1;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int row = e & 63, col = e >> 6;
+    if (row >= r.m || col >= r.n || (diag && row < col)) continue;
+    const double* q = L + r.pbase + e;
+    double sum = q[0];
+    for (int pi = 1; pi < r.nparts; ++pi) sum += q[(int64_t)pi * 4096];
+    L[r.c + (int64_t)col * r.ldc + row] += sum;
+  }
+}
+
 // The trailing updates of a step as a launch of their own.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_short(const UpdTile* __restrict__ tiles,
@@ -2337,10 +2355,11 @@ __global__ __launch_bounds__(256) void k_update16(const UpdTile* __restrict__ ti
   const int64_t ldc = t.ldc;
   const bool diag = t.flags & 1;
   const bool atomic = t.flags & 2;
+  const bool assign = t.flags & 4;  // write -(sum) without reading the target
   // elements met by a contribution (the FP32 accumulator layout)
-  const unsigned cover = cover_bits<Mfma<float>>(t, segs, wr, wc, lane);
+  const unsigned cover = assign ? 0xffffu : cover_bits<Mfma<float>>(t, segs, wr, wc, lane);
   double cv[2][2][4] = {};
-  if (!atomic) {
+  if (!atomic && !assign) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
@@ -3185,6 +3204,10 @@ void launch_update(const UpdTile* tiles, const UpdSeg* segs, int64_t count, doub
   else
     hipLaunchKernelGGL(k_update<double>, g, b, 0, st, tiles, segs, L, (const double*)L,
                        (int)count, xcd);
+}
+void launch_part_reduce(const PartReduce* recs, int64_t count, double* L, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)count), dim3(256), 0, st, recs, L);
 }
 void launch_assemble(const AsmCol* cols, int64_t count, const int32_t* rows, double* L,
                      hipStream_t st) {

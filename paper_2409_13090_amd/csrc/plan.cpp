@@ -67,6 +67,24 @@ constexpr int64_t FWD_BIG_LAUNCH = 2048;
 #define BELOW_ROWS 64
 #endif
 constexpr int64_t FUSE_TILES_PER_CU = 4;
+// deterministic load balance of an update launch of its own: a launch lasts
+// at least as long as its heaviest target tile, which one workgroup sums.
+// When that tile has more K chunks than SPLIT_TRIGGER times the launch's
+// balanced share (its chunks over min(tiles, resident workgroups)), every
+// tile of more than SPLIT_SHARE times the share, and of at least
+// SPLIT_MIN_CHUNKS, is cut along its contribution list into parts of about
+// half the share (at least SPLIT_MIN_PART chunks, at most SPLIT_MAX_PARTS
+// parts); each part is a workgroup that writes its sum into a 64x64 block of
+// the workspace, and a reduce launch right after adds the parts into the
+// tile in part order, so the result does not depend on timing. (Launches
+// with a milder tail do not win back the reduce launch.)
+constexpr int64_t RESIDENT_UPDATE_WGS = 4 * DEVICE_CUS;
+constexpr double SPLIT_TRIGGER = 2.0;
+constexpr double SPLIT_SHARE = 1.0;
+constexpr int64_t SPLIT_MIN_CHUNKS = 64;
+constexpr int64_t SPLIT_MIN_PART = 32;
+constexpr int64_t SPLIT_MAX_PARTS = 64;
+constexpr int FLAG_PART = 8;  // planner only: a part's target is relative to the part region
 
 // the update work of one step before it is placed: target tiles with their
 // contributions; `next` marks the trailing tiles of the column block right
@@ -332,7 +350,118 @@ int build_plan(Symbolic& s, std::string& err) {
   // (the tiles not marked next, followed by the next ones, which that
   // launch's panels apply themselves and which stay listed for the unfused
   // form)
-  auto commit = [&](const PendingUpdate& u, int64_t fused_into) {
+  // the deterministic split of a launch's heaviest tiles (SPLIT_SHARE above):
+  // false when no tile is cut; otherwise `out` holds the launch's tiles with
+  // every cut tile replaced by its parts (targets: 64x64 blocks at 4096 *
+  // slot, relative to the part region until the plan is complete) and `reds`
+  // one record per cut tile
+  auto split_heavy = [&](const PendingUpdate& u, PendingUpdate& out,
+                         std::vector<PartReduce>& reds) -> bool {
+    if (!s.opt.deterministic || s.opt.split_chunks < 0) return false;
+    const size_t nt = u.tiles.size();
+    if (nt == 0) return false;
+    std::vector<int64_t> ch(nt, 0);
+    int64_t total = 0;
+    for (size_t i = 0; i < nt; ++i) {
+      for (int32_t e = 0; e < u.tiles[i].nseg; ++e)
+        ch[i] += (u.segs[u.tiles[i].seg0 + e].k + KCH - 1) / KCH;
+      total += ch[i];
+    }
+    int64_t thr, part;
+    if (s.opt.split_chunks > 0) {
+      thr = part = s.opt.split_chunks;
+    } else {
+      const double share =
+          (double)total / (double)std::min<int64_t>((int64_t)nt, RESIDENT_UPDATE_WGS);
+      if ((double)*std::max_element(ch.begin(), ch.end()) <= SPLIT_TRIGGER * share) return false;
+      thr = std::max<int64_t>(SPLIT_MIN_CHUNKS, (int64_t)std::ceil(SPLIT_SHARE * share));
+      part = std::max<int64_t>(SPLIT_MIN_PART, (int64_t)std::ceil(0.5 * share));
+    }
+    auto eligible = [&](size_t i) {
+      const UpdTile& t = u.tiles[i];
+      return ch[i] > thr && t.n > NARROW_COLS && !(t.flags & (FLAG_ATOMIC | FLAG_ASSIGN));
+    };
+    bool any = false;
+    for (size_t i = 0; i < nt && !any; ++i) any = eligible(i);
+    if (!any) return false;
+    out = PendingUpdate();
+    out.valid = true;
+    out.level = u.level;
+    out.step = u.step;
+    int64_t slot = 0;
+    for (size_t i = 0; i < nt; ++i) {
+      const UpdTile& t = u.tiles[i];
+      if (!eligible(i)) {
+        UpdTile c = t;
+        c.seg0 = (int32_t)out.segs.size();
+        out.segs.insert(out.segs.end(), u.segs.begin() + t.seg0,
+                        u.segs.begin() + t.seg0 + t.nseg);
+        out.tiles.push_back(c);
+        out.next.push_back(u.next[i]);
+        out.alg.push_back(u.alg[i]);
+        continue;
+      }
+      const int64_t np = std::min<int64_t>(SPLIT_MAX_PARTS, (ch[i] + part - 1) / part);
+      const int64_t per = (ch[i] + np - 1) / np;  // K chunks of a part
+      const bool diag = (t.flags & FLAG_DIAG) != 0;
+      PartReduce r;
+      r.c = t.c;
+      r.pbase = slot * NB * NB;
+      r.ldc = t.ldc;
+      r.m = t.m;
+      r.n = t.n;
+      r.flags = diag ? 1 : 0;
+      r.nparts = 0;
+      r.pad = 0;
+      std::vector<UpdSeg> piece;
+      int64_t used = 0;
+      double a = 0;
+      auto emit = [&]() {
+        UpdTile pt = t;
+        pt.c = (slot + r.nparts) * NB * NB;
+        pt.ldc = (int32_t)NB;
+        pt.flags = (diag ? FLAG_DIAG : 0) | FLAG_ASSIGN | FLAG_PART;
+        pt.seg0 = (int32_t)out.segs.size();
+        pt.nseg = (int32_t)piece.size();
+        out.segs.insert(out.segs.end(), piece.begin(), piece.end());
+        out.tiles.push_back(pt);
+        out.next.push_back(u.next[i]);
+        out.alg.push_back(a);
+        r.nparts++;
+        piece.clear();
+        used = 0;
+        a = 0;
+      };
+      // consecutive pieces of the contribution list, cut inside a
+      // contribution's k range at a multiple of the K chunk where needed
+      for (int32_t e = 0; e < t.nseg; ++e) {
+        const UpdSeg& g = u.segs[t.seg0 + e];
+        for (int64_t q0 = 0; q0 < g.k;) {
+          const int64_t take = std::min<int64_t>(g.k - q0, (per - used) * KCH);
+          UpdSeg pc = g;
+          pc.x += q0 * g.lds;
+          pc.y += q0 * g.lds;
+          pc.k = (int32_t)take;
+          piece.push_back(pc);
+          a += 2.0 * (double)take * seg_entries(g.ra, g.rb, g.ca, g.cb, diag);
+          used += (take + KCH - 1) / KCH;
+          q0 += take;
+          if (used >= per) emit();
+        }
+      }
+      if (!piece.empty()) emit();
+      slot += r.nparts;
+      p.n_split_tiles += r.nparts;
+      reds.push_back(r);
+    }
+    p.part_elems = std::max(p.part_elems, slot * NB * NB);
+    return true;
+  };
+  auto commit = [&](const PendingUpdate& u_in, int64_t fused_into) {
+    PendingUpdate cut_u;
+    std::vector<PartReduce> reds;
+    const bool cut = fused_into < 0 && split_heavy(u_in, cut_u, reds);
+    const PendingUpdate& u = cut ? cut_u : u_in;
     const int64_t start = (int64_t)p.updates.size();
     int64_t nwave = 0;
     bool shortk = true;
@@ -403,6 +532,12 @@ int build_plan(Symbolic& s, std::string& err) {
                               : tile_variant(p.updates.data() + start, counts[0], p.segs.data());
       Launch lu{LAUNCH_UPDATE, u.level, u.step, var, start, counts[0], 0, (int32_t)nwave, 0, 0, 0};
       p.launches.push_back(lu);
+      if (cut) {
+        const int64_t r0 = (int64_t)p.reduces.size();
+        p.reduces.insert(p.reduces.end(), reds.begin(), reds.end());
+        p.launches.push_back(Launch{LAUNCH_REDUCE, u.level, u.step, 0, r0, (int64_t)reds.size(), 0,
+                                    0, 0, 0, 0});
+      }
     }
   };
   for (int32_t h = 0; h < p.nlevels; ++h) {
@@ -937,7 +1072,15 @@ int build_plan(Symbolic& s, std::string& err) {
     }
     if (pend.valid) commit(pend, -1);
   }
-  p.ws_elems = p.l_elems + p.u_elems;
+  // the part blocks follow the update matrices in the workspace
+  const int64_t part_base = p.l_elems + p.u_elems;
+  for (UpdTile& t : p.updates)
+    if (t.flags & FLAG_PART) {
+      t.c += part_base;
+      t.flags &= ~FLAG_PART;
+    }
+  for (PartReduce& r : p.reduces) r.pbase += part_base;
+  p.ws_elems = part_base + p.part_elems;
   // diagonal tiles of every 64-column step, inverted after the factorization,
   // grouped by width class
   for (int ci = 0; ci < 3; ++ci) {

@@ -31,6 +31,10 @@ struct AnalyzeOptions {
                            // when there are at least this many (<= 0: never)
   int tile_order = 0;      // 0: heaviest tiles first; 1: 8x8 blocks of neighbouring
                            // tiles, a contiguous eighth of the order per XCD
+  int split_chunks = 0;    // deterministic form: target tiles far heavier than a launch's
+                           // balanced share are cut into parts summed in a fixed order
+                           // (0: by the launch's balance; > 0: every tile of more K chunks
+                           // than this, in parts of this many; < 0: never)
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its
@@ -132,6 +136,21 @@ struct SolveLaunch {
 constexpr int32_t LAUNCH_PANEL = 0;
 constexpr int32_t LAUNCH_UPDATE = 1;
 constexpr int32_t LAUNCH_ASSEMBLE = 2;  // RL: update matrices scatter-added into ancestors
+constexpr int32_t LAUNCH_REDUCE = 3;    // the parts of split target tiles summed into them
+
+// A target tile of an update launch cut into nparts parts along its
+// contribution list (load balance in the deterministic form): part p wrote
+// -(its sum) into the 64x64 block at pbase + 4096 p of the workspace (column
+// major, ld 64); the reduce adds the parts, in part order, into the tile
+// (rows < m, columns < n; on the diagonal only row >= col).
+struct PartReduce {
+  int64_t c;      // target tile origin
+  int64_t pbase;  // first part's block
+  int32_t ldc, m, n, flags;  // flags bit0: diagonal tile
+  int32_t nparts;
+  int32_t pad;
+};
+static_assert(sizeof(PartReduce) == 40, "PartReduce layout");
 
 // RL (Algorithm 4): one column of an update matrix U_J, assembled into column
 // `dst` of an ancestor's factor storage: entry i of the column (the U_J
@@ -192,6 +211,10 @@ struct Plan {
   // r_J x r_J column-major each, reused from step to step; they follow the
   // factor storage in the workspace (ws_elems = l_elems + u_elems)
   int64_t u_elems = 0;
+  // the parts of split target tiles (64x64 blocks, reused from launch to
+  // launch) follow the update matrices: ws_elems = l_elems + u_elems + part_elems
+  int64_t part_elems = 0;
+  std::vector<PartReduce> reduces;
   int64_t ws_elems = 0;
   std::vector<AsmCol> asmcols;
   std::vector<int32_t> asm_rows;

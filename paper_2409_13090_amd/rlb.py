@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("panel_spread", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("outer_block", ctypes.c_int32), ("big_tile_min", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("tall_tile_min", ctypes.c_int32), ("hybrid_step_us", ctypes.c_double)]
+                ("tall_tile_min", ctypes.c_int32), ("hybrid_step_us", ctypes.c_double),
+                ("split_chunks", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -171,7 +172,7 @@ class Symbolic:
     def __init__(self, n, colptr, rowidx, ordering="grid", grid=(0, 0, 0, 1), merge_cap=0.125,
                  reorder=True, maximal_blocks=True, user_perm=None, panel_spread=0,
                  deterministic=True, outer_block=0, big_tile_min=0, method="rlb",
-                 tile_order="weight", hybrid_step_us=0.0, tall_tile_min=None):
+                 tile_order="weight", hybrid_step_us=0.0, tall_tile_min=None, split_chunks=0):
         L = lib()
         self._cp = np.ascontiguousarray(colptr, np.int64)
         self._ri = np.ascontiguousarray(rowidx, np.int64)
@@ -193,6 +194,7 @@ class Symbolic:
         o.hybrid_step_us = float(hybrid_step_us)
         if tall_tile_min is not None:
             o.tall_tile_min = int(tall_tile_min)
+        o.split_chunks = int(split_chunks)
         if user_perm is not None:
             self._up = np.ascontiguousarray(user_perm, np.int64)
             o.user_perm = self._up.ctypes.data_as(_c_i64p)

@@ -44,6 +44,13 @@ def compare_factor(gpu_csc, ora, n, ncols=None, tol=FP64_TOL):
     return err
 
 
+def factor_elems(sym):
+    """Elements of the factor storage at the start of the workspace (what
+    follows it -- update matrices, the part blocks of split tiles -- is
+    scratch whose unwritten entries keep whatever the buffer held)."""
+    return int(sym.array("off")[-1])
+
+
 def gpu_factor(A, precision=0, device="cuda", graph=False, **kw):
     import torch
     s = rlb.Symbolic.from_matrix(A, **kw)

@@ -9,7 +9,8 @@ properties of the whole factor."""
 import numpy as np
 import pytest
 
-from parity_util import FP64_TOL, compare_factor, gpu_factor, oracle_factor, probe_residual
+from parity_util import (FP64_TOL, compare_factor, factor_elems, gpu_factor, oracle_factor,
+                         probe_residual)
 from paper_2409_13090_amd import rlb
 from paper_2409_13090_amd import workloads as W
 
@@ -201,8 +202,9 @@ def test_empty_matrix_through_every_call():
     for i in (0, 2):
         single = rlb.Numeric(syms[i])
         assert single.factor(bv[i]) == 0
-        assert np.array_equal(ws_b[base[i]:base[i] + elems[i]],
-                              single.workspace[:elems[i]].cpu().numpy()), i
+        nf = factor_elems(syms[i])
+        assert np.array_equal(ws_b[base[i]:base[i] + nf],
+                              single.workspace[:nf].cpu().numpy()), i
     b.solve(1, torch.zeros(0, dtype=torch.float64, device="cuda"))
     B = torch.from_numpy(mats[2].rhs[:, 0].copy()).cuda()
     Xb = B.clone()
@@ -265,8 +267,9 @@ def test_batched_matches_unbatched_and_oracle():
     for i, A in enumerate(mats):
         num = rlb.Numeric(syms[i])
         num.factor(vals[i])
-        ws_s = num.workspace[:elems[i]].cpu().numpy()
-        part = ws_b[base[i]:base[i] + elems[i]]
+        nf = factor_elems(syms[i])
+        ws_s = num.workspace[:nf].cpu().numpy()
+        part = ws_b[base[i]:base[i] + nf]
         err = np.linalg.norm(part - ws_s) / np.linalg.norm(ws_s)
         assert err <= 1e-12, (i, err)
         # the batch's factor of matrix i, solved through the batch handle
@@ -474,6 +477,73 @@ def test_irregular_graph_ordering_matches_oracle(n, method):
     err = compare_factor(num.export(), f, A.n)
     print(f"[case] irregular n={n} {method} rel_err={err:.3e}", flush=True)
     solve_check(num, A)
+
+
+@pytest.mark.parametrize("name,make,kw", [
+    ("lap3d27_13", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                        shift=1e-4), {"split_chunks": 2}),
+    ("irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"split_chunks": 3, "ordering": "graph"}),
+])
+def test_split_tiles_match_oracle_and_repeat_bitwise(name, make, kw):
+    """Heavy target tiles cut into parts (every part a workgroup writing its
+    sum into a block of the workspace, a reduce launch adding the parts in
+    part order): the factor meets the oracle, repeats bit for bit, eagerly
+    and from the HIP graph, and the FP32 and 16-bit update forms (whose
+    kernels write the parts the same way) refine to 1e-14."""
+    torch = _torch()
+    A = make()
+    o, f = oracle_factor(A, **({"ordering": kw["ordering"]} if "ordering" in kw else {}))
+    s, num, vals, info = gpu_factor(A, **kw)
+    assert info == 0
+    L = s.array("launches").reshape(-1, 12)
+    assert (L[:, 0] == 3).sum() >= 1 and s.info()["n_split_tiles"] > 0
+    err = compare_factor(num.export(), f, A.n)
+    print(f"[case] split {name} reduces={(L[:, 0] == 3).sum()} rel_err={err:.3e}", flush=True)
+    first = num.workspace.clone()
+    num.set_graph_mode(True)
+    for _ in range(3):
+        assert num.factor(vals) == 0
+        assert torch.equal(num.workspace, first)
+    solve_check(num, A)
+    B = torch.from_numpy(np.asfortranarray(A.rhs)).cuda().T.contiguous().T
+    for prec in (rlb.RLB_PREC_FP32_UPDATES, rlb.RLB_PREC_BF16_UPDATES):
+        red = rlb.Numeric(s, prec)
+        assert red.factor(vals) == 0
+        compare_factor(red.export(), f, A.n,
+                       tol=1e-3 if prec == rlb.RLB_PREC_FP32_UPDATES else 0.5)
+        X = torch.zeros_like(B).T.contiguous().T
+        rep = red.refine(B, X, tol=1e-14, max_iter=100)
+        assert rep["converged"] and max(rep["backward_error"]) <= 1e-14, (prec, rep)
+
+
+def test_batch_of_split_plans_is_bitwise_single():
+    """Members whose plans cut heavy tiles into parts: each member's factor
+    storage in the batch workspace equals its own factorization's, bit for
+    bit (the part blocks after it are scratch: only the entries a part writes
+    are ever read)."""
+    torch = _torch()
+    mats = [W.batch_member(i) for i in (3, 5, 9)]
+    syms = [rlb.Symbolic.from_matrix(A, split_chunks=2) for A in mats]
+    assert all(sy.info()["n_split_tiles"] > 0 for sy in syms)
+    b = rlb.Batch(syms)
+    vals = [torch.from_numpy(A.values).cuda() for A in mats]
+    assert np.all(b.factor(vals) == 0)
+    ws_b = b.workspace.cpu().numpy()
+    elems = [sy.info()["factor_bytes"] // 8 for sy in syms]
+    base = np.concatenate([[0], np.cumsum(elems)])
+    for i, A in enumerate(mats):
+        sy = syms[i]
+        lel = factor_elems(sy)
+        assert lel < elems[i]
+        single = rlb.Numeric(sy)
+        assert single.factor(vals[i]) == 0
+        assert np.array_equal(ws_b[base[i]:base[i] + lel],
+                              single.workspace[:lel].cpu().numpy()), i
+    o, f = oracle_factor(mats[0])
+    single = rlb.Numeric(syms[0])
+    single.factor(vals[0])
+    compare_factor(single.export(), f, mats[0].n)
 
 
 def test_xcd_tile_order_matches_oracle():

@@ -100,7 +100,20 @@ def replay_factor(A, expand=False, alt=False, **kw):
         launches = with_alt(launches)
     AC = s.array("asm_cols").reshape(-1, 4)
     AR = s.array("asm_rows")
+    PR = s.array("part_reduces").reshape(-1, 7)
     for kind, lev, step, st, cnt, variant, pre, ust, ucnt, ncnt, ast, acnt in launches:
+        if kind == 3:
+            # the parts of split tiles (64x64 blocks, -(their sums)) added into
+            # their tiles in part order
+            for c, pbase, ldc, m, n, flags, nparts in PR[st:st + cnt]:
+                assert nparts >= 2 and pbase + 4096 * nparts <= size
+                for j in range(n):
+                    lo = j if flags & 1 else 0
+                    acc = Lb[pbase + 64 * j + lo: pbase + 64 * j + m].copy()
+                    for q in range(1, nparts):
+                        acc += Lb[pbase + 4096 * q + 64 * j + lo: pbase + 4096 * q + 64 * j + m]
+                    Lb[c + j * ldc + lo: c + j * ldc + m] += acc
+            continue
         if kind == 2:
             # RL: every update-matrix column added into its ancestor column
             for src, dst, rp, ln in AC[st:st + cnt]:
@@ -314,6 +327,12 @@ CASES = [
     ("lap3d27_14_outer64", lambda: W.small_grid("27pt", (14, 14, 14), seed=25, lo=0.1, hi=1.0,
                                                 shift=1e-4),
      {"outer_block": 64}),
+    # heavy target tiles cut into parts that a reduce launch sums in order
+    ("lap3d27_13_split", lambda: W.small_grid("27pt", (13, 13, 13), seed=24, lo=0.1, hi=1.0,
+                                              shift=1e-4),
+     {"split_chunks": 2}),
+    ("irregular_3000_split", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"split_chunks": 3, "ordering": "graph"}),
 ]
 
 
@@ -328,6 +347,10 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     s2, Lb2 = replay_factor(A, expand=True, **kw)
     assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
     L12 = s.array("launches").reshape(-1, 12)
+    if kw.get("split_chunks", 0) > 0:
+        # heavy tiles were cut: every reduce follows the update launch of its parts
+        red = np.flatnonzero(L12[:, 0] == 3)
+        assert red.size and np.all(L12[red - 1, 0] == 1)
     if kw.get("tall_tile_min") == 1:
         # the long parts went to 128x64 tiles; their 64x64 form (FP32, 16-bit) too
         assert np.any((L12[:, 0] == 1) & (L12[:, 5] == 6))

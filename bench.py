@@ -52,9 +52,9 @@ PEAK_16BIT_TFLOPS = 2516.6  # dense BF16/FP16 MFMA
 # only for the kernel source they were taken on (first 16 hex digits of the
 # SHA-256 of kernels.hip), otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "lap3d27_64": {"kernels_sha256": "5badb170d940dff4", "bytes_per_launch": 1015519661,
+    "lap3d27_64": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 959508818,
                    "summary": "profiles/k_update_lap3d27_64_hbm_traffic.md"},
-    "lap3d7_48": {"kernels_sha256": "5badb170d940dff4", "bytes_per_launch": 179991425,
+    "lap3d7_48": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 179838352,
                   "summary": "profiles/k_update_lap3d7_48_hbm_traffic.md"},
 }
 
@@ -244,7 +244,8 @@ def main():
     # block's update inside the panel launches is not part of them)
     ach = info["flops_upd_launch"] / upd_s / 1e12
     roof = {"kernel": "update launches: k_update / k_update_win / k_update_pack / k_update_short "
-                      "(SYRK/GEMM summed into 64x64 target tiles, MFMA f64 16x16x4)",
+                      "(SYRK/GEMM summed into 64x64 target tiles, MFMA f64 16x16x4), with the "
+                      "k_part_reduce launches that sum the parts of split tiles",
             "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(args.workload, args.side),
@@ -286,10 +287,11 @@ def main():
         "roofline": roof,
     }
 
-    def time_method(method):
-        """FP64 factor of the same matrix with another update method, on the
-        same symbolic phase settings (median of the timed steps)."""
-        sym_m = rlb.Symbolic.from_matrix(A, method=method, **order_kw)
+    def time_method(method, **extra):
+        """FP64 factor of the same matrix with another update method (or
+        another planner option), on the same symbolic phase settings (median
+        of the timed steps)."""
+        sym_m = rlb.Symbolic.from_matrix(A, method=method, **order_kw, **extra)
         info_m = sym_m.info()
         num_m = rlb.Numeric(sym_m, rlb.RLB_PREC_FP64)
         num_m.set_graph_mode(graph)
@@ -309,7 +311,8 @@ def main():
         num_m.solve(X)
         be_m = num_m.backward_error(B, X)
         t_m = statistics.median(ms_m) / 1e3
-        n_asm = int((sym_m.array("launches").reshape(-1, 12)[:, 0] == 2).sum())
+        kinds = sym_m.array("launches").reshape(-1, 12)[:, 0]
+        n_asm = int((kinds == 2).sum())
         return {"factor_ms": round(t_m * 1e3, 3), "gflops": round(F / t_m / 1e9, 2),
                 "rlb_factor_ms": round(t_fac * 1e3, 3),
                 "over_rlb_time": round(t_m / t_fac, 3),
@@ -317,6 +320,8 @@ def main():
                 "update_matrix_bytes": info_m["u_bytes"],
                 "rlb_fp_storage_bytes": info["factor_bytes"],
                 "assembly_launches": n_asm,
+                "reduce_launches": int((kinds == 3).sum()),
+                "split_workgroups": info_m["n_split_tiles"],
                 "backward_error_max": float(f"{max(be_m):.3e}")}
 
     if not args.no_rl:
@@ -331,6 +336,14 @@ def main():
                                    "whose rectangles meet many target tiles (planner's "
                                    "cost model; not the paper's method)",
                          **time_method("hybrid")}
+        # RLB with the launches' heaviest tiles cut into parts summed by a
+        # reduce launch in a fixed order (load balance; adds part blocks of
+        # working storage that Algorithm 5 does without, hence an option)
+        out["split"] = {"method": "RLB with heavy target tiles cut into parts written to "
+                                  "workspace blocks and summed in part order by a reduce "
+                                  "launch (split_chunks < 0; deterministic; not the paper's "
+                                  "method)",
+                        **time_method("rlb", split_chunks=-1)}
     if not args.no_mixed:
         mixed = args.mixed or ("bf16" if args.workload == "elast3_40" else "fp32")
         prec = {"fp32": rlb.RLB_PREC_FP32_UPDATES, "bf16": rlb.RLB_PREC_BF16_UPDATES,

@@ -117,16 +117,19 @@ typedef struct rlb_options {
                                taken there; 0 (default): 30, about the step's two extra
                                launches; < 0: any saving */
   int32_t split_chunks;     /* deterministic form: an update launch lasts at least as long
-                               as its heaviest target tile, which one workgroup sums. 0
-                               (default): tiles of more 16-deep K chunks than the launch's
-                               balanced share (its chunks over min(tiles, 1024 resident
-                               workgroups)) are cut along their contribution list into
-                               parts of about half that share; each part writes its sum
-                               into a 64x64 block of the workspace (factor_bytes counts
-                               them) and a reduce launch adds the parts into the tile in
-                               part order, so repeated factorizations stay bitwise equal;
-                               > 0: every tile of more chunks than this, in parts of this
-                               many; < 0: never */
+                               as its heaviest target tile, which one workgroup sums.
+                               0 (default): no tile is cut; every update is written
+                               straight into its target (Alg. 5: no floating-point
+                               working storage). < 0: in a launch whose heaviest tile
+                               holds more than twice its balanced share of 16-deep K
+                               chunks (its chunks over min(tiles, 1024 resident
+                               workgroups)), the tiles above that share are cut along
+                               their contribution list into parts of about half the
+                               share; each part writes its sum into a 64x64 block of the
+                               workspace (factor_bytes counts them) and a reduce launch
+                               adds the parts into the tile in part order, so repeated
+                               factorizations stay bitwise equal. > 0: every tile of more
+                               chunks than this, in parts of this many */
 } rlb_options;
 
 #define RLB_TILE_ORDER_WEIGHT 0

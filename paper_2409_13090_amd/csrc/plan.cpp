@@ -67,9 +67,11 @@ constexpr int64_t FWD_BIG_LAUNCH = 2048;
 #define BELOW_ROWS 64
 #endif
 constexpr int64_t FUSE_TILES_PER_CU = 4;
-// deterministic load balance of an update launch of its own: a launch lasts
-// at least as long as its heaviest target tile, which one workgroup sums.
-// When that tile has more K chunks than SPLIT_TRIGGER times the launch's
+// deterministic load balance of an update launch of its own (an option,
+// split_chunks < 0; off by default, since it adds working storage that
+// Algorithm 5 does without): a launch lasts at least as long as its heaviest
+// target tile, which one workgroup sums. When that tile has more K chunks
+// than SPLIT_TRIGGER times the launch's
 // balanced share (its chunks over min(tiles, resident workgroups)), every
 // tile of more than SPLIT_SHARE times the share, and of at least
 // SPLIT_MIN_CHUNKS, is cut along its contribution list into parts of about
@@ -357,7 +359,7 @@ int build_plan(Symbolic& s, std::string& err) {
   // one record per cut tile
   auto split_heavy = [&](const PendingUpdate& u, PendingUpdate& out,
                          std::vector<PartReduce>& reds) -> bool {
-    if (!s.opt.deterministic || s.opt.split_chunks < 0) return false;
+    if (!s.opt.deterministic || s.opt.split_chunks == 0) return false;
     const size_t nt = u.tiles.size();
     if (nt == 0) return false;
     std::vector<int64_t> ch(nt, 0);

@@ -31,10 +31,12 @@ struct AnalyzeOptions {
                            // when there are at least this many (<= 0: never)
   int tile_order = 0;      // 0: heaviest tiles first; 1: 8x8 blocks of neighbouring
                            // tiles, a contiguous eighth of the order per XCD
-  int split_chunks = 0;    // deterministic form: target tiles far heavier than a launch's
-                           // balanced share are cut into parts summed in a fixed order
-                           // (0: by the launch's balance; > 0: every tile of more K chunks
-                           // than this, in parts of this many; < 0: never)
+  int split_chunks = 0;    // deterministic form: target tiles cut into parts that write
+                           // into workspace blocks, summed in a fixed order by a reduce
+                           // launch (0: never -- every update written straight into its
+                           // target, as Algorithm 5; < 0: the tiles far heavier than their
+                           // launch's balanced share; > 0: every tile of more K chunks than
+                           // this, in parts of this many)
 };
 
 // One 64x64 (or smaller) target tile of factor storage and the list of its

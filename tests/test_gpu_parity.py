@@ -484,6 +484,8 @@ def test_irregular_graph_ordering_matches_oracle(n, method):
                                         shift=1e-4), {"split_chunks": 2}),
     ("irregular_3000", lambda: W.irregular3d(3000, k=10, seed=40),
      {"split_chunks": 3, "ordering": "graph"}),
+    ("irregular_3000_auto", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"split_chunks": -1, "ordering": "graph"}),
 ])
 def test_split_tiles_match_oracle_and_repeat_bitwise(name, make, kw):
     """Heavy target tiles cut into parts (every part a workgroup writing its

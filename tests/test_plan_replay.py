@@ -333,6 +333,9 @@ CASES = [
      {"split_chunks": 2}),
     ("irregular_3000_split", lambda: W.irregular3d(3000, k=10, seed=40),
      {"split_chunks": 3, "ordering": "graph"}),
+    # the automatic rule: tiles above the balanced share of launches with a long tail
+    ("irregular_3000_split_auto", lambda: W.irregular3d(3000, k=10, seed=40),
+     {"split_chunks": -1, "ordering": "graph"}),
 ]
 
 
@@ -347,7 +350,7 @@ def test_work_lists_replayed_match_oracle(name, make, kw):
     s2, Lb2 = replay_factor(A, expand=True, **kw)
     assert compare_factor(export(s2, Lb2), f, A.n) <= 1e-12
     L12 = s.array("launches").reshape(-1, 12)
-    if kw.get("split_chunks", 0) > 0:
+    if kw.get("split_chunks", 0) != 0:
         # heavy tiles were cut: every reduce follows the update launch of its parts
         red = np.flatnonzero(L12[:, 0] == 3)
         assert red.size and np.all(L12[red - 1, 0] == 1)
@@ -421,3 +424,42 @@ def test_update_variant_follows_chunk_rounds(name, make, kw):
         seen.add(var)
     if name != "irregular_3000":
         assert 5 in seen, seen
+
+
+def test_split_rule_cuts_only_long_tails():
+    """The automatic cut (split_chunks < 0): in every update launch it cuts,
+    the heaviest original tile held more than twice the launch's balanced
+    share of K chunks; the parts of a cut tile are assign tiles into
+    consecutive 64x64 workspace blocks past the factor storage, each part at
+    most about half a share, and together they carry the tile's K chunks.
+    Off by default (Algorithm 5 writes every update in place)."""
+    A = W.irregular3d(3000, k=10, seed=40)
+    assert rlb.Symbolic.from_matrix(A, ordering="graph").info()["n_split_tiles"] == 0
+    s = rlb.Symbolic.from_matrix(A, ordering="graph", split_chunks=-1)
+    L = s.array("launches").reshape(-1, 12)
+    U = s.array("update_tiles").reshape(-1, 7)
+    G = s.array("update_segs").reshape(-1, 9)
+    PR = s.array("part_reduces").reshape(-1, 7)
+    lel = int(s.array("off")[-1])
+    red = np.flatnonzero(L[:, 0] == 3)
+    assert red.size >= 1
+    for j in red:
+        up = L[j - 1]
+        assert up[0] == 1 and up[1] == L[j, 1] and up[2] == L[j, 2]
+        tiles = U[up[3]:up[3] + up[4]]
+        chunks = np.array([int(((G[t[5]:t[5] + t[6], 3] + 15) // 16).sum()) for t in tiles])
+        recs = PR[L[j, 3]:L[j, 3] + L[j, 4]]
+        is_part = (tiles[:, 4] & 4) != 0
+        assert is_part.sum() == recs[:, 6].sum()
+        # the launch's tiles before the cut: parts regrouped into their tiles
+        whole = list(chunks[~is_part])
+        by_block = {int(t[0]): c for t, c in zip(tiles[is_part], chunks[is_part])}
+        for c, pbase, ldc, m, n, flags, nparts in recs:
+            assert pbase >= lel and nparts >= 2
+            parts = [by_block[int(pbase) + 4096 * q] for q in range(nparts)]
+            whole.append(sum(parts))
+            assert max(parts) <= min(parts) + 1 + max(parts) // 2  # nearly even parts
+        share = sum(whole) / min(len(whole), 1024)
+        assert max(whole) > 2 * share
+        for (c, pbase, ldc, m, n, flags, nparts) in recs:
+            assert sum(by_block[int(pbase) + 4096 * q] for q in range(nparts)) > share

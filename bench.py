@@ -52,9 +52,9 @@ PEAK_16BIT_TFLOPS = 2516.6  # dense BF16/FP16 MFMA
 # only for the kernel source they were taken on (first 16 hex digits of the
 # SHA-256 of kernels.hip), otherwise the roofline reports traffic as null.
 MEASURED_TRAFFIC = {
-    "lap3d27_64": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 959508818,
+    "lap3d27_64": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 1015278042,
                    "summary": "profiles/k_update_lap3d27_64_hbm_traffic.md"},
-    "lap3d7_48": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 179838352,
+    "lap3d7_48": {"kernels_sha256": "8061a75a28f12f09", "bytes_per_launch": 179886029,
                   "summary": "profiles/k_update_lap3d7_48_hbm_traffic.md"},
 }
 
